@@ -1,0 +1,168 @@
+"""Benchmark: implicit CP-ALS time steps per second on one MI355X.
+
+Workload: 6-D advection with variable separable coefficients a_i(x) = 1 + 0.5 sin(x_{i+1}),
+implicit Euler (13 Kronecker terms), n = 256 points per dimension, fixed separation rank 32
+(from a rank-8 Gaussian-mixture initial condition), ALS tolerance 1e-8 on the relative
+increment, at most 200 sweeps per step, FP64.  Synthetic seeded inputs.
+
+A step is one implicit time step: the full ALS solve of A f_{n+1} = f_n (all sweeps), run
+device-resident in one persistent kernel launch per batch of steps.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "CP-ALS time-steps/s (d=6,n=256,r=32) at equal residual, learned/batched vs plain"
+FP64_PEAK_TFLOPS = 78.6   # MI355X FP64 vector (= FP64 matrix) peak
+HBM_PEAK_GBS = 8000.0
+
+
+def flop_model(p, reports):
+    """Algorithmic FP64 flops of the reported sweeps / PCG iterations (per launch).
+
+    Per dimension update q (n = n_q, m = distinct ops of A in dim q, mb of B, r, r0):
+      Gram refresh      2 n (m r)^2 + 2 n (m r)(mb r0)
+      Hadamard assembly (T_A^2 (d-1) r^2 + T_A T_B (d-1) r r0) * 2
+      right-hand side   2 n (mb r0)(m r)
+      matvec (M+lam)x   2 n (m r)^2                    (the stencil parts are O(n r m) and omitted)
+      preconditioner    2 n r^2
+      increment         2 n r^2
+    and one matvec for the initial residual, per update; per PCG iteration a matvec and a
+    preconditioner application."""
+    A, B = p.A, p.B
+    d = A.d
+    r = p.rank_cap
+    dims = A.dims()
+    T_A, T_B = A.n_terms, B.n_terms
+    per_sweep = 0.0
+    for q in range(d):
+        n = dims[q]
+        m = len(A.ops[q])
+        mb = len(B.ops[q])
+        r0 = r
+        per_sweep += 2 * n * (m * r) ** 2 + 2 * n * (m * r) * (mb * r0)
+        per_sweep += 2 * (T_A * T_A * (d - 1) * r * r + T_A * T_B * (d - 1) * r * r0)
+        per_sweep += 2 * n * (mb * r0) * (m * r)
+        per_sweep += 2 * n * (m * r) ** 2 + 2 * n * r * r      # initial residual + increment
+    n_avg = float(np.mean(dims))
+    m_avg = float(np.mean([len(o) for o in A.ops]))
+    per_pcg = 2 * n_avg * (m_avg * r) ** 2 + 2 * n_avg * r * r
+    sweeps = sum(rp["sweeps"] for rp in reports)
+    iters = sum(rp["pcg_iters"] for rp in reports)
+    return sweeps * per_sweep + iters * per_pcg
+
+
+def cpu_baseline(p, sweeps_per_step, n_sweeps=4):
+    """The FP64 oracle on the host: the first n_sweeps sweeps of the first step, scaled to
+    time-steps/s with the GPU run's mean sweeps per step."""
+    from oracle import cpals_oracle as O
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([t.get("num_threads", 1) for t in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count() or 1
+    t0 = time.perf_counter()
+    O.als_step(p.A, p.B, p.f0, p.guess, tol=0.0, max_sweeps=n_sweeps)
+    dt = time.perf_counter() - t0
+    per_sweep = dt / n_sweeps
+    return {"value": 1.0 / (per_sweep * sweeps_per_step), "unit": "time-steps/s", "cores": int(cores),
+            "kind": "oracle",
+            "sample": "first %d ALS sweeps of step 1 (%.1f s, %.2f s/sweep) scaled by %.1f sweeps/step; "
+                      "dense BLAS threads=%d, sparse direct solve single-threaded" % (
+                          n_sweeps, dt, per_sweep, sweeps_per_step, cores)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--max-sweeps", type=int, default=200)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build runs on one GPU only (the multi-GPU sharding is a design, not code); "
+              "use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1803_10270_amd import binding as B
+    from paper_1803_10270_amd import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    p = W.advection_ie_variable(seed=args.seed)
+    h = B.Handle()
+    opts = B.default_opts(tol=p.tol, max_sweeps=args.max_sweeps)
+    V = B.to_device(p.f0)
+    U = B.to_device(p.guess)
+    # warmup: the first W steps (untimed); they also leave f_W as the state to continue from
+    t_w = time.perf_counter()
+    if args.warmup > 0:
+        B.cp_als_run(h, p.A, p.B, V, U, args.warmup, opts)
+    torch.cuda.synchronize()
+    t_w = time.perf_counter() - t_w
+    print("warmup %d steps: %.2f s" % (args.warmup, t_w), file=sys.stderr, flush=True)
+    V2 = [u.clone() for u in U]
+    stream = torch.cuda.current_stream()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    reports = B.cp_als_run(h, p.A, p.B, V2, U, args.steps, opts)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    print("timed %d steps: %.3f s wall, %.3f ms events" % (args.steps, wall, gpu_ms), file=sys.stderr, flush=True)
+    sweeps = [r["sweeps"] for r in reports]
+    flops = flop_model(p, reports)
+    achieved = flops / (gpu_ms * 1e-3) / 1e12
+    value = args.steps / wall
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "time-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "advection_ie_variable d=6 n=256 r=32 (13 Kronecker terms, implicit Euler, "
+                               "dt=1e-3, tol=1e-8, max_sweeps=%d, seed %d)" % (args.max_sweeps, args.seed),
+                   "d": 6, "n": 256, "r": 32, "form": "plain", "precision": "fp64"},
+        "sweeps_per_step": float(np.mean(sweeps)),
+        "pcg_iters_per_update": float(sum(r["pcg_iters"] for r in reports) / max(1, 6 * sum(sweeps))),
+        "converged_steps": int(sum(1 for r in reports if not (r["flags"] & B.FLAG_NOT_CONVERGED))),
+        "eps_conv_last": reports[-1]["eps_conv"],
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
+                     "kernel": "als_persistent", "flops_per_launch": flops, "launch_ms": gpu_ms},
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(p, float(np.mean(sweeps)))
+    print(json.dumps(out), flush=True)
+    h.close()
+
+
+if __name__ == "__main__":
+    main()

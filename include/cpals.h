@@ -1,0 +1,189 @@
+/*
+ * cpals.h -- C ABI of the MI355X (gfx950) implicit CP-ALS library (libcpals.so).
+ *
+ * The library implements the hot path of the canonical-tensor (CP) time stepper of
+ * Boelens, Venturi & Tartakovsky, "Parallel numerical tensor methods for
+ * high-dimensional PDEs":
+ *   - a CP tensor f = sum_l prod_k U_k[:, l]                  (Section 2.1, eq. functional-SSE)
+ *   - separable operators A = sum_e eta_e kron_k E_k^e        (Section 3, eqs. Lz and BLs)
+ *   - the implicit step A f_{n+1} = B f_n solved by alternating least squares over the
+ *     dimensions, one convex problem per dimension               (Section 3.1, eqs. ALS2, ML, MR)
+ *   - rank reduction by the same ALS with A = B = I           (Section 2.1, Section 3.2)
+ *   - scalar products and operator application on CP tensors  (Sections 2.2 and 3.2)
+ *
+ * Memory and ownership
+ *   - Every factor panel (cp_tensor.U[k]) is DEVICE memory owned by the caller; the
+ *     library never frees or keeps it past the call.  Panels are column-major n_k x r with
+ *     leading dimension ld[k] >= n[k] (element (i, l) at U[k][i + l * ld[k]]).
+ *   - Operator descriptions (cp_operator, cp_op1d and everything they point to) are HOST
+ *     memory; the library copies them to the device during the call.
+ *   - Scalar outputs named *_dev are DEVICE pointers; report structs are HOST memory.
+ *   - The library owns an internal device workspace per handle (grown on demand, freed by
+ *     cp_destroy).
+ *
+ * Execution: calls are enqueued on the handle's HIP stream.  Calls that return a report
+ * synchronise that stream once before returning.  One handle per host thread.
+ *
+ * Errors never cross the ABI as exceptions: every call returns a cp_status, and
+ * cp_last_error() gives a message for the last failing call on the handle.  Shape and
+ * argument checks happen before anything is launched.
+ */
+#ifndef CPALS_H
+#define CPALS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CP_MAX_DIMS 8
+#define CP_MAX_OPS 4
+#define CP_MAX_TERMS 64
+#define CP_MAX_RANK 64
+#define CP_MAX_N 4096
+
+typedef enum {
+    CP_OK = 0,
+    CP_ERR_INVALID_ARG = 1,  /* null pointer, bad enum, bad option value          */
+    CP_ERR_SHAPE = 2,        /* dimensions, ranks or sizes inconsistent / too big */
+    CP_ERR_UNSUPPORTED = 3,  /* valid request that this build does not implement  */
+    CP_ERR_HIP = 4,          /* HIP runtime error (allocation, launch, copy)      */
+    CP_ERR_NOT_CONVERGED = 5 /* soft: results written, report.flags says why      */
+} cp_status;
+
+/* report.flags bits */
+#define CP_FLAG_NOT_CONVERGED 1u  /* max_sweeps reached with eps_conv > tol            */
+#define CP_FLAG_PCG_MAXITER 2u    /* a per-dimension solve hit pcg_max_iter            */
+#define CP_FLAG_REGULARIZED 4u    /* a Cholesky pivot of H_q fell below 1e-12 max diag */
+#define CP_FLAG_NONFINITE 8u      /* a NaN/Inf was produced                            */
+
+typedef struct cp_handle_s* cp_handle;
+
+/* Create a handle bound to the current HIP device and to `hip_stream` (a hipStream_t;
+ * NULL = the null stream). */
+cp_status cp_create(cp_handle* handle, void* hip_stream);
+cp_status cp_destroy(cp_handle handle);
+cp_status cp_set_stream(cp_handle handle, void* hip_stream);
+const char* cp_last_error(cp_handle handle);
+/* Library version string (static storage). */
+const char* cp_version(void);
+
+/* A CP tensor of dimension d and separation rank r (Section 2.1).  U[k] are device
+ * pointers to column-major n[k] x r panels with leading dimension ld[k]. */
+typedef struct {
+    int32_t d;
+    int32_t r;
+    int32_t n[CP_MAX_DIMS];
+    int32_t ld[CP_MAX_DIMS];
+    double* U[CP_MAX_DIMS];
+} cp_tensor;
+
+/* A one-dimensional linear operator on a periodic grid of n points (HOST data):
+ *   CP_OP_IDENTITY : data unused
+ *   CP_OP_DIAG     : data[n], O = diag(data)
+ *   CP_OP_BAND     : data[(2*half_bw+1) * n], O[i, (i + j - half_bw) mod n] += data[j*n + i]
+ *                    (periodic band, e.g. the central difference with half_bw = 1)
+ *   CP_OP_RANK1    : data[2*n] = [m ; w], O = m w^T (e.g. a velocity-moment projector) */
+typedef enum { CP_OP_IDENTITY = 0, CP_OP_DIAG = 1, CP_OP_BAND = 2, CP_OP_RANK1 = 3 } cp_op_kind;
+
+typedef struct {
+    int32_t kind;
+    int32_t n;
+    int32_t half_bw;
+    const double* data;
+} cp_op1d;
+
+/* A separable operator sum_{e < n_terms} coef[e] * kron_k ops[k][op_index[e*d + k]]
+ * (eq. Lz / eq. BLs).  ops[k] lists the DISTINCT 1-D operators of dimension k
+ * (n_ops[k] <= CP_MAX_OPS), which is the paper's map of unique one-dimensional integrals
+ * (Section 3.1, "Summary of the Algorithm").  All HOST memory. */
+typedef struct {
+    int32_t d;
+    int32_t n_terms;
+    const double* coef;
+    const int32_t* op_index;
+    int32_t n_ops[CP_MAX_DIMS];
+    const cp_op1d* ops[CP_MAX_DIMS];
+} cp_operator;
+
+typedef enum { CP_PREC_FP64 = 0, CP_PREC_MIXED = 1 } cp_precision;
+
+/* ALS options.
+ *  tol          : stop when eps_conv = max_q ||Delta f_q|| / ||f|| <= tol after a sweep
+ *                 (increment test of Section 3.1 / Appendix B, on the represented tensor)
+ *  max_sweeps   : cap on Gauss-Seidel sweeps per time step (>= 1)
+ *  eps_reg      : every per-dimension system is shifted by
+ *                 lambda_q = eps_reg * trace(M_q) / (n_q r)  (regularisation, Section 2.1)
+ *  pcg_tol      : relative residual target of the per-dimension PCG solve
+ *  pcg_max_iter : PCG iteration cap per dimension update
+ *  precision    : CP_PREC_FP64, or CP_PREC_MIXED (FP32 contractions, FP64 solves/checks) */
+typedef struct {
+    double tol;
+    int32_t max_sweeps;
+    double eps_reg;
+    double pcg_tol;
+    int32_t pcg_max_iter;
+    int32_t precision;
+} cp_als_opts;
+
+/* Per-step report (HOST memory, filled after the call's single stream synchronisation). */
+typedef struct {
+    int32_t sweeps;      /* sweeps performed                          */
+    int32_t pcg_iters;   /* PCG iterations summed over all updates     */
+    double eps_conv;     /* eps_conv after the last sweep             */
+    double fnorm;        /* ||f_{n+1}||                               */
+    uint32_t flags;      /* CP_FLAG_* bits                            */
+    int32_t reserved;
+} cp_als_report;
+
+/* Fill `opts` with the defaults (tol 1e-8, max_sweeps 200, eps_reg 1e-10, pcg_tol 1e-14,
+ * pcg_max_iter 100, FP64). */
+cp_status cp_als_default_opts(cp_als_opts* opts);
+
+/* <x, y> = sum_{l,l'} prod_k <X_k[:,l], Y_k[:,l']>  (scalar product of CP tensors,
+ * Section 2.2).  out_dev: one double in device memory.  Requires x.d == y.d, equal n. */
+cp_status cp_inner(cp_handle h, const cp_tensor* x, const cp_tensor* y, double* out_dev);
+/* ||x|| = sqrt(max(<x,x>, 0)).  out_dev: one double in device memory. */
+cp_status cp_norm(cp_handle h, const cp_tensor* x, double* out_dev);
+
+/* y = L x as a CP tensor of rank n_terms * x.r (operator application, Section 3.2):
+ * column e*x.r + l of y.U[k] is E_k^e X_k[:, l], with coef[e] multiplied into dimension 0.
+ * y must have y.r == L.n_terms * x.r and the same n; y's panels are overwritten. */
+cp_status cp_apply_operator(cp_handle h, const cp_operator* L, const cp_tensor* x, cp_tensor* y);
+
+/* One implicit time step: minimise ||A f_{n+1} - B f_n|| over rank-r CP tensors
+ * (eqs. rRr1, resnorm) by Gauss-Seidel ALS over q = 1..d (eqs. sequential_min, ALS2).
+ * f_next is in/out: on entry the initial guess (rank r = f_next.r), on exit f_{n+1}.
+ * The columns of the result are balanced (equal factor norms per column).
+ * Returns CP_ERR_NOT_CONVERGED (results still written) if max_sweeps was reached. */
+cp_status cp_als_step(cp_handle h, const cp_operator* A, const cp_operator* B, const cp_tensor* f_n,
+                      cp_tensor* f_next, const cp_als_opts* opts, cp_als_report* report);
+
+/* n_steps implicit steps in one device-resident launch: f_0 = f_init, guess for step s is
+ * f_{s-1} (the first step uses f_io as guess, which must have rank == cap), result f_{n_steps}
+ * written to f_io.  reports: host array of n_steps.  traj (nullable): device buffer of
+ * n_steps * sum_k n_k * r doubles receiving every step's factors, packed dimension after
+ * dimension, column-major. */
+cp_status cp_als_run(cp_handle h, const cp_operator* A, const cp_operator* B, const cp_tensor* f_init,
+                     cp_tensor* f_io, int32_t n_steps, const cp_als_opts* opts, cp_als_report* reports,
+                     double* traj);
+
+/* Rank reduction: minimise ||f - g|| over rank-f.r CP tensors by ALS (Section 2.1).
+ * f is in/out (initial guess in, result out). */
+cp_status cp_truncate(cp_handle h, const cp_tensor* g, cp_tensor* f, const cp_als_opts* opts,
+                      cp_als_report* report);
+
+/* Many independent problems advanced in one persistent launch (one workgroup per problem).
+ * Arrays of length count: A[i], B[i] (host descriptions), f_init[i], f_io[i] as in
+ * cp_als_run; reports: count * n_steps entries, problem-major. */
+cp_status cp_als_run_batched(cp_handle h, int32_t count, const cp_operator* A, const cp_operator* B,
+                             const cp_tensor* f_init, cp_tensor* f_io, int32_t n_steps,
+                             const cp_als_opts* opts, cp_als_report* reports);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CPALS_H */

@@ -1,0 +1,273 @@
+"""ctypes binding of libcpals.so (C ABI in include/cpals.h).
+
+Argument marshalling only: every step of the method runs in the HIP library.  Device
+memory comes from PyTorch tensors; a CP factor panel U_k (n_k x r, column-major) is a
+contiguous float64 CUDA tensor of shape (r, n_k).
+
+If the library has not been built, loading raises: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcpals.so")
+
+CP_MAX_DIMS = 8
+CP_MAX_OPS = 4
+
+CP_OK, CP_ERR_INVALID_ARG, CP_ERR_SHAPE, CP_ERR_UNSUPPORTED, CP_ERR_HIP, CP_ERR_NOT_CONVERGED = range(6)
+FLAG_NOT_CONVERGED, FLAG_PCG_MAXITER, FLAG_REGULARIZED, FLAG_NONFINITE = 1, 2, 4, 8
+PREC_FP64, PREC_MIXED = 0, 1
+OP_KIND = {"identity": 0, "diag": 1, "band": 2, "rank1": 3}
+
+
+class cp_tensor(C.Structure):
+    _fields_ = [("d", C.c_int32), ("r", C.c_int32), ("n", C.c_int32 * CP_MAX_DIMS),
+                ("ld", C.c_int32 * CP_MAX_DIMS), ("U", C.c_void_p * CP_MAX_DIMS)]
+
+
+class cp_op1d(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("n", C.c_int32), ("half_bw", C.c_int32), ("data", C.c_void_p)]
+
+
+class cp_operator(C.Structure):
+    _fields_ = [("d", C.c_int32), ("n_terms", C.c_int32), ("coef", C.c_void_p), ("op_index", C.c_void_p),
+                ("n_ops", C.c_int32 * CP_MAX_DIMS), ("ops", C.c_void_p * CP_MAX_DIMS)]
+
+
+class cp_als_opts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("max_sweeps", C.c_int32), ("eps_reg", C.c_double),
+                ("pcg_tol", C.c_double), ("pcg_max_iter", C.c_int32), ("precision", C.c_int32)]
+
+
+class cp_als_report(C.Structure):
+    _fields_ = [("sweeps", C.c_int32), ("pcg_iters", C.c_int32), ("eps_conv", C.c_double),
+                ("fnorm", C.c_double), ("flags", C.c_uint32), ("reserved", C.c_int32)]
+
+    def as_dict(self):
+        return {"sweeps": self.sweeps, "pcg_iters": self.pcg_iters, "eps_conv": self.eps_conv,
+                "fnorm": self.fnorm, "flags": self.flags}
+
+
+class CpalsError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("cpals status %d: %s" % (status, msg))
+        self.status = status
+
+
+_LIB = None
+
+
+def lib() -> C.CDLL:
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libcpals.so is not built (python -m paper_1803_10270_amd.build)")
+        L = C.CDLL(LIB_PATH)
+        H = C.c_void_p
+        P = C.POINTER
+        sigs = {
+            "cp_create": [P(H), C.c_void_p], "cp_destroy": [H], "cp_set_stream": [H, C.c_void_p],
+            "cp_inner": [H, P(cp_tensor), P(cp_tensor), C.c_void_p],
+            "cp_norm": [H, P(cp_tensor), C.c_void_p],
+            "cp_apply_operator": [H, P(cp_operator), P(cp_tensor), P(cp_tensor)],
+            "cp_als_step": [H, P(cp_operator), P(cp_operator), P(cp_tensor), P(cp_tensor), P(cp_als_opts),
+                            P(cp_als_report)],
+            "cp_als_run": [H, P(cp_operator), P(cp_operator), P(cp_tensor), P(cp_tensor), C.c_int32,
+                           P(cp_als_opts), P(cp_als_report), C.c_void_p],
+            "cp_truncate": [H, P(cp_tensor), P(cp_tensor), P(cp_als_opts), P(cp_als_report)],
+            "cp_als_run_batched": [H, C.c_int32, P(cp_operator), P(cp_operator), P(cp_tensor), P(cp_tensor),
+                                   C.c_int32, P(cp_als_opts), P(cp_als_report)],
+            "cp_als_default_opts": [P(cp_als_opts)],
+        }
+        for name, argt in sigs.items():
+            f = getattr(L, name)
+            f.argtypes = argt
+            f.restype = C.c_int
+        L.cp_last_error.argtypes = [H]
+        L.cp_last_error.restype = C.c_char_p
+        L.cp_version.argtypes = []
+        L.cp_version.restype = C.c_char_p
+        _LIB = L
+    return _LIB
+
+
+# ----------------------------------------------------------------------------------------
+# marshalling helpers
+# ----------------------------------------------------------------------------------------
+
+def to_device(U: Sequence[np.ndarray], device="cuda"):
+    """numpy factor panels (n_k, r) -> list of contiguous float64 (r, n_k) CUDA tensors."""
+    import torch
+    return [torch.from_numpy(np.ascontiguousarray(np.asarray(u, dtype=np.float64).T)).to(device) for u in U]
+
+
+def to_host(T) -> List[np.ndarray]:
+    return [t.detach().cpu().numpy().T.copy() for t in T]
+
+
+def tensor_desc(T) -> cp_tensor:
+    """List of (r, n_k) float64 CUDA tensors -> cp_tensor (column-major n_k x r panels)."""
+    import torch
+    desc = cp_tensor()
+    desc.d = len(T)
+    desc.r = int(T[0].shape[0])
+    for k, t in enumerate(T):
+        if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or t.dim() != 2:
+            raise ValueError("factor panels must be contiguous float64 CUDA tensors of shape (r, n)")
+        if int(t.shape[0]) != desc.r:
+            raise ValueError("all panels must have the same rank")
+        desc.n[k] = int(t.shape[1])
+        desc.ld[k] = int(t.shape[1])
+        desc.U[k] = t.data_ptr()
+    return desc
+
+
+class OperatorDesc:
+    """Keeps the host arrays of a separable operator alive for the duration of a call."""
+
+    def __init__(self, L):
+        self.coef = np.ascontiguousarray(L.coef, dtype=np.float64)
+        self.idx = np.ascontiguousarray(L.op_index, dtype=np.int32)
+        self.datas = []
+        self.op_arrays = []
+        self.desc = cp_operator()
+        self.desc.d = L.d
+        self.desc.n_terms = L.n_terms
+        self.desc.coef = self.coef.ctypes.data
+        self.desc.op_index = self.idx.ctypes.data
+        for k, ops_k in enumerate(L.ops):
+            arr = (cp_op1d * len(ops_k))()
+            for a, op in enumerate(ops_k):
+                arr[a].kind = OP_KIND[op.kind]
+                arr[a].n = op.n
+                arr[a].half_bw = op.half_bw
+                if op.data is not None:
+                    dat = np.ascontiguousarray(op.data, dtype=np.float64).reshape(-1)
+                    self.datas.append(dat)
+                    arr[a].data = dat.ctypes.data
+                else:
+                    arr[a].data = None
+            self.op_arrays.append(arr)
+            self.desc.n_ops[k] = len(ops_k)
+            self.desc.ops[k] = C.cast(arr, C.c_void_p)
+
+
+def default_opts(**kw) -> cp_als_opts:
+    o = cp_als_opts()
+    lib().cp_als_default_opts(C.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+class Handle:
+    """A library handle bound to a HIP stream (default: torch's current stream)."""
+
+    def __init__(self, stream=None):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        self.h = C.c_void_p()
+        st = lib().cp_create(C.byref(self.h), C.c_void_p(stream.cuda_stream))
+        if st != CP_OK:
+            raise CpalsError(st, "cp_create failed")
+
+    def close(self):
+        if self.h:
+            lib().cp_destroy(self.h)
+            self.h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def check(self, st, allow_not_converged=False):
+        if st == CP_OK or (allow_not_converged and st == CP_ERR_NOT_CONVERGED):
+            return st
+        raise CpalsError(st, lib().cp_last_error(self.h).decode())
+
+
+# ----------------------------------------------------------------------------------------
+# the C ABI, one Python function per entry point
+# ----------------------------------------------------------------------------------------
+
+def cp_inner(h: Handle, x, y, out) -> None:
+    """out (1-element float64 CUDA tensor) <- <x, y>."""
+    xd, yd = tensor_desc(x), tensor_desc(y)
+    h.check(lib().cp_inner(h.h, C.byref(xd), C.byref(yd), C.c_void_p(out.data_ptr())))
+
+
+def cp_norm(h: Handle, x, out) -> None:
+    xd = tensor_desc(x)
+    h.check(lib().cp_norm(h.h, C.byref(xd), C.c_void_p(out.data_ptr())))
+
+
+def cp_apply_operator(h: Handle, L, x, y) -> None:
+    """y (rank n_terms * x.r panels) <- L x."""
+    Ld = OperatorDesc(L)
+    xd, yd = tensor_desc(x), tensor_desc(y)
+    h.check(lib().cp_apply_operator(h.h, C.byref(Ld.desc), C.byref(xd), C.byref(yd)))
+
+
+def cp_als_step(h: Handle, A, B, f_n, f_next, opts: Optional[cp_als_opts] = None) -> dict:
+    """One implicit step; f_next is in/out (guess in, solution out).  Returns the report."""
+    opts = default_opts() if opts is None else opts
+    Ad, Bd = OperatorDesc(A), OperatorDesc(B)
+    fd, gd = tensor_desc(f_n), tensor_desc(f_next)
+    rep = cp_als_report()
+    h.check(lib().cp_als_step(h.h, C.byref(Ad.desc), C.byref(Bd.desc), C.byref(fd), C.byref(gd), C.byref(opts),
+                              C.byref(rep)), allow_not_converged=True)
+    return rep.as_dict()
+
+
+def cp_als_run(h: Handle, A, B, f_init, f_io, n_steps: int, opts: Optional[cp_als_opts] = None,
+               traj=None) -> List[dict]:
+    """n_steps implicit steps in one launch; f_io in/out.  traj: optional float64 CUDA buffer of
+    n_steps * sum_k n_k r elements receiving every step's factors."""
+    opts = default_opts() if opts is None else opts
+    Ad, Bd = OperatorDesc(A), OperatorDesc(B)
+    fd, gd = tensor_desc(f_init), tensor_desc(f_io)
+    reps = (cp_als_report * n_steps)()
+    if traj is not None:
+        import torch
+        need = n_steps * sum(int(t.shape[1]) * int(f_io[0].shape[0]) for t in f_io)
+        if traj.dtype != torch.float64 or not traj.is_cuda or not traj.is_contiguous() or traj.numel() < need:
+            raise ValueError("traj must be a contiguous float64 CUDA buffer of at least %d elements" % need)
+    tp = C.c_void_p(traj.data_ptr()) if traj is not None else C.c_void_p()
+    h.check(lib().cp_als_run(h.h, C.byref(Ad.desc), C.byref(Bd.desc), C.byref(fd), C.byref(gd), n_steps,
+                             C.byref(opts), reps, tp), allow_not_converged=True)
+    return [r.as_dict() for r in reps]
+
+
+def cp_truncate(h: Handle, g, f, opts: Optional[cp_als_opts] = None) -> dict:
+    opts = default_opts() if opts is None else opts
+    gd, fd = tensor_desc(g), tensor_desc(f)
+    rep = cp_als_report()
+    h.check(lib().cp_truncate(h.h, C.byref(gd), C.byref(fd), C.byref(opts), C.byref(rep)), allow_not_converged=True)
+    return rep.as_dict()
+
+
+def cp_als_run_batched(h: Handle, As, Bs, f_inits, f_ios, n_steps: int,
+                       opts: Optional[cp_als_opts] = None) -> List[List[dict]]:
+    opts = default_opts() if opts is None else opts
+    count = len(As)
+    Ads = [OperatorDesc(a) for a in As]
+    Bds = [OperatorDesc(b) for b in Bs]
+    A_arr = (cp_operator * count)(*[a.desc for a in Ads])
+    B_arr = (cp_operator * count)(*[b.desc for b in Bds])
+    fi = (cp_tensor * count)(*[tensor_desc(f) for f in f_inits])
+    fo = (cp_tensor * count)(*[tensor_desc(f) for f in f_ios])
+    reps = (cp_als_report * (count * n_steps))()
+    h.check(lib().cp_als_run_batched(h.h, count, A_arr, B_arr, fi, fo, n_steps, C.byref(opts), reps),
+            allow_not_converged=True)
+    return [[reps[i * n_steps + s].as_dict() for s in range(n_steps)] for i in range(count)]

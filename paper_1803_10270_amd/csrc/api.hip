@@ -1,0 +1,737 @@
+// Host side of the libcpals C ABI: argument validation, problem packing, workspace
+// management and kernel launches.  See include/cpals.h for the contract of every call.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "cpals_internal.h"
+
+namespace cpals {
+// defined in basic_kernels.hip
+int gram_chunks(const int32_t* n, int d, int32_t* chunk0);
+hipError_t launch_inner(const GramJob& job, double* partial, double* out, bool sqrt_out, hipStream_t st);
+hipError_t launch_apply(const ApplyJob& job, int max_n, hipStream_t st);
+// defined in als_kernel.hip
+hipError_t launch_als(const Problem* d_problems, int count, hipStream_t stream);
+size_t als_smem_bytes();
+}  // namespace cpals
+
+using namespace cpals;
+
+struct cp_handle_s {
+    hipStream_t stream = nullptr;
+    int device = 0;
+    std::string err;
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+};
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+
+size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
+
+cp_status fail(cp_handle h, cp_status st, const std::string& msg) {
+    if (h) h->err = msg;
+    return st;
+}
+
+cp_status hip_fail(cp_handle h, hipError_t e, const char* what) {
+    return fail(h, CP_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, what)                     \
+    do {                                        \
+        hipError_t e_ = (expr);                 \
+        if (e_ != hipSuccess) return hip_fail(h, e_, what); \
+    } while (0)
+
+cp_status ensure_ws(cp_handle h, size_t bytes) {
+    if (bytes <= h->ws_bytes) return CP_OK;
+    HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+    if (h->ws) {
+        HIP_TRY(hipFree(h->ws), "hipFree");
+        h->ws = nullptr;
+        h->ws_bytes = 0;
+    }
+    size_t sz = std::max(bytes, (size_t)1 << 20);
+    HIP_TRY(hipMalloc(&h->ws, sz), "hipMalloc(workspace)");
+    h->ws_bytes = sz;
+    return CP_OK;
+}
+
+cp_status check_tensor(cp_handle h, const cp_tensor* t, const char* name, int max_n) {
+    if (!t) return fail(h, CP_ERR_INVALID_ARG, std::string(name) + " is null");
+    if (t->d < 1 || t->d > CP_MAX_DIMS) return fail(h, CP_ERR_SHAPE, std::string(name) + ": d out of range");
+    if (t->r < 1 || t->r > CP_MAX_RANK) return fail(h, CP_ERR_SHAPE, std::string(name) + ": r out of range 1..64");
+    for (int k = 0; k < t->d; ++k) {
+        if (t->n[k] < 1 || t->n[k] > max_n)
+            return fail(h, CP_ERR_SHAPE, std::string(name) + ": n[" + std::to_string(k) + "] out of range");
+        if (t->ld[k] < t->n[k]) return fail(h, CP_ERR_SHAPE, std::string(name) + ": ld < n");
+        if (!t->U[k]) return fail(h, CP_ERR_INVALID_ARG, std::string(name) + ": null panel");
+    }
+    return CP_OK;
+}
+
+// Host-side copy of a separable operator with the identity placed at op index 0 of every
+// dimension (the Hadamard factor of the identity block, o_k U_k^T U_k, is needed for the
+// preconditioner and for ||f||).
+struct HostOp {
+    int d = 0, T = 0;
+    std::vector<double> coef;
+    std::vector<int> idx;                      // T x d
+    int m[CP_MAX_DIMS] = {0};
+    std::vector<cp_op1d> ops[CP_MAX_DIMS];
+};
+
+cp_status check_operator(cp_handle h, const cp_operator* L, const char* name, int d, const int32_t* n,
+                         bool identity_first, HostOp& out) {
+    if (!L) return fail(h, CP_ERR_INVALID_ARG, std::string(name) + " is null");
+    if (L->d != d) return fail(h, CP_ERR_SHAPE, std::string(name) + ": d mismatch");
+    if (L->n_terms < 1 || L->n_terms > CP_MAX_TERMS) return fail(h, CP_ERR_SHAPE, std::string(name) + ": n_terms");
+    if (!L->coef || !L->op_index) return fail(h, CP_ERR_INVALID_ARG, std::string(name) + ": null table");
+    out.d = d;
+    out.T = L->n_terms;
+    out.coef.assign(L->coef, L->coef + L->n_terms);
+    out.idx.assign(L->op_index, L->op_index + (size_t)L->n_terms * d);
+    for (int k = 0; k < d; ++k) {
+        const int m = L->n_ops[k];
+        if (m < 1 || m > CP_MAX_OPS || !L->ops[k]) return fail(h, CP_ERR_SHAPE, std::string(name) + ": n_ops");
+        out.ops[k].assign(L->ops[k], L->ops[k] + m);
+        for (int a = 0; a < m; ++a) {
+            const cp_op1d& o = out.ops[k][a];
+            if (o.n != n[k]) return fail(h, CP_ERR_SHAPE, std::string(name) + ": operator size != n");
+            if (o.kind < CP_OP_IDENTITY || o.kind > CP_OP_RANK1)
+                return fail(h, CP_ERR_INVALID_ARG, std::string(name) + ": bad operator kind");
+            if (o.kind != CP_OP_IDENTITY && !o.data) return fail(h, CP_ERR_INVALID_ARG, std::string(name) + ": null op data");
+            if (o.kind == CP_OP_BAND && (o.half_bw < 0 || 2 * o.half_bw + 1 > 64))
+                return fail(h, CP_ERR_SHAPE, std::string(name) + ": band half width out of range");
+        }
+        for (int e = 0; e < out.T; ++e) {
+            const int a = out.idx[(size_t)e * d + k];
+            if (a < 0 || a >= m) return fail(h, CP_ERR_INVALID_ARG, std::string(name) + ": op_index out of range");
+        }
+        if (identity_first) {
+            int id = -1;
+            for (int a = 0; a < m; ++a)
+                if (out.ops[k][a].kind == CP_OP_IDENTITY) { id = a; break; }
+            if (id < 0) {
+                if (m == CP_MAX_OPS) return fail(h, CP_ERR_SHAPE, std::string(name) + ": no room for the identity op");
+                cp_op1d ident{CP_OP_IDENTITY, n[k], 0, nullptr};
+                out.ops[k].insert(out.ops[k].begin(), ident);
+                for (int e = 0; e < out.T; ++e) out.idx[(size_t)e * d + k] += 1;
+            } else if (id > 0) {
+                std::swap(out.ops[k][0], out.ops[k][id]);
+                for (int e = 0; e < out.T; ++e) {
+                    int& a = out.idx[(size_t)e * d + k];
+                    if (a == 0) a = id;
+                    else if (a == id) a = 0;
+                }
+            }
+        }
+        out.m[k] = (int)out.ops[k].size();
+    }
+    for (int e = 0; e < out.T; ++e)
+        if (!std::isfinite(out.coef[e])) return fail(h, CP_ERR_INVALID_ARG, std::string(name) + ": non-finite coef");
+    return CP_OK;
+}
+
+size_t op_data_len(const cp_op1d& o) {
+    switch (o.kind) {
+        case CP_OP_DIAG: return (size_t)o.n;
+        case CP_OP_BAND: return (size_t)(2 * o.half_bw + 1) * o.n;
+        case CP_OP_RANK1: return (size_t)2 * o.n;
+        default: return 0;
+    }
+}
+
+// Dense entry O[i, j] of a 1-D operator (host, for Frobenius products).
+double op_entry(const cp_op1d& o, int i, int j) {
+    const int n = o.n;
+    switch (o.kind) {
+        case CP_OP_IDENTITY: return i == j ? 1.0 : 0.0;
+        case CP_OP_DIAG: return i == j ? o.data[i] : 0.0;
+        case CP_OP_BAND: {
+            double v = 0.0;
+            for (int jj = 0; jj <= 2 * o.half_bw; ++jj) {
+                int c = ((i + jj - o.half_bw) % n + n) % n;
+                if (c == j) v += o.data[(size_t)jj * n + i];
+            }
+            return v;
+        }
+        default: return o.data[i] * o.data[n + j];
+    }
+}
+
+// <O1, O2>_F = trace(O1^T O2).
+double frob(const cp_op1d& a, const cp_op1d& b) {
+    const int n = a.n;
+    if (a.kind == CP_OP_RANK1 || b.kind == CP_OP_RANK1) {
+        if (a.kind == CP_OP_RANK1 && b.kind == CP_OP_RANK1) {
+            double s1 = 0.0, s2 = 0.0;
+            for (int i = 0; i < n; ++i) { s1 += a.data[i] * b.data[i]; s2 += a.data[n + i] * b.data[n + i]; }
+            return s1 * s2;
+        }
+        const cp_op1d& R = (a.kind == CP_OP_RANK1) ? a : b;
+        const cp_op1d& S = (a.kind == CP_OP_RANK1) ? b : a;
+        // sum_ij m_i w_j S_ij over S's sparsity (S not rank-1)
+        double s = 0.0;
+        for (int i = 0; i < n; ++i) {
+            if (S.kind == CP_OP_BAND) {
+                std::vector<int> cols;
+                for (int jj = 0; jj <= 2 * S.half_bw; ++jj) {
+                    const int c = ((i + jj - S.half_bw) % n + n) % n;
+                    if (std::find(cols.begin(), cols.end(), c) == cols.end()) cols.push_back(c);
+                }
+                for (int c : cols) s += R.data[i] * R.data[n + c] * op_entry(S, i, c);
+            } else {
+                s += R.data[i] * R.data[n + i] * op_entry(S, i, i);
+            }
+        }
+        return s;
+    }
+    // both sparse (identity / diag / band): sum over the union of row patterns
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) {
+        std::vector<int> cols;
+        auto add = [&](const cp_op1d& o) {
+            if (o.kind == CP_OP_BAND) {
+                for (int jj = 0; jj <= 2 * o.half_bw; ++jj) {
+                    const int c = ((i + jj - o.half_bw) % n + n) % n;
+                    if (std::find(cols.begin(), cols.end(), c) == cols.end()) cols.push_back(c);
+                }
+            } else if (std::find(cols.begin(), cols.end(), i) == cols.end()) {
+                cols.push_back(i);
+            }
+        };
+        add(a);
+        const std::vector<int> ca = cols;
+        cols.clear();
+        add(b);
+        for (int c : ca)
+            if (std::find(cols.begin(), cols.end(), c) != cols.end()) s += op_entry(a, i, c) * op_entry(b, i, c);
+    }
+    return s;
+}
+
+// Byte layout of one problem's device region.
+struct Layout {
+    size_t problem, opdata, pairsC, pairsD, U, V, Q, G, X, P, Z, Cm, Dm, H0, Hinv, S, vec, reports, total;
+    size_t n_opdata, n_pairsC, n_pairsD;
+    int64_t offU[CP_MAX_DIMS], offV[CP_MAX_DIMS], offQ[CP_MAX_DIMS], offG[CP_MAX_DIMS], offX[CP_MAX_DIMS];
+    int nmax, mAmax, mBmax, r0max;
+};
+
+struct Packed {
+    Problem pb;
+    std::vector<double> opdata;
+    std::vector<PairRec> pairsC, pairsD;
+    Layout lay;
+    // host op data pointers in the same order as opdata, to rebase
+    std::vector<std::pair<int, int>> opref;  // (side*CP_MAX_DIMS + k, a)
+};
+
+cp_status pack_problem(cp_handle h, const HostOp& A, const HostOp& B, const cp_tensor* f_init, const cp_tensor* f_io,
+                       int n_steps, const cp_als_opts& o, Packed& pk) {
+    const int d = f_io->d, r = f_io->r, r0 = f_init->r;
+    Problem& pb = pk.pb;
+    std::memset(&pb, 0, sizeof(pb));
+    pb.d = d;
+    pb.r = r;
+    pb.r0 = r0;
+    pb.n_steps = n_steps;
+    Layout& L = pk.lay;
+    L.nmax = 0;
+    L.mAmax = 0;
+    L.mBmax = 0;
+    L.r0max = (n_steps > 1) ? std::max(r0, r) : r0;
+    for (int k = 0; k < d; ++k) {
+        pb.n[k] = f_io->n[k];
+        pb.mA[k] = A.m[k];
+        pb.mB[k] = B.m[k];
+        L.nmax = std::max(L.nmax, pb.n[k]);
+        L.mAmax = std::max(L.mAmax, A.m[k]);
+        L.mBmax = std::max(L.mBmax, B.m[k]);
+    }
+    // operator data
+    pk.opdata.clear();
+    std::vector<size_t> offA[CP_MAX_DIMS], offB[CP_MAX_DIMS];
+    for (int side = 0; side < 2; ++side) {
+        const HostOp& X = side == 0 ? A : B;
+        for (int k = 0; k < d; ++k) {
+            for (int a = 0; a < X.m[k]; ++a) {
+                const cp_op1d& op = X.ops[k][a];
+                const size_t len = op_data_len(op);
+                (side == 0 ? offA : offB)[k].push_back(pk.opdata.size());
+                pk.opdata.insert(pk.opdata.end(), op.data, op.data + len);
+                // keep 32-byte alignment of every array
+                while (pk.opdata.size() % 4) pk.opdata.push_back(0.0);
+            }
+        }
+    }
+    // Frobenius products of A's ops per dim
+    for (int q = 0; q < d; ++q)
+        for (int a = 0; a < A.m[q]; ++a)
+            for (int b = 0; b < A.m[q]; ++b) pb.trOO[q][a + b * A.m[q]] = frob(A.ops[q][a], A.ops[q][b]);
+    // pair lists
+    pk.pairsC.clear();
+    pk.pairsD.clear();
+    for (int q = 0; q < d; ++q) {
+        const int mq = A.m[q];
+        for (int blk = 0; blk < mq * mq; ++blk) {
+            pb.offC[q][blk] = (int32_t)pk.pairsC.size();
+            for (int e = 0; e < A.T; ++e)
+                for (int z = 0; z < A.T; ++z) {
+                    const int a = A.idx[(size_t)e * d + q], b = A.idx[(size_t)z * d + q];
+                    if (a + b * mq != blk) continue;
+                    PairRec pr;
+                    std::memset(&pr, 0, sizeof(pr));
+                    pr.coef = A.coef[e] * A.coef[z];
+                    for (int k = 0; k < d; ++k) {
+                        pr.a[k] = (uint8_t)A.idx[(size_t)e * d + k];
+                        pr.b[k] = (uint8_t)A.idx[(size_t)z * d + k];
+                    }
+                    pk.pairsC.push_back(pr);
+                }
+        }
+        pb.offC[q][mq * mq] = (int32_t)pk.pairsC.size();
+        const int mbq = B.m[q];
+        for (int blk = 0; blk < mq * mbq; ++blk) {
+            pb.offD[q][blk] = (int32_t)pk.pairsD.size();
+            for (int e = 0; e < A.T; ++e)
+                for (int z = 0; z < B.T; ++z) {
+                    const int a = A.idx[(size_t)e * d + q], b = B.idx[(size_t)z * d + q];
+                    if (a + b * mq != blk) continue;
+                    PairRec pr;
+                    std::memset(&pr, 0, sizeof(pr));
+                    pr.coef = A.coef[e] * B.coef[z];
+                    for (int k = 0; k < d; ++k) {
+                        pr.a[k] = (uint8_t)A.idx[(size_t)e * d + k];
+                        pr.b[k] = (uint8_t)B.idx[(size_t)z * d + k];
+                    }
+                    pk.pairsD.push_back(pr);
+                }
+        }
+        pb.offD[q][mq * mbq] = (int32_t)pk.pairsD.size();
+    }
+    // layout (bytes, relative to the region base)
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o2 = off;
+        off = align_up(off + bytes);
+        return o2;
+    };
+    L.problem = take(sizeof(Problem));
+    L.opdata = take(pk.opdata.size() * sizeof(double));
+    L.pairsC = take(pk.pairsC.size() * sizeof(PairRec));
+    L.pairsD = take(pk.pairsD.size() * sizeof(PairRec));
+    size_t nU = 0, nV = 0, nQ = 0, nG = 0, nX = 0;
+    for (int k = 0; k < d; ++k) {
+        L.offU[k] = (int64_t)nU;
+        nU += (size_t)pb.n[k] * r;
+        L.offV[k] = (int64_t)nV;
+        nV += (size_t)pb.n[k] * L.r0max;
+        L.offQ[k] = (int64_t)nQ;
+        nQ += (size_t)pb.n[k] * B.m[k] * L.r0max;
+        L.offG[k] = (int64_t)nG;
+        nG += (size_t)(A.m[k] * r) * (A.m[k] * r);
+        L.offX[k] = (int64_t)nX;
+        nX += (size_t)(A.m[k] * r) * (B.m[k] * L.r0max);
+    }
+    L.U = take(nU * 8);
+    L.V = take(nV * 8);
+    L.Q = take(nQ * 8);
+    L.G = take(nG * 8);
+    L.X = take(nX * 8);
+    L.P = take((size_t)L.nmax * L.mAmax * r * 8);
+    L.Z = take((size_t)L.nmax * L.mAmax * r * 8);
+    L.Cm = take((size_t)(L.mAmax * r) * (L.mAmax * r) * 8);
+    L.Dm = take((size_t)(L.mAmax * r) * (L.mBmax * L.r0max) * 8);
+    L.H0 = take((size_t)r * r * 8);
+    L.Hinv = take((size_t)r * r * 8);
+    L.S = take((size_t)r * r * 8);
+    L.vec = take((size_t)6 * align_up((size_t)L.nmax * r * 8));
+    L.reports = take((size_t)n_steps * sizeof(cp_als_report));
+    L.total = off;
+    L.n_opdata = pk.opdata.size();
+    L.n_pairsC = pk.pairsC.size();
+    L.n_pairsD = pk.pairsD.size();
+    // options
+    pb.tol = o.tol;
+    pb.eps_reg = o.eps_reg;
+    pb.pcg_tol = o.pcg_tol;
+    pb.max_sweeps = o.max_sweeps;
+    pb.pcg_max = o.pcg_max_iter;
+    pb.precision = o.precision;
+    // op descriptors get device pointers at rebase time; remember offsets in elements
+    for (int k = 0; k < d; ++k) {
+        for (int a = 0; a < A.m[k]; ++a) {
+            pb.opA[k][a].kind = A.ops[k][a].kind;
+            pb.opA[k][a].hbw = A.ops[k][a].half_bw;
+            pb.opA[k][a].data = reinterpret_cast<const double*>(offA[k][a]);
+        }
+        for (int b = 0; b < B.m[k]; ++b) {
+            pb.opB[k][b].kind = B.ops[k][b].kind;
+            pb.opB[k][b].hbw = B.ops[k][b].half_bw;
+            pb.opB[k][b].data = reinterpret_cast<const double*>(offB[k][b]);
+        }
+    }
+    (void)h;
+    return CP_OK;
+}
+
+// Fill in device pointers of a packed problem placed at device address `base`.
+void rebase(Packed& pk, char* base, double* traj) {
+    Problem& pb = pk.pb;
+    const Layout& L = pk.lay;
+    double* opd = reinterpret_cast<double*>(base + L.opdata);
+    for (int k = 0; k < pb.d; ++k) {
+        for (int a = 0; a < pb.mA[k]; ++a)
+            pb.opA[k][a].data = pb.opA[k][a].kind == CP_OP_IDENTITY ? nullptr
+                                : opd + reinterpret_cast<size_t>(pb.opA[k][a].data);
+        for (int b = 0; b < pb.mB[k]; ++b)
+            pb.opB[k][b].data = pb.opB[k][b].kind == CP_OP_IDENTITY ? nullptr
+                                : opd + reinterpret_cast<size_t>(pb.opB[k][b].data);
+        pb.offU[k] = L.offU[k];
+        pb.offV[k] = L.offV[k];
+        pb.offQ[k] = L.offQ[k];
+        pb.offG[k] = L.offG[k];
+        pb.offX[k] = L.offX[k];
+    }
+    pb.pairsC = reinterpret_cast<const PairRec*>(base + L.pairsC);
+    pb.pairsD = reinterpret_cast<const PairRec*>(base + L.pairsD);
+    pb.U = reinterpret_cast<double*>(base + L.U);
+    pb.V = reinterpret_cast<double*>(base + L.V);
+    pb.Q = reinterpret_cast<double*>(base + L.Q);
+    pb.G = reinterpret_cast<double*>(base + L.G);
+    pb.X = reinterpret_cast<double*>(base + L.X);
+    pb.P = reinterpret_cast<double*>(base + L.P);
+    pb.Z = reinterpret_cast<double*>(base + L.Z);
+    pb.Cm = reinterpret_cast<double*>(base + L.Cm);
+    pb.Dm = reinterpret_cast<double*>(base + L.Dm);
+    pb.H0 = reinterpret_cast<double*>(base + L.H0);
+    pb.Hinv = reinterpret_cast<double*>(base + L.Hinv);
+    pb.S = reinterpret_cast<double*>(base + L.S);
+    const size_t vstride = align_up((size_t)L.nmax * pb.r * 8);
+    char* vb = base + L.vec;
+    pb.vb = reinterpret_cast<double*>(vb + 0 * vstride);
+    pb.vx = reinterpret_cast<double*>(vb + 1 * vstride);
+    pb.vr = reinterpret_cast<double*>(vb + 2 * vstride);
+    pb.vz = reinterpret_cast<double*>(vb + 3 * vstride);
+    pb.vp = reinterpret_cast<double*>(vb + 4 * vstride);
+    pb.vw = reinterpret_cast<double*>(vb + 5 * vstride);
+    pb.reports = reinterpret_cast<cp_als_report*>(base + L.reports);
+    pb.traj = traj;
+}
+
+cp_status check_opts(cp_handle h, const cp_als_opts* o) {
+    if (!o) return fail(h, CP_ERR_INVALID_ARG, "opts is null");
+    if (!(o->tol >= 0.0) || o->max_sweeps < 1 || !(o->eps_reg >= 0.0) || !(o->pcg_tol > 0.0) || o->pcg_max_iter < 1)
+        return fail(h, CP_ERR_INVALID_ARG, "bad ALS options");
+    if (o->precision != CP_PREC_FP64 && o->precision != CP_PREC_MIXED)
+        return fail(h, CP_ERR_INVALID_ARG, "bad precision");
+    if (o->precision == CP_PREC_MIXED) return fail(h, CP_ERR_UNSUPPORTED, "mixed precision is not built yet");
+    return CP_OK;
+}
+
+cp_status copy_panels_in(cp_handle h, const cp_tensor* t, double* dst, const int64_t* off) {
+    for (int k = 0; k < t->d; ++k)
+        HIP_TRY(hipMemcpy2DAsync(dst + off[k], (size_t)t->n[k] * 8, t->U[k], (size_t)t->ld[k] * 8, (size_t)t->n[k] * 8,
+                                 t->r, hipMemcpyDeviceToDevice, h->stream),
+                "hipMemcpy2DAsync(in)");
+    return CP_OK;
+}
+
+cp_status copy_panels_out(cp_handle h, const double* src, const int64_t* off, cp_tensor* t) {
+    for (int k = 0; k < t->d; ++k)
+        HIP_TRY(hipMemcpy2DAsync(t->U[k], (size_t)t->ld[k] * 8, src + off[k], (size_t)t->n[k] * 8, (size_t)t->n[k] * 8,
+                                 t->r, hipMemcpyDeviceToDevice, h->stream),
+                "hipMemcpy2DAsync(out)");
+    return CP_OK;
+}
+
+cp_status run_problems(cp_handle h, int count, const HostOp* A, const HostOp* B, const cp_tensor* f_init,
+                       cp_tensor* f_io, int n_steps, const cp_als_opts* o, cp_als_report* reports, double* traj) {
+    std::vector<Packed> pk(count);
+    std::vector<size_t> base(count);
+    size_t total = 0;
+    for (int i = 0; i < count; ++i) {
+        cp_status st = pack_problem(h, A[i], B[i], &f_init[i], &f_io[i], n_steps, *o, pk[i]);
+        if (st != CP_OK) return st;
+        base[i] = total;
+        total += align_up(pk[i].lay.total);
+    }
+    // problem descriptors are gathered in one array, ordered by estimated cost (largest
+    // first) so that the longest problems start first when workgroups outnumber CUs
+    const size_t desc_bytes = align_up((size_t)count * sizeof(Problem));
+    cp_status st = ensure_ws(h, total + desc_bytes);
+    if (st != CP_OK) return st;
+    char* ws = static_cast<char*>(h->ws);
+    std::vector<int> order(count);
+    std::vector<double> cost(count);
+    for (int i = 0; i < count; ++i) {
+        order[i] = i;
+        double c = 0.0;
+        for (int k = 0; k < f_io[i].d; ++k) c += (double)f_io[i].n[k] * A[i].m[k] * A[i].m[k] * f_io[i].r * f_io[i].r;
+        cost[i] = c;
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    std::vector<Problem> descs(count);
+    for (int i = 0; i < count; ++i) {
+        Packed& p = pk[i];
+        char* b = ws + base[i];
+        rebase(p, b, traj);
+        HIP_TRY(hipMemcpyAsync(b + p.lay.opdata, p.opdata.data(), p.opdata.size() * 8, hipMemcpyHostToDevice, h->stream),
+                "hipMemcpyAsync(opdata)");
+        if (!p.pairsC.empty())
+            HIP_TRY(hipMemcpyAsync(b + p.lay.pairsC, p.pairsC.data(), p.pairsC.size() * sizeof(PairRec),
+                                   hipMemcpyHostToDevice, h->stream),
+                    "hipMemcpyAsync(pairsC)");
+        if (!p.pairsD.empty())
+            HIP_TRY(hipMemcpyAsync(b + p.lay.pairsD, p.pairsD.data(), p.pairsD.size() * sizeof(PairRec),
+                                   hipMemcpyHostToDevice, h->stream),
+                    "hipMemcpyAsync(pairsD)");
+        st = copy_panels_in(h, &f_init[i], p.pb.V, p.pb.offV);
+        if (st != CP_OK) return st;
+        st = copy_panels_in(h, &f_io[i], p.pb.U, p.pb.offU);
+        if (st != CP_OK) return st;
+    }
+    for (int j = 0; j < count; ++j) descs[j] = pk[order[j]].pb;
+    Problem* d_desc = reinterpret_cast<Problem*>(ws + total);
+    HIP_TRY(hipMemcpyAsync(d_desc, descs.data(), (size_t)count * sizeof(Problem), hipMemcpyHostToDevice, h->stream),
+            "hipMemcpyAsync(problems)");
+    HIP_TRY(launch_als(d_desc, count, h->stream), "als kernel launch");
+    for (int i = 0; i < count; ++i) {
+        st = copy_panels_out(h, pk[i].pb.U, pk[i].pb.offU, &f_io[i]);
+        if (st != CP_OK) return st;
+        HIP_TRY(hipMemcpyAsync(reports + (size_t)i * n_steps, pk[i].pb.reports, (size_t)n_steps * sizeof(cp_als_report),
+                               hipMemcpyDeviceToHost, h->stream),
+                "hipMemcpyAsync(reports)");
+    }
+    HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+    bool nc = false;
+    for (int i = 0; i < count * n_steps; ++i) nc |= (reports[i].flags & CP_FLAG_NOT_CONVERGED) != 0;
+    if (nc) return fail(h, CP_ERR_NOT_CONVERGED, "ALS reached max_sweeps before eps_conv <= tol");
+    return CP_OK;
+}
+
+cp_status prepare_step(cp_handle h, const cp_operator* A, const cp_operator* B, const cp_tensor* f_init,
+                       const cp_tensor* f_io, int n_steps, const cp_als_opts* opts, HostOp& hA, HostOp& hB) {
+    cp_status st = check_tensor(h, f_init, "f_init", CP_MAX_N);
+    if (st != CP_OK) return st;
+    st = check_tensor(h, f_io, "f_io", CP_MAX_N);
+    if (st != CP_OK) return st;
+    if (f_init->d != f_io->d) return fail(h, CP_ERR_SHAPE, "f_init and f_io differ in d");
+    for (int k = 0; k < f_io->d; ++k)
+        if (f_init->n[k] != f_io->n[k]) return fail(h, CP_ERR_SHAPE, "f_init and f_io differ in n");
+    if (n_steps < 1) return fail(h, CP_ERR_INVALID_ARG, "n_steps < 1");
+    st = check_opts(h, opts);
+    if (st != CP_OK) return st;
+    st = check_operator(h, A, "A", f_io->d, f_io->n, true, hA);
+    if (st != CP_OK) return st;
+    return check_operator(h, B, "B", f_io->d, f_io->n, false, hB);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* cp_version(void) { return "cpals-gfx950 0.1"; }
+
+cp_status cp_create(cp_handle* handle, void* hip_stream) {
+    if (!handle) return CP_ERR_INVALID_ARG;
+    cp_handle h = new (std::nothrow) cp_handle_s();
+    if (!h) return CP_ERR_INVALID_ARG;
+    h->stream = static_cast<hipStream_t>(hip_stream);
+    if (hipGetDevice(&h->device) != hipSuccess) {
+        delete h;
+        return CP_ERR_HIP;
+    }
+    *handle = h;
+    return CP_OK;
+}
+
+cp_status cp_destroy(cp_handle h) {
+    if (!h) return CP_ERR_INVALID_ARG;
+    if (h->ws) {
+        (void)hipStreamSynchronize(h->stream);
+        (void)hipFree(h->ws);
+    }
+    delete h;
+    return CP_OK;
+}
+
+cp_status cp_set_stream(cp_handle h, void* hip_stream) {
+    if (!h) return CP_ERR_INVALID_ARG;
+    h->stream = static_cast<hipStream_t>(hip_stream);
+    return CP_OK;
+}
+
+const char* cp_last_error(cp_handle h) { return h ? h->err.c_str() : "null handle"; }
+
+cp_status cp_als_default_opts(cp_als_opts* o) {
+    if (!o) return CP_ERR_INVALID_ARG;
+    o->tol = 1e-8;
+    o->max_sweeps = 200;
+    o->eps_reg = 1e-10;
+    o->pcg_tol = 1e-14;
+    o->pcg_max_iter = 100;
+    o->precision = CP_PREC_FP64;
+    return CP_OK;
+}
+
+static cp_status inner_impl(cp_handle h, const cp_tensor* x, const cp_tensor* y, double* out_dev, bool sq) {
+    if (!h) return CP_ERR_INVALID_ARG;
+    cp_status st = check_tensor(h, x, "x", 1 << 28);
+    if (st != CP_OK) return st;
+    st = check_tensor(h, y, "y", 1 << 28);
+    if (st != CP_OK) return st;
+    if (!out_dev) return fail(h, CP_ERR_INVALID_ARG, "out_dev is null");
+    if (x->d != y->d) return fail(h, CP_ERR_SHAPE, "x and y differ in d");
+    GramJob job;
+    std::memset(&job, 0, sizeof(job));
+    job.d = x->d;
+    job.rx = x->r;
+    job.ry = y->r;
+    for (int k = 0; k < x->d; ++k) {
+        if (x->n[k] != y->n[k]) return fail(h, CP_ERR_SHAPE, "x and y differ in n");
+        job.X[k] = x->U[k];
+        job.Y[k] = y->U[k];
+        job.ldx[k] = x->ld[k];
+        job.ldy[k] = y->ld[k];
+        job.n[k] = x->n[k];
+    }
+    const int nch = gram_chunks(job.n, job.d, job.chunk0);
+    st = ensure_ws(h, (size_t)nch * x->r * y->r * 8 + 256);
+    if (st != CP_OK) return st;
+    HIP_TRY(launch_inner(job, static_cast<double*>(h->ws), out_dev, sq, h->stream), "inner launch");
+    return CP_OK;
+}
+
+cp_status cp_inner(cp_handle h, const cp_tensor* x, const cp_tensor* y, double* out_dev) {
+    return inner_impl(h, x, y, out_dev, false);
+}
+
+cp_status cp_norm(cp_handle h, const cp_tensor* x, double* out_dev) { return inner_impl(h, x, x, out_dev, true); }
+
+cp_status cp_apply_operator(cp_handle h, const cp_operator* L, const cp_tensor* x, cp_tensor* y) {
+    if (!h) return CP_ERR_INVALID_ARG;
+    cp_status st = check_tensor(h, x, "x", 1 << 28);
+    if (st != CP_OK) return st;
+    if (!y) return fail(h, CP_ERR_INVALID_ARG, "y is null");
+    if (y->d != x->d) return fail(h, CP_ERR_SHAPE, "y.d != x.d");
+    HostOp hL;
+    st = check_operator(h, L, "L", x->d, x->n, false, hL);
+    if (st != CP_OK) return st;
+    if ((int64_t)y->r != (int64_t)hL.T * x->r) return fail(h, CP_ERR_SHAPE, "y.r must equal n_terms * x.r");
+    for (int k = 0; k < x->d; ++k) {
+        if (y->n[k] != x->n[k] || y->ld[k] < y->n[k] || !y->U[k]) return fail(h, CP_ERR_SHAPE, "bad y panel");
+    }
+    // upload op data, coef and op_index
+    std::vector<double> blob;
+    std::vector<size_t> offs[CP_MAX_DIMS];
+    for (int k = 0; k < x->d; ++k)
+        for (int a = 0; a < hL.m[k]; ++a) {
+            const cp_op1d& op = hL.ops[k][a];
+            offs[k].push_back(blob.size());
+            blob.insert(blob.end(), op.data, op.data + op_data_len(op));
+            while (blob.size() % 4) blob.push_back(0.0);
+        }
+    const size_t coef_off = blob.size();
+    blob.insert(blob.end(), hL.coef.begin(), hL.coef.end());
+    while (blob.size() % 4) blob.push_back(0.0);
+    const size_t idx_off_bytes = blob.size() * 8;
+    const size_t total = idx_off_bytes + hL.idx.size() * 4 + 256;
+    st = ensure_ws(h, total);
+    if (st != CP_OK) return st;
+    char* ws = static_cast<char*>(h->ws);
+    HIP_TRY(hipMemcpyAsync(ws, blob.data(), blob.size() * 8, hipMemcpyHostToDevice, h->stream), "upload op data");
+    HIP_TRY(hipMemcpyAsync(ws + idx_off_bytes, hL.idx.data(), hL.idx.size() * 4, hipMemcpyHostToDevice, h->stream),
+            "upload op index");
+    ApplyJob job;
+    std::memset(&job, 0, sizeof(job));
+    job.d = x->d;
+    job.r = x->r;
+    job.n_terms = hL.T;
+    job.coef = reinterpret_cast<const double*>(ws) + coef_off;
+    job.op_index = reinterpret_cast<const int32_t*>(ws + idx_off_bytes);
+    int max_n = 0;
+    for (int k = 0; k < x->d; ++k) {
+        job.X[k] = x->U[k];
+        job.Y[k] = y->U[k];
+        job.ldx[k] = x->ld[k];
+        job.ldy[k] = y->ld[k];
+        job.n[k] = x->n[k];
+        max_n = std::max(max_n, x->n[k]);
+        for (int a = 0; a < hL.m[k]; ++a) {
+            job.ops[k][a].kind = hL.ops[k][a].kind;
+            job.ops[k][a].hbw = hL.ops[k][a].half_bw;
+            job.ops[k][a].data = reinterpret_cast<const double*>(ws) + offs[k][a];
+        }
+    }
+    HIP_TRY(launch_apply(job, max_n, h->stream), "apply launch");
+    // the host blobs must outlive the asynchronous uploads
+    HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+    return CP_OK;
+}
+
+cp_status cp_als_run(cp_handle h, const cp_operator* A, const cp_operator* B, const cp_tensor* f_init, cp_tensor* f_io,
+                     int32_t n_steps, const cp_als_opts* opts, cp_als_report* reports, double* traj) {
+    if (!h) return CP_ERR_INVALID_ARG;
+    if (!reports) return fail(h, CP_ERR_INVALID_ARG, "reports is null");
+    HostOp hA, hB;
+    cp_status st = prepare_step(h, A, B, f_init, f_io, n_steps, opts, hA, hB);
+    if (st != CP_OK) return st;
+    if (n_steps > 1 && f_init->r > f_io->r) {
+        // V holds rank max(r0, r); fine.  Nothing to reject.
+    }
+    return run_problems(h, 1, &hA, &hB, f_init, f_io, n_steps, opts, reports, traj);
+}
+
+cp_status cp_als_step(cp_handle h, const cp_operator* A, const cp_operator* B, const cp_tensor* f_n, cp_tensor* f_next,
+                      const cp_als_opts* opts, cp_als_report* report) {
+    return cp_als_run(h, A, B, f_n, f_next, 1, opts, report, nullptr);
+}
+
+cp_status cp_truncate(cp_handle h, const cp_tensor* g, cp_tensor* f, const cp_als_opts* opts, cp_als_report* report) {
+    if (!h) return CP_ERR_INVALID_ARG;
+    if (!g || !f) return fail(h, CP_ERR_INVALID_ARG, "null tensor");
+    if (g->d < 1 || g->d > CP_MAX_DIMS) return fail(h, CP_ERR_SHAPE, "g: d out of range");
+    cp_op1d ident[CP_MAX_DIMS];
+    double one = 1.0;
+    int32_t idx[CP_MAX_DIMS] = {0};
+    cp_operator I;
+    std::memset(&I, 0, sizeof(I));
+    I.d = g->d;
+    I.n_terms = 1;
+    I.coef = &one;
+    I.op_index = idx;
+    for (int k = 0; k < g->d; ++k) {
+        ident[k] = cp_op1d{CP_OP_IDENTITY, g->n[k], 0, nullptr};
+        I.n_ops[k] = 1;
+        I.ops[k] = &ident[k];
+    }
+    return cp_als_run(h, &I, &I, g, f, 1, opts, report, nullptr);
+}
+
+cp_status cp_als_run_batched(cp_handle h, int32_t count, const cp_operator* A, const cp_operator* B,
+                             const cp_tensor* f_init, cp_tensor* f_io, int32_t n_steps, const cp_als_opts* opts,
+                             cp_als_report* reports) {
+    if (!h) return CP_ERR_INVALID_ARG;
+    if (count < 1 || !A || !B || !f_init || !f_io || !reports) return fail(h, CP_ERR_INVALID_ARG, "bad batch arguments");
+    std::vector<HostOp> hA(count), hB(count);
+    for (int i = 0; i < count; ++i) {
+        cp_status st = prepare_step(h, &A[i], &B[i], &f_init[i], &f_io[i], n_steps, opts, hA[i], hB[i]);
+        if (st != CP_OK) return fail(h, st, "problem " + std::to_string(i) + ": " + h->err);
+    }
+    return run_problems(h, count, hA.data(), hB.data(), f_init, f_io, n_steps, opts, reports, nullptr);
+}
+
+}  // extern "C"

@@ -1,0 +1,87 @@
+// Internal descriptors shared by the host side of libcpals and its HIP kernels.
+#pragma once
+#include <stdint.h>
+#include "../../include/cpals.h"
+
+namespace cpals {
+
+constexpr int WG = 1024;          // threads of the persistent ALS workgroup (16 waves)
+constexpr int NWAVES = WG / 64;
+
+// One distinct 1-D operator on the device.
+struct OpDev {
+    int32_t kind;      // cp_op_kind
+    int32_t hbw;       // half bandwidth (band)
+    const double* data;  // device pointer into the problem blob (null for identity)
+};
+
+// Pair record (e, z) for the Hadamard assembly of one block of C (or D): the product
+// coefficient and, per dimension k, the block (a[k], b[k]) of G_k (or X_k) it multiplies in
+// (entries for k == q are unused).
+struct PairRec {
+    double coef;
+    uint8_t a[CP_MAX_DIMS];
+    uint8_t b[CP_MAX_DIMS];
+};
+
+// Everything one ALS problem needs on the device (lives in device memory; copied to LDS
+// by the kernel).
+struct Problem {
+    int32_t d, r, r0, n_steps;
+    int32_t n[CP_MAX_DIMS];
+    int32_t mA[CP_MAX_DIMS];   // distinct ops of A per dim (op 0 is the identity)
+    int32_t mB[CP_MAX_DIMS];
+    OpDev opA[CP_MAX_DIMS][CP_MAX_OPS];
+    OpDev opB[CP_MAX_DIMS][CP_MAX_OPS];
+    double trOO[CP_MAX_DIMS][CP_MAX_OPS * CP_MAX_OPS];  // <O^a, O^b>_F of A's ops, dim q
+    // Hadamard pair lists, per q: C blocks (mA x mA, column-major block index a + b*mA),
+    // then D blocks (mA x mB, index a + b*mA).  *_off[q][blk] .. *_off[q][blk+1].
+    const PairRec* pairsC;
+    const PairRec* pairsD;
+    int32_t offC[CP_MAX_DIMS][CP_MAX_OPS * CP_MAX_OPS + 1];
+    int32_t offD[CP_MAX_DIMS][CP_MAX_OPS * CP_MAX_OPS + 1];
+    // state (device, doubles): offsets in elements from the base pointers
+    double* U;  int64_t offU[CP_MAX_DIMS];   // n_k x r
+    double* V;  int64_t offV[CP_MAX_DIMS];   // n_k x r0
+    double* Q;  int64_t offQ[CP_MAX_DIMS];   // n_k x (mB_k r0): [O_B^b V_k]_b
+    double* G;  int64_t offG[CP_MAX_DIMS];   // (mA_k r)^2: P_k^T P_k
+    double* X;  int64_t offX[CP_MAX_DIMS];   // (mA_k r) x (mB_k r0): P_k^T Q_k
+    // scratch
+    double* P;     // n_max x mA_max r  (applied panel / matvec T)
+    double* Z;     // n_max x mA_max r  (matvec Z, RHS Y)
+    double* Cm;    // (mA_max r)^2
+    double* Dm;    // (mA_max r) x (mB_max r0)
+    double* H0;    // r x r
+    double* Hinv;  // r x r
+    double* S;     // r x r
+    double* vb; double* vx; double* vr; double* vz; double* vp; double* vw;  // n_max x r
+    // options
+    double tol, eps_reg, pcg_tol;
+    int32_t max_sweeps, pcg_max, precision, pad_;
+    // outputs
+    cp_als_report* reports;   // device array of n_steps
+    double* traj;             // nullable: n_steps * sum_k n_k r
+};
+
+// Scalar product of two CP tensors: per-dimension Gram partials over row chunks.
+struct GramJob {
+    const double* X[CP_MAX_DIMS];
+    const double* Y[CP_MAX_DIMS];
+    int32_t ldx[CP_MAX_DIMS], ldy[CP_MAX_DIMS];
+    int32_t n[CP_MAX_DIMS];
+    int32_t chunk0[CP_MAX_DIMS + 1];   // prefix sum of row chunks per dimension
+    int32_t d, rx, ry;
+};
+
+// Operator application job.
+struct ApplyJob {
+    const double* X[CP_MAX_DIMS];
+    double* Y[CP_MAX_DIMS];
+    int32_t ldx[CP_MAX_DIMS], ldy[CP_MAX_DIMS], n[CP_MAX_DIMS];
+    OpDev ops[CP_MAX_DIMS][CP_MAX_OPS];
+    const double* coef;       // device, n_terms
+    const int32_t* op_index;  // device, n_terms x d
+    int32_t d, r, n_terms;
+};
+
+}  // namespace cpals

@@ -1,0 +1,169 @@
+// Device helpers for the persistent CP-ALS workgroup: reductions, 1-D operator
+// application, and workgroup-level FP64 contractions.
+#pragma once
+#include <hip/hip_runtime.h>
+#include "cpals_internal.h"
+
+namespace cpals {
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;  // valid in lane 0
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, 64));
+    return v;
+}
+
+// Sum of one value per thread over the workgroup; every thread gets the result.
+// `red` is an LDS array of at least NWAVES doubles.  Fixed reduction tree (deterministic).
+__device__ __forceinline__ double wg_sum(double v, double* red) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    v = wave_sum(v);
+    __syncthreads();
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < NWAVES; ++i) s += red[i];
+    return s;
+}
+
+// Two sums at once.
+__device__ __forceinline__ void wg_sum2(double& a, double& b, double* red) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    a = wave_sum(a);
+    b = wave_sum(b);
+    __syncthreads();
+    if (lane == 0) { red[wave] = a; red[NWAVES + wave] = b; }
+    __syncthreads();
+    double s = 0.0, t = 0.0;
+#pragma unroll
+    for (int i = 0; i < NWAVES; ++i) { s += red[i]; t += red[NWAVES + i]; }
+    a = s;
+    b = t;
+}
+
+// out[l] = sum_i a[i] * B[i + l*ldb], l < ncol (one wave per column, rows strided by lane).
+// Result in LDS `out`.  Ends with a barrier.
+__device__ void wg_coldots(int n, int ncol, const double* a, const double* B, int ldb, double* out) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int l = wave; l < ncol; l += NWAVES) {
+        double s = 0.0;
+        for (int i = lane; i < n; i += 64) s = fma(a[i], B[i + (int64_t)l * ldb], s);
+        s = wave_sum(s);
+        if (lane == 0) out[l] = s;
+    }
+    __syncthreads();
+}
+
+// y = O x for an n x r panel (column-major, ld = n for both).  For a rank-1 operator
+// O = m w^T, `dots` must hold w^T x[:, l] (computed beforehand).  Grid-stride over the
+// workgroup; no barrier.
+__device__ __forceinline__ void apply_op(const OpDev& op, int n, int r, const double* x, int ldx,
+                                         double* y, int ldy, const double* dots) {
+    const int total = n * r;
+    for (int t = threadIdx.x; t < total; t += WG) {
+        const int i = t % n, l = t / n;
+        const double* xc = x + (int64_t)l * ldx;
+        double v;
+        switch (op.kind) {
+            case CP_OP_IDENTITY: v = xc[i]; break;
+            case CP_OP_DIAG: v = op.data[i] * xc[i]; break;
+            case CP_OP_BAND: {
+                v = 0.0;
+                const int h = op.hbw;
+                for (int j = 0; j <= 2 * h; ++j) {
+                    int c = i + j - h;
+                    c %= n;
+                    if (c < 0) c += n;
+                    v = fma(op.data[j * n + i], xc[c], v);
+                }
+                break;
+            }
+            default: v = op.data[i] * dots[l]; break;  // rank-1: m[i] * (w^T x_l)
+        }
+        y[i + (int64_t)l * ldy] = v;
+    }
+}
+
+// y (+)= O^T z.  For rank-1 O = m w^T, O^T z = w (m^T z): `dots` must hold m^T z[:, l].
+template <bool ACC>
+__device__ __forceinline__ void apply_op_t(const OpDev& op, int n, int r, const double* z, int ldz,
+                                           double* y, int ldy, const double* dots) {
+    const int total = n * r;
+    for (int t = threadIdx.x; t < total; t += WG) {
+        const int i = t % n, l = t / n;
+        const double* zc = z + (int64_t)l * ldz;
+        double v;
+        switch (op.kind) {
+            case CP_OP_IDENTITY: v = zc[i]; break;
+            case CP_OP_DIAG: v = op.data[i] * zc[i]; break;
+            case CP_OP_BAND: {
+                // (O^T z)[i] = sum_j O[k, i] z[k] with k = i - j + h (mod n), O[k, i] = data[j][k]
+                v = 0.0;
+                const int h = op.hbw;
+                for (int j = 0; j <= 2 * h; ++j) {
+                    int k = i - j + h;
+                    k %= n;
+                    if (k < 0) k += n;
+                    v = fma(op.data[j * n + k], zc[k], v);
+                }
+                break;
+            }
+            default: v = op.data[n + i] * dots[l]; break;  // rank-1 transpose: w[i] * (m^T z_l)
+        }
+        double* yp = y + i + (int64_t)l * ldy;
+        if (ACC) *yp += v; else *yp = v;
+    }
+}
+
+// C (M x N) = alpha * op(A) * op(B) + beta * C, column-major, all in global memory.
+// op(A)(i,k) = TA ? A[k + i*lda] : A[i + k*lda];  op(B)(k,j) = TB ? B[j + k*ldb] : B[k + j*ldb].
+// Register micro-tiles of 4 x 4 per thread.  No barrier.
+template <bool TA, bool TB>
+__device__ void wg_gemm(int M, int N, int K, double alpha, const double* __restrict__ A, int lda,
+                        const double* __restrict__ B, int ldb, double beta, double* __restrict__ C, int ldc) {
+    constexpr int TM = 4, TN = 4;
+    const int mt = (M + TM - 1) / TM, nt = (N + TN - 1) / TN;
+    for (int t = threadIdx.x; t < mt * nt; t += WG) {
+        const int i0 = (t % mt) * TM, j0 = (t / mt) * TN;
+        double acc[TM][TN];
+#pragma unroll
+        for (int a = 0; a < TM; ++a)
+#pragma unroll
+            for (int b = 0; b < TN; ++b) acc[a][b] = 0.0;
+        for (int k = 0; k < K; ++k) {
+            double av[TM], bv[TN];
+#pragma unroll
+            for (int a = 0; a < TM; ++a) {
+                const int i = i0 + a;
+                av[a] = (i < M) ? (TA ? A[k + (int64_t)i * lda] : A[i + (int64_t)k * lda]) : 0.0;
+            }
+#pragma unroll
+            for (int b = 0; b < TN; ++b) {
+                const int j = j0 + b;
+                bv[b] = (j < N) ? (TB ? B[j + (int64_t)k * ldb] : B[k + (int64_t)j * ldb]) : 0.0;
+            }
+#pragma unroll
+            for (int a = 0; a < TM; ++a)
+#pragma unroll
+                for (int b = 0; b < TN; ++b) acc[a][b] = fma(av[a], bv[b], acc[a][b]);
+        }
+#pragma unroll
+        for (int a = 0; a < TM; ++a)
+#pragma unroll
+            for (int b = 0; b < TN; ++b) {
+                const int i = i0 + a, j = j0 + b;
+                if (i < M && j < N) {
+                    double* cp = C + i + (int64_t)j * ldc;
+                    *cp = (beta == 0.0) ? alpha * acc[a][b] : fma(beta, *cp, alpha * acc[a][b]);
+                }
+            }
+    }
+}
+
+}  // namespace cpals

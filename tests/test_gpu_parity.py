@@ -1,0 +1,230 @@
+"""GPU parity: every entry point of libcpals, called through the C ABI, against the FP64 oracle
+on the same seeded inputs.  FP64 bar: 1e-10 relative L2 on the represented tensor."""
+import numpy as np
+import pytest
+
+from gpu_util import dev, host, log, rel_panels, tensor_distance
+from oracle import cpals_oracle as O
+from paper_1803_10270_amd import binding as B
+from paper_1803_10270_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def handle():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    h = B.Handle()
+    yield h
+    h.close()
+
+
+def mixed_operator(rng, dims, n_terms, with_rank1=True, scale=0.3):
+    ops = []
+    for n in dims:
+        o = [W.op_identity(n), W.op_central_diff(n), W.op_diag(rng.uniform(-1, 1, n))]
+        if with_rank1:
+            o.append(W.op_rank1(rng.uniform(0, 1, n), rng.uniform(0, 1, n) / n))
+        ops.append(o)
+    idx = rng.integers(0, len(ops[0]), size=(n_terms, len(dims))).astype(np.int32)
+    idx[0, :] = 0
+    coef = np.concatenate([[1.0], scale * rng.uniform(-1, 1, n_terms - 1)])
+    return W.SepOperator(coef, idx, ops)
+
+
+# ------------------------------------------------------------------ inner / norm / apply
+
+@pytest.mark.parametrize("dims,rx,ry", [([5, 300, 1000], 3, 7), ([256] * 6, 32, 32), ([1], 1, 1),
+                                        ([513, 64], 64, 17)])
+def test_inner_and_norm(handle, dims, rx, ry):
+    import torch
+    log("inner", dims, rx, ry)
+    rng = np.random.default_rng(sum(dims) + rx)
+    X = W.random_factors(rng, dims, rx)
+    Y = W.random_factors(rng, dims, ry)
+    out = torch.zeros(2, dtype=torch.float64, device="cuda")
+    B.cp_inner(handle, dev(X), dev(Y), out[0:1])
+    B.cp_norm(handle, dev(X), out[1:2])
+    got = out.cpu().numpy()
+    ref_i, ref_n = O.cp_inner(X, Y), O.cp_norm(X)
+    scale = O.cp_norm(X) * O.cp_norm(Y)
+    assert abs(got[0] - ref_i) <= 1e-12 * scale
+    assert abs(got[1] - ref_n) <= 1e-12 * ref_n
+
+
+@pytest.mark.parametrize("dims,r,T", [([7, 64, 300], 3, 5), ([256] * 6, 8, 13), ([2, 3], 1, 2)])
+def test_apply_operator(handle, dims, r, T):
+    import torch
+    log("apply", dims, r, T)
+    rng = np.random.default_rng(100 + r + T)
+    L = mixed_operator(rng, dims, T)
+    X = W.random_factors(rng, dims, r)
+    Yd = [torch.zeros((T * r, n), dtype=torch.float64, device="cuda") for n in dims]
+    B.cp_apply_operator(handle, L, dev(X), Yd)
+    ref = O.cp_apply_operator(L, X)
+    for y, yr in zip(host(Yd), ref):
+        assert np.abs(y - yr).max() <= 1e-13 * max(1.0, np.abs(yr).max())
+
+
+# ------------------------------------------------------------------------ ALS steps
+
+def run_gpu_step(handle, A, Bop, V, guess, **opts):
+    Vd, Gd = dev(V), dev(guess)
+    rep = B.cp_als_step(handle, A, Bop, Vd, Gd, B.default_opts(**opts))
+    return host(Gd), rep
+
+
+def test_step_mixed_operators_fixed_sweeps(handle):
+    """Band, diagonal and rank-1 factors on both sides, B with several terms, r0 != r."""
+    log("step mixed")
+    rng = np.random.default_rng(7)
+    dims = [12, 10, 9]
+    A = mixed_operator(rng, dims, 5)
+    Bop = mixed_operator(rng, dims, 3)
+    V = W.random_factors(rng, dims, 3)
+    guess = W.random_factors(rng, dims, 4)
+    Ug, rep = run_gpu_step(handle, A, Bop, V, guess, tol=0.0, max_sweeps=5)
+    Uo, ro = O.als_step(A, Bop, V, guess, tol=0.0, max_sweeps=5)
+    assert rep["sweeps"] == ro["sweeps"] == 5
+    assert tensor_distance(Ug, Uo) <= TOL
+    assert rel_panels(Ug, Uo) <= 1e-8
+    assert abs(rep["eps_conv"] - ro["eps_conv"]) <= 1e-6 * ro["eps_conv"]
+
+
+def test_step_advection_cn_converges_like_oracle(handle):
+    """Constant-velocity CN advection (d = 6, n = 32, rank 4 from a rank-2 start): same sweep
+    count at the same tolerance and the same tensor."""
+    log("step cn advection")
+    p = W.advection_cn_constant(seed=0, d=6, n=32, cap=4)
+    Ug, rep = run_gpu_step(handle, p.A, p.B, p.f0, p.guess, tol=1e-9, max_sweeps=60)
+    Uo, ro = O.als_step(p.A, p.B, p.f0, p.guess, tol=1e-9, max_sweeps=60)
+    log("gpu", rep, "oracle", ro["sweeps"], ro["eps_conv"])
+    assert rep["sweeps"] == ro["sweeps"]
+    assert tensor_distance(Ug, Uo) <= TOL
+
+
+def test_run_three_steps_matches_oracle(handle):
+    """Device-resident time loop (three implicit-Euler steps of the variable-coefficient
+    operator, d = 4, n = 24, rank 6 from rank 2) against the oracle's time loop, and the
+    per-step trajectory buffer against the final state."""
+    import torch
+    log("run 3 steps")
+    p = W.advection_ie_variable(seed=3, d=4, n=24, dt=1e-2, ic_rank=2, cap=6, n_steps=3)
+    Vd, Gd = dev(p.f0), dev(p.guess)
+    total = sum(u.shape[0] * 6 for u in p.guess)
+    traj = torch.zeros(3 * total, dtype=torch.float64, device="cuda")
+    reps = B.cp_als_run(handle, p.A, p.B, Vd, Gd, 3, B.default_opts(tol=0.0, max_sweeps=4), traj=traj)
+    traj_o, reps_o = O.run(p, 3, max_sweeps=4, tol=0.0)
+    assert [r["sweeps"] for r in reps] == [4, 4, 4]
+    Ug = host(Gd)
+    assert tensor_distance(Ug, traj_o[-1]) <= TOL
+    t = traj.cpu().numpy()
+    off = 2 * total
+    last = []
+    for u in p.guess:
+        n = u.shape[0]
+        last.append(t[off:off + n * 6].reshape(6, n).T)
+        off += n * 6
+    assert all(np.array_equal(a, b) for a, b in zip(last, Ug))
+    off = 0
+    first = []
+    for u in p.guess:
+        n = u.shape[0]
+        first.append(t[off:off + n * 6].reshape(6, n).T)
+        off += n * 6
+    assert tensor_distance(first, traj_o[0]) <= TOL
+
+
+@pytest.mark.parametrize("sweeps", [1, 2])
+def test_full_size_variable_advection(handle, sweeps):
+    """The d = 6, n = 256, r = 32 implicit-Euler step with 13 Kronecker terms, from the padded
+    rank-32 guess, in the launch configuration the benchmark times: fixed sweep counts
+    against the oracle."""
+    log("full size", sweeps)
+    p = W.advection_ie_variable(seed=0)
+    Ug, rep = run_gpu_step(handle, p.A, p.B, p.f0, p.guess, tol=0.0, max_sweeps=sweeps)
+    Uo, ro = O.als_step(p.A, p.B, p.f0, p.guess, tol=0.0, max_sweeps=sweeps)
+    d = tensor_distance(Ug, Uo)
+    log("distance", d, rep, ro["eps_conv"])
+    assert d <= TOL
+    assert abs(rep["eps_conv"] - ro["eps_conv"]) <= 1e-6 * ro["eps_conv"]
+
+
+def test_truncate(handle):
+    log("truncate")
+    rng = np.random.default_rng(12)
+    dims = [20, 17, 33, 8]
+    G = W.random_factors(rng, dims, 6)
+    F0 = W.random_factors(rng, dims, 3)
+    Gd, Fd = dev(G), dev(F0)
+    rep = B.cp_truncate(handle, Gd, Fd, B.default_opts(tol=0.0, max_sweeps=8))
+    Fo, ro = O.truncate(G, F0, tol=0.0, max_sweeps=8)
+    assert rep["sweeps"] == 8
+    assert tensor_distance(host(Fd), Fo) <= TOL
+
+
+def test_kinetic_rank1_projector(handle):
+    """Kinetic model with the rank-1 Maxwellian projector in the velocity dimensions."""
+    log("kinetic")
+    p = W.kinetic_cn(seed=2, n=16, field_rank=2, cap=5)
+    Ug, rep = run_gpu_step(handle, p.A, p.B, p.f0, p.guess, tol=0.0, max_sweeps=4)
+    Uo, ro = O.als_step(p.A, p.B, p.f0, p.guess, tol=0.0, max_sweeps=4)
+    assert tensor_distance(Ug, Uo) <= TOL
+
+
+# --------------------------------------------------------------- batched / determinism
+
+def test_batched_matches_single(handle):
+    """Uneven problems in one persistent launch give bitwise the same result as one by one."""
+    log("batched")
+    probs = [W.advection_ie_constant(seed=s, d=d, n=n, cap=c, ic_rank=2, n_steps=2)
+             for s, d, n, c in [(1, 4, 64, 5), (2, 6, 32, 3), (3, 3, 128, 8), (4, 4, 40, 4)]]
+    fi = [dev(p.f0) for p in probs]
+    fo = [dev(p.guess) for p in probs]
+    opts = B.default_opts(tol=1e-8, max_sweeps=30)
+    reps = B.cp_als_run_batched(handle, [p.A for p in probs], [p.B for p in probs], fi, fo, 2, opts)
+    for p, f, rb in zip(probs, fo, reps):
+        g = dev(p.guess)
+        rs = B.cp_als_run(handle, p.A, p.B, dev(p.f0), g, 2, opts)
+        assert [r["sweeps"] for r in rs] == [r["sweeps"] for r in rb]
+        assert all(np.array_equal(a, b) for a, b in zip(host(f), host(g)))
+
+
+def test_deterministic(handle):
+    log("determinism")
+    p = W.advection_ie_variable(seed=1, d=5, n=48, ic_rank=3, cap=7)
+    a, _ = run_gpu_step(handle, p.A, p.B, p.f0, p.guess, tol=0.0, max_sweeps=3)
+    b, _ = run_gpu_step(handle, p.A, p.B, p.f0, p.guess, tol=0.0, max_sweeps=3)
+    assert all(np.array_equal(x, y) for x, y in zip(a, b))
+
+
+# ------------------------------------------------------------------------ error paths
+
+def test_argument_errors(handle):
+    import torch
+    log("errors")
+    p = W.advection_ie_variable(seed=0, d=3, n=16, ic_rank=2, cap=3)
+    with pytest.raises(B.CpalsError) as e:   # rank above the limit
+        big = [torch.zeros((65, 16), dtype=torch.float64, device="cuda") for _ in range(3)]
+        B.cp_als_step(handle, p.A, p.B, dev(p.f0), big)
+    assert e.value.status == B.CP_ERR_SHAPE
+    with pytest.raises(B.CpalsError) as e:   # mismatched grid size
+        wrong = dev([np.ones((17, 3))] * 3)
+        B.cp_als_step(handle, p.A, p.B, dev(p.f0), wrong)
+    assert e.value.status == B.CP_ERR_SHAPE
+    with pytest.raises(B.CpalsError) as e:   # bad options
+        B.cp_als_step(handle, p.A, p.B, dev(p.f0), dev(p.guess), B.default_opts(max_sweeps=0))
+    assert e.value.status == B.CP_ERR_INVALID_ARG
+    with pytest.raises(B.CpalsError) as e:   # apply with a wrong output rank
+        B.cp_apply_operator(handle, p.A, dev(p.f0), dev([np.zeros((16, 5))] * 3))
+    assert e.value.status == B.CP_ERR_SHAPE
+
+
+def test_not_converged_flag(handle):
+    log("not converged")
+    p = W.advection_ie_variable(seed=0, d=3, n=16, ic_rank=2, cap=3)
+    _, rep = run_gpu_step(handle, p.A, p.B, p.f0, p.guess, tol=1e-30, max_sweeps=2)
+    assert rep["sweeps"] == 2 and rep["flags"] & B.FLAG_NOT_CONVERGED

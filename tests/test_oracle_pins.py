@@ -118,7 +118,7 @@ def test_step_d1_is_banded_solve():
     """d = 1, r = 1: the step is the textbook 1-D periodic Crank-Nicolson solve
     u = A^{-1} B v (eq. (CNFDE))."""
     p = W.advection_cn_constant(seed=3, d=1, n=64, dt=0.05, ic_rank=1, cap=1)
-    U, rep = O.als_step(p.A, p.B, p.f0, p.guess, tol=1e-14, max_sweeps=5)
+    U, rep = O.als_step(p.A, p.B, p.f0, p.guess, tol=1e-14, max_sweeps=5, eps_reg=0.0)
     Ad, Bd = full_operator(p.A), full_operator(p.B)
     ref = np.linalg.solve(Ad, Bd @ p.f0[0][:, 0])
     assert rel(U[0][:, 0], ref) <= 1e-12
@@ -146,7 +146,7 @@ def test_single_direction_advection_preserves_rank():
     the rank is preserved exactly."""
     p = W.advection_cn_constant(seed=5, d=4, n=16, dt=0.05, ic_rank=2, cap=2,
                                 velocity=np.array([0.8, 0.0, 0.0, 0.0]))
-    U, rep = O.als_step(p.A, p.B, p.f0, p.guess, tol=1e-13, max_sweeps=100)
+    U, rep = O.als_step(p.A, p.B, p.f0, p.guess, tol=1e-13, max_sweeps=100, eps_reg=0.0)
     n = 16
     D = dense_op(W.op_central_diff(n))
     th = 0.5 * 0.05 * 0.8
@@ -179,7 +179,7 @@ def test_cn_steps_track_fft_evolution_and_conserve_mass_and_norm():
     error, conserves mass (1^T D = 0) and the L2 norm (D skew, so CN is unitary) up to
     the ALS residual."""
     p = W.advection_cn_constant(seed=6, d=3, n=16, dt=0.02, ic_rank=2, cap=3, n_steps=5)
-    traj, reps = O.run(p, 5, max_sweeps=300)
+    traj, reps = O.run(p, 5, max_sweeps=300, eps_reg=0.0)
     f0 = cp_full(p.f0)
     ref = fft_cn_evolution(f0, p.meta["velocity"], 0.02, 5)
     assert np.allclose(ref, full_step_n(p, f0, 5), atol=1e-12)
@@ -263,7 +263,7 @@ def test_kinetic_maxwellian_is_fixed_point():
     m = p.meta["maxwellian"]
     n = m.shape[0]
     f = [np.ones((n, 1)) for _ in range(3)] + [m[:, None].copy() for _ in range(3)]
-    U, rep = O.als_step(p.A, p.B, f, f, tol=1e-13, max_sweeps=5)
+    U, rep = O.als_step(p.A, p.B, f, f, tol=1e-13, max_sweeps=5, eps_reg=0.0)
     assert rel(cp_full(U), cp_full(f)) <= 1e-12
     assert rep["sweeps"] == 1
 
@@ -281,7 +281,9 @@ def test_kinetic_relaxation_rate(n):
     eps = 0.2
     f = [np.ones((n, 2)) for _ in range(3)] + [np.stack([m, m], 1) for _ in range(3)]
     f[3][:, 1] = m * g1 * eps
-    U, rep = O.als_step(p.A, p.B, f, f, tol=1e-14, max_sweeps=50)
+    # the two columns coincide in five dimensions, so the factor problem is singular (the
+    # tensor is not): a tiny shift picks the minimum-norm factors
+    U, rep = O.als_step(p.A, p.B, f, f, tol=1e-14, max_sweeps=50, eps_reg=1e-14)
     fac = (1 - 0.5 * nu * dt) / (1 + 0.5 * nu * dt)
     ref = [u.copy() for u in f]
     ref[3][:, 1] *= fac
@@ -295,7 +297,7 @@ def test_kinetic_mass_conservation():
     """Transport and Maxwellian relaxation both conserve mass: the full-grid CN step
     conserves it exactly and CP-ALS up to its residual."""
     p = W.kinetic_cn(seed=1, n=4, dt=0.05, field_rank=2, cap=4, n_steps=1)
-    U, rep = O.als_step(p.A, p.B, p.f0, p.guess, tol=1e-12, max_sweeps=300)
+    U, rep = O.als_step(p.A, p.B, p.f0, p.guess, tol=1e-12, max_sweeps=300, eps_reg=0.0)
     hx = 2 * np.pi / 4
     w = p.meta["w"]
     def mass(f):
