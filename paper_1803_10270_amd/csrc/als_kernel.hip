@@ -18,27 +18,119 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include "device_common.h"
+#include "mfma_f64.h"
 
 namespace cpals {
+
+constexpr int SCRATCH = 15616;   // doubles of LDS shared by the phases of one dimension update
+constexpr int LDS_PAIRS = 384;   // pair records of one dimension kept in LDS during assembly
+constexpr int MAX_ITEMS = 48;    // work items of one Hadamard pass
+
+struct StageSlot {               // one staged Gram block of the assembly
+    int64_t base;                // element offset of entry (0, 0) of the block
+    int32_t ld;                  // its leading dimension, 0 for an empty slot
+    int32_t pad;
+};
+
+struct Smem;
+extern __shared__ __attribute__((aligned(16))) unsigned char cpals_smem[];
 
 struct Smem {
     Problem pb;
     double red[2 * NWAVES];
-    double dots[CP_MAX_OPS * CP_MAX_RANK];
-    double chol[CP_MAX_RANK * CP_MAX_RANK];
-    double linv[CP_MAX_RANK * CP_MAX_RANK];
+    double dots[CP_MAX_OPS * CP_MAX_OPS * CP_MAX_RANK];
     double colnorm[CP_MAX_DIMS * CP_MAX_RANK];
-    double scal[8];
+    double scratch[SCRATCH];
+    PairRec pairs[LDS_PAIRS];
+    StageSlot slots[(CP_MAX_DIMS - 1) * CP_MAX_OPS * CP_MAX_OPS];
+    int32_t items[MAX_ITEMS][3];
+    int32_t blk_item[CP_MAX_OPS * CP_MAX_OPS + 1];
     int32_t iscal[8];
 };
+
+// The workgroup's LDS state, reached through the LDS symbol itself so that every access
+// compiles to LDS instructions, also inside non-inlined functions.
+#define SMEM (*reinterpret_cast<Smem*>(cpals_smem))
+
+
+// Row index i + o of a periodic grid of n points, for |o| small (one or two wraps).
+__device__ __forceinline__ int wrap_idx(int i, int n) {
+    if (i < 0) {
+        i += n;
+        while (i < 0) i += n;
+    } else if (i >= n) {
+        i -= n;
+        while (i >= n) i -= n;
+    }
+    return i;
+}
+
+// Value of (O x)[i] for one 1-D operator and one column x (ld irrelevant).  For a rank-1
+// operator O = m w^T, `dot` must hold w^T x.
+// x is a column in device memory.
+__device__ __forceinline__ double op_value(const OpDev& op, int n, int i, const double* x, double dot) {
+    switch (op.kind) {
+        case CP_OP_IDENTITY: return ldg(x + i);
+        case CP_OP_DIAG: return ldg(op.data + i) * ldg(x + i);
+        case CP_OP_BAND: {
+            double v = 0.0;
+            const int h = op.hbw;
+            for (int j = 0; j <= 2 * h; ++j) v = fma(ldg(op.data + j * n + i), ldg(x + wrap_idx(i + j - h, n)), v);
+            return v;
+        }
+        default: return ldg(op.data + i) * dot;
+    }
+}
+
+// Element (i, c) of the stacked applied panel [O^0 X, O^1 X, ...] (column c = a*r + l).
+// For a rank-1 operator O^a = m w^T, dots[a*r + l] must hold w^T X[:, l].
+struct OpApplyF {
+    const OpDev* ops;
+    int n, r;
+    const double* X;
+    const double* dots;
+    __device__ __forceinline__ double operator()(int i, int c) const {
+        // c / r through a float reciprocal (exact for c < 2^16, r <= 64)
+        const int a = (int)(((float)c + 0.5f) * __frcp_rn((float)r));
+        const int l = c - a * r;
+        return op_value(ops[a], n, i, X + (int64_t)l * n, dots[a * r + l]);
+    }
+};
+
+// Plain column-major panel element (i, c).
+struct ColF {
+    const double* X;
+    int ld;
+    __device__ __forceinline__ double operator()(int i, int c) const { return ldg(X + i + (int64_t)c * ld); }
+};
+
+// x - u elementwise (the increment of one factor).
+struct DiffF {
+    const double* x;
+    const double* u;
+    int ld;
+    __device__ __forceinline__ double operator()(int i, int c) const {
+        const int64_t o = i + (int64_t)c * ld;
+        return ldg(x + o) - ldg(u + o);
+    }
+};
+
+// w^T X[:, l] for every rank-1 operator among ops[0..m) -> s.dots[a*r + l].  Uniform; ends
+// with a barrier when there is any rank-1 operator.
+__device__ void rank1_dots_fwd(const OpDev* ops, int m, int n, int r, const double* X) {
+    Smem& s = SMEM;
+    for (int a = 0; a < m; ++a)
+        if (ops[a].kind == CP_OP_RANK1) wg_coldots(n, r, ops[a].data + n, X, n, s.dots + a * r);
+}
 
 // ------------------------------------------------------------------------------------
 // applied panels
 // ------------------------------------------------------------------------------------
 
 // out[:, a*r:(a+1)*r] = O^a in (n x r panel, ld ldin), for the m operators ops[0..m).
-__device__ void apply_ops_fwd(Smem& s, const OpDev* ops, int m, int n, int r, const double* in, int ldin,
+__device__ void apply_ops_fwd(const OpDev* ops, int m, int n, int r, const double* in, int ldin,
                               double* out) {
+    Smem& s = SMEM;
     bool any_rank1 = false;
     for (int a = 0; a < m; ++a) any_rank1 |= (ops[a].kind == CP_OP_RANK1);
     if (any_rank1) {
@@ -50,8 +142,9 @@ __device__ void apply_ops_fwd(Smem& s, const OpDev* ops, int m, int n, int r, co
 }
 
 // w = sum_a (O^a)^T Z[:, a-block] + lam * p ; returns <p, w> (all threads).
-__device__ double apply_ops_t_sum(Smem& s, const OpDev* ops, int m, int n, int r, const double* Z,
+__device__ double apply_ops_t_sum(const OpDev* ops, int m, int n, int r, const double* Z,
                                   double lam, const double* p, double* w) {
+    Smem& s = SMEM;
     bool any_rank1 = false;
     for (int a = 0; a < m; ++a) any_rank1 |= (ops[a].kind == CP_OP_RANK1);
     if (any_rank1) {
@@ -63,7 +156,7 @@ __device__ double apply_ops_t_sum(Smem& s, const OpDev* ops, int m, int n, int r
     const int total = n * r;
     for (int t = threadIdx.x; t < total; t += WG) {
         const int i = t % n, l = t / n;
-        const double pv = p[t];
+        const double pv = p ? p[t] : 0.0;
         double v = lam * pv;
         for (int a = 0; a < m; ++a) {
             const OpDev& op = ops[a];
@@ -91,205 +184,589 @@ __device__ double apply_ops_t_sum(Smem& s, const OpDev* ops, int m, int n, int r
 }
 
 // ------------------------------------------------------------------------------------
-// Gram refresh of one dimension: P_k = [O^a U_k], G_k = P_k^T P_k, X_k = P_k^T Q_k
+// Gram refresh of one dimension: G_k = P_k^T P_k, X_k = P_k^T Q_k with P_k = [O^a U_k]_a
+// formed row chunk by row chunk in LDS (never stored).
 // ------------------------------------------------------------------------------------
-__device__ void refresh_dim(Smem& s, int k, int r0) {
+__device__ __noinline__ void refresh_dim(int k, int r0) {
+    Smem& s = SMEM;
     const Problem& pb = s.pb;
     const int n = pb.n[k], r = pb.r, m = pb.mA[k], mb = pb.mB[k];
-    apply_ops_fwd(s, pb.opA[k], m, n, r, pb.U + pb.offU[k], n, pb.P);
-    wg_gemm<true, false>(m * r, m * r, n, 1.0, pb.P, n, pb.P, n, 0.0, pb.G + pb.offG[k], m * r);
-    wg_gemm<true, false>(m * r, mb * r0, n, 1.0, pb.P, n, pb.Q + pb.offQ[k], n, 0.0, pb.X + pb.offX[k], m * r);
-    __syncthreads();
+    const double* Uk = pb.U + pb.offU[k];
+    rank1_dots_fwd(pb.opA[k], m, n, r, Uk);
+    OpApplyF fa{pb.opA[k], n, r, Uk, s.dots};
+    ColF fb{pb.Q + pb.offQ[k], n};
+    gram_lds(n, m * r, mb * r0, fa, fb, pb.G + pb.offG[k], m * r, pb.X + pb.offX[k], m * r, s.scratch);
 }
 
-__device__ void compute_Q(Smem& s, int k, int r0) {
+__device__ void compute_Q(int k, int r0) {
+    Smem& s = SMEM;
     const Problem& pb = s.pb;
     const int n = pb.n[k];
-    apply_ops_fwd(s, pb.opB[k], pb.mB[k], n, r0, pb.V + pb.offV[k], n, pb.Q + pb.offQ[k]);
+    apply_ops_fwd(pb.opB[k], pb.mB[k], n, r0, pb.V + pb.offV[k], n, pb.Q + pb.offQ[k]);
 }
 
 // ------------------------------------------------------------------------------------
 // Hadamard assembly for dimension q: C (mA x mA blocks r x r), D (mA x mB blocks r x r0),
 // H0 = o_{k != q} U_k^T U_k.  Returns trace(M_q) (without the shift).
+// The Gram entries of a chunk of matrix positions are staged in LDS once (all dimensions
+// k != q, all operator blocks), then eight lanes share one position and split its pair
+// list; the partial sums meet through lane shuffles.
 // ------------------------------------------------------------------------------------
-__device__ double assemble(Smem& s, int q, int r0) {
+// One Hadamard pass over the r x rc position grid of dimension q:
+//   out[l + (blk rc + lc) r] = sum over the pair records of block blk of
+//                              coef * prod_{j-th dim k != q} src_k[block slot_j][l, lc]
+// (src = G for the C blocks, X for the D blocks).  Per chunk of E positions the entries of
+// every (dimension, operator block) slot are staged in LDS; the pair list is cut into
+// work items of similar length, each wave takes items and sums them for its positions
+// (EPT per lane, identity-block factors held in registers), and a last pass adds the items
+// of a block in a fixed order.  With WITH_H0 also H0 = prod_j src_k[slot 0] and the trace
+// sum_blk trace(C^blk) <O^a, O^b>_F are produced.
+template <bool WITH_H0, int EPT>
+__device__ __noinline__ double hadamard_pass(int q, int rc, int MM, const double* src, int nblk,
+                                const int32_t* off, const PairRec* pairs_g, double* out, const double* trOO) {
+    Smem& s = SMEM;
+    const Problem& pb = s.pb;
+    const int d = pb.d, r = pb.r;
+    const int nk = d - 1;
+    const int nE = r * rc;
+    constexpr int E = 64 * EPT;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double* st = s.scratch;
+    const int p0 = off[0], np = off[nblk] - off[0];
+    __syncthreads();
+    const PairRec* pairs = pairs_g + p0;
+    if (np <= LDS_PAIRS) {
+        for (int t = threadIdx.x; t < np; t += WG) {
+            const double* src_rec = reinterpret_cast<const double*>(pairs_g + p0 + t);
+            double* dst_rec = reinterpret_cast<double*>(s.pairs + t);
+            dst_rec[0] = ldg(src_rec);
+            dst_rec[1] = ldg(src_rec + 1);
+        }
+        pairs = s.pairs;
+    }
+    for (int t = threadIdx.x; t < nk * MM; t += WG) {
+        const int j = t / MM, ab = t % MM;
+        const int k = j < q ? j : j + 1;
+        const int mk = pb.mA[k];
+        const int nb = WITH_H0 ? mk : pb.mB[k];
+        StageSlot sl;
+        sl.pad = 0;
+        if (ab < mk * nb) {
+            const int a = ab % mk, b = ab / mk;
+            sl.ld = mk * r;
+            sl.base = (WITH_H0 ? pb.offG[k] : pb.offX[k]) + (int64_t)(b * rc) * sl.ld + a * r;
+        } else {
+            sl.ld = 0;
+            sl.base = 0;
+        }
+        s.slots[t] = sl;
+    }
+    if (threadIdx.x == 0) {
+        int S = max(1, (np + 2 * NWAVES - 1) / (2 * NWAVES));
+        int cnt;
+        for (;;) {
+            cnt = 0;
+            for (int blk = 0; blk < nblk; ++blk) cnt += max(1, (off[blk + 1] - off[blk] + S - 1) / S);
+            if (cnt <= MAX_ITEMS) break;
+            S *= 2;
+        }
+        cnt = 0;
+        for (int blk = 0; blk < nblk; ++blk) {
+            s.blk_item[blk] = cnt;
+            const int b0 = off[blk] - p0, b1 = off[blk + 1] - p0;
+            int a = b0;
+            do {
+                const int e = min(b1, a + S);
+                s.items[cnt][0] = blk;
+                s.items[cnt][1] = a;
+                s.items[cnt][2] = e;
+                ++cnt;
+                a = e;
+            } while (a < b1);
+        }
+        s.blk_item[nblk] = cnt;
+        s.iscal[1] = cnt;
+    }
+    __syncthreads();
+    const int nitems = s.iscal[1];
+    double* part = st + nk * MM * E;
+    double trpart = 0.0;
+    for (int e0 = 0; e0 < nE; e0 += E) {
+        // stage the slot entries of positions e0 .. e0 + E
+        {
+            const int e = threadIdx.x & (E - 1);
+            const int pos = e0 + e;
+            const bool ok = pos < nE;
+            const int l = ok ? pos % r : 0, lc = ok ? pos / r : 0;
+            for (int sl = threadIdx.x / E; sl < nk * MM; sl += WG / E) {
+                const StageSlot ss = s.slots[sl];
+                st[sl * E + e] = (ok && ss.ld) ? ldg(src + ss.base + (int64_t)lc * ss.ld + l) : 0.0;
+            }
+        }
+        __syncthreads();
+        // identity-block factors of this lane's positions
+        double h0r[CP_MAX_DIMS - 1][EPT];
+#pragma unroll
+        for (int j = 0; j < CP_MAX_DIMS - 1; ++j)
+#pragma unroll
+            for (int u = 0; u < EPT; ++u) h0r[j][u] = (j < nk) ? st[(j * MM) * E + lane + 64 * u] : 1.0;
+        if (WITH_H0 && wave == 0) {
+#pragma unroll
+            for (int u = 0; u < EPT; ++u) {
+                const int pos = e0 + lane + 64 * u;
+                double prod = 1.0;
+#pragma unroll
+                for (int j = 0; j < CP_MAX_DIMS - 1; ++j) prod *= h0r[j][u];
+                if (pos < nE) stg(pb.H0 + pos, prod);
+            }
+        }
+        for (int it = wave; it < nitems; it += NWAVES) {
+            const int i0 = s.items[it][1], i1 = s.items[it][2];
+            double acc[EPT];
+#pragma unroll
+            for (int u = 0; u < EPT; ++u) acc[u] = 0.0;
+            for (int pi = i0; pi < i1; ++pi) {
+                const double coef = pairs[pi].coef;
+                const uint64_t sw = *reinterpret_cast<const uint64_t*>(pairs[pi].slot);
+                double prod[EPT];
+#pragma unroll
+                for (int u = 0; u < EPT; ++u) prod[u] = coef;
+#pragma unroll
+                for (int j = 0; j < CP_MAX_DIMS - 1; ++j) {
+                    if (j < nk) {
+                        const int sj = (int)((sw >> (8 * j)) & 0xffu);
+                        if (sj == 0) {
+#pragma unroll
+                            for (int u = 0; u < EPT; ++u) prod[u] *= h0r[j][u];
+                        } else {
+                            const double* row = st + (j * MM + sj) * E + lane;
+#pragma unroll
+                            for (int u = 0; u < EPT; ++u) prod[u] *= row[64 * u];
+                        }
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < EPT; ++u) acc[u] += prod[u];
+            }
+#pragma unroll
+            for (int u = 0; u < EPT; ++u) part[it * E + lane + 64 * u] = acc[u];
+        }
+        __syncthreads();
+        for (int t = threadIdx.x; t < nblk * E; t += WG) {
+            const int blk = t / E, e = t - blk * E;
+            const int pos = e0 + e;
+            if (pos < nE) {
+                double acc = 0.0;
+                for (int it = s.blk_item[blk]; it < s.blk_item[blk + 1]; ++it) acc += part[it * E + e];
+                const int l = pos % r, lc = pos / r;
+                stg(out + l + (int64_t)(blk * rc + lc) * r, acc);
+                if (WITH_H0 && l == lc) trpart = fma(acc, trOO[blk], trpart);
+            }
+        }
+        __syncthreads();
+    }
+    return trpart;
+}
+
+__device__ double assemble(int q, int r0) {
+    Smem& s = SMEM;
     const Problem& pb = s.pb;
     const int d = pb.d, r = pb.r, mq = pb.mA[q], mbq = pb.mB[q];
-    const int ldC = mq * r;
     double trpart = 0.0;
-    // C blocks
-    const int rr = r * r;
-    const int nC = mq * mq * rr;
-    for (int t = threadIdx.x; t < nC; t += WG) {
-        const int blk = t / rr, e = t % rr;
-        const int l = e % r, lp = e / r;
-        const int a = blk % mq, b = blk / mq;
-        double acc = 0.0;
-        for (int pi = pb.offC[q][blk]; pi < pb.offC[q][blk + 1]; ++pi) {
-            const PairRec& pr = pb.pairsC[pi];
-            double prod = pr.coef;
-            for (int k = 0; k < d; ++k) {
-                if (k == q) continue;
-                const int ld = pb.mA[k] * r;
-                prod *= pb.G[pb.offG[k] + (int64_t)(pr.b[k] * r + lp) * ld + pr.a[k] * r + l];
-            }
-            acc += prod;
+    if (d == 1) {
+        // every Hadamard product over k != q is empty (all ones)
+        for (int t = threadIdx.x; t < mq * mq * r * r; t += WG) {
+            const int blk = t / (r * r), e = t % (r * r);
+            const int l = e % r, lp = e / r;
+            double acc = 0.0;
+            for (int pi = pb.offC[q][blk]; pi < pb.offC[q][blk + 1]; ++pi) acc += pb.pairsC[pi].coef;
+            pb.Cm[l + (int64_t)(blk * r + lp) * r] = acc;
+            if (l == lp) trpart = fma(acc, pb.trOO[q][blk], trpart);
         }
-        pb.Cm[(a * r + l) + (int64_t)(b * r + lp) * ldC] = acc;
-        if (l == lp) trpart = fma(acc, pb.trOO[q][blk], trpart);
-    }
-    // D blocks
-    const int rr0 = r * r0;
-    const int nD = mq * mbq * rr0;
-    for (int t = threadIdx.x; t < nD; t += WG) {
-        const int blk = t / rr0, e = t % rr0;
-        const int l = e % r, l0 = e / r;
-        const int a = blk % mq, b = blk / mq;
-        double acc = 0.0;
-        for (int pi = pb.offD[q][blk]; pi < pb.offD[q][blk + 1]; ++pi) {
-            const PairRec& pr = pb.pairsD[pi];
-            double prod = pr.coef;
-            for (int k = 0; k < d; ++k) {
-                if (k == q) continue;
-                const int ld = pb.mA[k] * r;
-                prod *= pb.X[pb.offX[k] + (int64_t)(pr.b[k] * r0 + l0) * ld + pr.a[k] * r + l];
-            }
-            acc += prod;
+        for (int t = threadIdx.x; t < mq * mbq * r * r0; t += WG) {
+            const int blk = t / (r * r0), e = t % (r * r0);
+            const int l = e % r, l0 = e / r;
+            double acc = 0.0;
+            for (int pi = pb.offD[q][blk]; pi < pb.offD[q][blk + 1]; ++pi) acc += pb.pairsD[pi].coef;
+            pb.Dm[l + (int64_t)(blk * r0 + l0) * r] = acc;
         }
-        pb.Dm[(a * r + l) + (int64_t)(b * r0 + l0) * ldC] = acc;
+        for (int t = threadIdx.x; t < r * r; t += WG) pb.H0[t] = 1.0;
+        return wg_sum(trpart, s.red);
     }
-    // H0
-    for (int t = threadIdx.x; t < rr; t += WG) {
-        const int l = t % r, lp = t / r;
-        double prod = 1.0;
-        for (int k = 0; k < d; ++k) {
-            if (k == q) continue;
-            prod *= pb.G[pb.offG[k] + (int64_t)lp * (pb.mA[k] * r) + l];
-        }
-        pb.H0[t] = prod;
-    }
+    const int nk = d - 1;
+    // positions per chunk: as many as the LDS staging area holds (items need E doubles each)
+    const int MM = pb.MMq[q], MX = pb.MXq[q];
+    if ((nk * MM + MAX_ITEMS) * 256 <= SCRATCH)
+        trpart = hadamard_pass<true, 4>(q, r, MM, pb.G, mq * mq, pb.offC[q], pb.pairsC, pb.Cm, pb.trOO[q]);
+    else if ((nk * MM + MAX_ITEMS) * 128 <= SCRATCH)
+        trpart = hadamard_pass<true, 2>(q, r, MM, pb.G, mq * mq, pb.offC[q], pb.pairsC, pb.Cm, pb.trOO[q]);
+    else
+        trpart = hadamard_pass<true, 1>(q, r, MM, pb.G, mq * mq, pb.offC[q], pb.pairsC, pb.Cm, pb.trOO[q]);
+    if ((nk * MX + MAX_ITEMS) * 256 <= SCRATCH)
+        hadamard_pass<false, 4>(q, r0, MX, pb.X, mq * mbq, pb.offD[q], pb.pairsD, pb.Dm, nullptr);
+    else if ((nk * MX + MAX_ITEMS) * 128 <= SCRATCH)
+        hadamard_pass<false, 2>(q, r0, MX, pb.X, mq * mbq, pb.offD[q], pb.pairsD, pb.Dm, nullptr);
+    else
+        hadamard_pass<false, 1>(q, r0, MX, pb.X, mq * mbq, pb.offD[q], pb.pairsD, pb.Dm, nullptr);
     return wg_sum(trpart, s.red);  // includes the barrier that publishes C, D, H0
 }
 
 // ------------------------------------------------------------------------------------
-// Preconditioner: Hinv = (H0 + lam I)^{-1} via Cholesky in LDS (wave 0).  Returns flags.
+// Preconditioner: Hinv = (H0 + lam I)^{-1} by in-place Gauss-Jordan elimination on the
+// diagonal pivots (H0 + lam I is symmetric positive definite), all positions of the r x r
+// matrix updated in parallel, two barriers per pivot.  Returns flags.
 // ------------------------------------------------------------------------------------
-__device__ uint32_t factor_precond(Smem& s, double lam) {
+__device__ __noinline__ uint32_t factor_precond(double lam) {
+    Smem& s = SMEM;
     const Problem& pb = s.pb;
-    const int r = pb.r;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    double* c = s.chol;
-    double* li = s.linv;
-    for (int t = threadIdx.x; t < r * r; t += WG) {
+    const int r = pb.r, rr = r * r;
+    double* H = s.scratch;
+    for (int t = threadIdx.x; t < rr; t += WG) {
         const int i = t % r, j = t / r;
-        c[t] = pb.H0[t] + ((i == j) ? lam : 0.0);
+        H[t] = ldg(pb.H0 + t) + ((i == j) ? lam : 0.0);
     }
+    double dpart = 0.0;
+    for (int t = threadIdx.x; t < r; t += WG) dpart = fmax(dpart, ldg(pb.H0 + t + t * r) + lam);
+    dpart = wave_max(dpart);
     __syncthreads();
-    if (wave == 0) {
-        double maxdiag = 0.0;
-        for (int j = 0; j < r; ++j) maxdiag = fmax(maxdiag, c[j + j * r]);
-        uint32_t fl = 0;
-        const int i = lane;
-        for (int j = 0; j < r; ++j) {
-            double piv = c[j + j * r];
-            // H0 + lam I is positive definite for lam > 0; a pivot at or below zero can only
-            // come from rounding, and is replaced by the shift itself.
-            if (!(piv > 1e-12 * maxdiag)) fl |= CP_FLAG_REGULARIZED;
-            if (!(piv > 0.0)) piv = (lam > 0.0) ? lam : 1e-300;
-            const double dj = sqrt(piv);
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            if (i > j && i < r) c[i + j * r] /= dj;
-            if (i == j) c[j + j * r] = dj;
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            if (i > j && i < r) {
-                const double lij = c[i + j * r];
-                for (int k = j + 1; k <= i; ++k) c[i + k * r] -= lij * c[k + j * r];
-            }
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-        }
-        // column `lane` of L^{-1} by forward substitution (entries above the diagonal are 0)
-        if (lane < r) {
-            const int j = lane;
-            for (int ii = 0; ii < j; ++ii) li[ii + j * r] = 0.0;
-            li[j + j * r] = 1.0 / c[j + j * r];
-            for (int ii = j + 1; ii < r; ++ii) {
-                double acc = 0.0;
-                for (int k = j; k < ii; ++k) acc = fma(c[ii + k * r], li[k + j * r], acc);
-                li[ii + j * r] = -acc / c[ii + ii * r];
+    if ((threadIdx.x & 63) == 0) s.red[threadIdx.x >> 6] = dpart;
+    __syncthreads();
+    double maxdiag = 0.0;
+    for (int w = 0; w < NWAVES; ++w) maxdiag = fmax(maxdiag, s.red[w]);
+    uint32_t fl = 0;
+    constexpr int PER = (CP_MAX_RANK * CP_MAX_RANK + WG - 1) / WG;
+    for (int p = 0; p < r; ++p) {
+        double piv = H[p + p * r];
+        if (!(piv > 1e-12 * maxdiag)) fl |= CP_FLAG_REGULARIZED;
+        if (!(piv > 0.0)) piv = (lam > 0.0) ? lam : 1e-300;
+        const double ip = 1.0 / piv;
+        double nv[PER];
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int t = threadIdx.x + u * WG;
+            nv[u] = 0.0;
+            if (t < rr) {
+                const int i = t % r, j = t / r;
+                const double hip = H[i + p * r], hpj = H[p + j * r];
+                if (i == p) nv[u] = (j == p) ? ip : hpj * ip;
+                else if (j == p) nv[u] = -hip * ip;
+                else nv[u] = fma(-hip * ip, hpj, H[t]);
             }
         }
-        if (lane == 0) s.iscal[0] = (int32_t)fl;
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int t = threadIdx.x + u * WG;
+            if (t < rr) H[t] = nv[u];
+        }
+        __syncthreads();
+    }
+    // symmetrise (the preconditioner of CG must be symmetric)
+    for (int t = threadIdx.x; t < rr; t += WG) {
+        const int i = t % r, j = t / r;
+        stg(pb.Hinv + t, 0.5 * (H[t] + H[j + i * r]));
     }
     __syncthreads();
-    // Hinv = L^{-T} L^{-1}
-    for (int t = threadIdx.x; t < r * r; t += WG) {
-        const int a = t % r, b = t / r;
-        const int i0 = a > b ? a : b;
-        double acc = 0.0;
-        for (int i = i0; i < r; ++i) acc = fma(li[i + a * r], li[i + b * r], acc);
-        pb.Hinv[t] = acc;
+    return fl;
+}
+
+// Fast composite product for operators that are all band/diagonal/identity with half
+// bandwidth <= 2 (the usual finite-difference case): X is copied to LDS once, and for
+// every chunk of KCH columns of the stacked panel the (at most two) composite operators
+// it touches are staged in LDS as five-tap stencils, so the panel chunk is formed from
+// LDS only (no dependent device-memory loads).  Requires rc >= KCH >= 4.
+template <int SPW, class EP>
+__device__ __noinline__ double comp_gemm_fast(const OpDev* comps, int nblk, int n, int rc, const double* X,
+                                              const double* Kt, int KCH, const EP& ep) {
+    Smem& s = SMEM;
+    const int r = s.pb.r;
+    const int K = nblk * rc;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int kq = lane >> 4, cc = lane & 15;
+    const int tm = (n + 15) >> 4, tn = (r + 15) >> 4;
+    const int nw = tn * 16, ldb = nw + 1, ldw = n + 1;
+    double* Xs = s.scratch;
+    double* Ws = Xs + ((n * rc + 1) & ~1);
+    double* Bs = Ws + ((ldw * KCH + 1) & ~1);
+    double* Ds = Bs + ((ldb * KCH + 1) & ~1);   // two five-tap stencils, 5 n each
+    __syncthreads();
+    for (int t = threadIdx.x; t < n * rc; t += WG) Xs[t] = ldg(X + t);
+    d4 acc[SPW][4];
+#pragma unroll
+    for (int u = 0; u < SPW; ++u)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[u][t] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int kc0 = 0; kc0 < K; kc0 += KCH) {
+        const int blk0 = kc0 / rc;
+        __syncthreads();
+        // stencils of the blocks touched by this chunk
+        for (int t = threadIdx.x; t < 2 * 5 * n; t += WG) {
+            const int which = t / (5 * n), rem = t - which * 5 * n;
+            const int j = rem / n, i = rem - j * n;
+            const int blk = blk0 + which;
+            double v = 0.0;
+            if (blk < nblk) {
+                const OpDev op = comps[blk];
+                if (op.kind == CP_OP_IDENTITY) v = (j == 2) ? 1.0 : 0.0;
+                else if (op.kind == CP_OP_DIAG) v = (j == 2) ? ldg(op.data + i) : 0.0;
+                else {
+                    const int jj = j - 2 + op.hbw;   // tap j sits at offset j - 2
+                    v = (jj >= 0 && jj <= 2 * op.hbw) ? ldg(op.data + jj * n + i) : 0.0;
+                }
+            }
+            Ds[t] = v;
+        }
+        for (int t = threadIdx.x; t < KCH * nw; t += WG) {
+            const int kk = t / nw, j = t - kk * nw;
+            Bs[kk * ldb + j] = (kc0 + kk < K && j < r) ? ldg(Kt + j + (int64_t)(kc0 + kk) * r) : 0.0;
+        }
+        __syncthreads();
+        for (int t = threadIdx.x; t < KCH * n; t += WG) {
+            const int kk = t / n, i = t - kk * n;
+            const int c = kc0 + kk;
+            double v = 0.0;
+            if (c < K) {
+                const int blk = c / rc, l = c - blk * rc;
+                const double* d5 = Ds + (blk - blk0) * 5 * n;
+                const double* x = Xs + l * n;
+#pragma unroll
+                for (int j = 0; j < 5; ++j) {
+                    int ci = i + j - 2;
+                    ci += (ci < 0) ? n : 0;
+                    ci -= (ci >= n) ? n : 0;
+                    v = fma(d5[j * n + i], x[ci], v);
+                }
+            }
+            Ws[kk * ldw + i] = v;
+        }
+        __syncthreads();
+        for (int ks = 0; ks < KCH / 4; ++ks) {
+            const int kr = 4 * ks + kq;
+            double b[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) b[t] = (t < tn) ? Bs[kr * ldb + t * 16 + cc] : 0.0;
+#pragma unroll
+            for (int u = 0; u < SPW; ++u) {
+                const int strip = wave + NWAVES * u;
+                if (strip < tm) {
+                    const int i = strip * 16 + cc;
+                    const double a = (i < n) ? Ws[kr * ldw + i] : 0.0;
+#pragma unroll
+                    for (int t = 0; t < 4; ++t)
+                        if (t < tn) acc[u][t] = mfma_f64(a, b[t], acc[u][t]);
+                }
+            }
+        }
+    }
+    double part = 0.0;
+#pragma unroll
+    for (int u = 0; u < SPW; ++u) {
+        const int strip = wave + NWAVES * u;
+        if (strip < tm) {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                if (t < tn) {
+                    const int col = t * 16 + cc;
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int row = strip * 16 + tile_row(lane, v);
+                        if (row < n && col < r) part += ep(row, col, acc[u][t][v]);
+                    }
+                }
+            }
+        }
     }
     __syncthreads();
-    return (uint32_t)s.iscal[0];
+    return part;
+}
+
+// General composite product (any operator kinds, any sizes that fit): the stacked panel
+// chunk is formed from device memory, column by column.
+template <int SPW, class EP>
+__device__ __noinline__ double comp_gemm_chunked(const OpDev* comps, int n, int rc, const double* X, const double* Kt,
+                                    int K, int KCH, const EP& ep) {
+    Smem& s = SMEM;
+    const int r = s.pb.r;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int kq = lane >> 4, cc = lane & 15;
+    const int tm = (n + 15) >> 4, tn = (r + 15) >> 4;
+    const int nw = tn * 16, ldb = nw + 1, ldw = n + 1;
+    double* Ws = s.scratch;
+    double* Bs = s.scratch + ((ldw * KCH + 1) & ~1);
+    const int tpc = min(WG, ((n + 63) / 64) * 64);   // threads per panel column (multiple of 64)
+    const int cpp = WG / tpc;                          // columns per pass
+    const int my_col = threadIdx.x / tpc, my_row = threadIdx.x - my_col * tpc;
+    const float inv_rc = __frcp_rn((float)rc);
+    d4 acc[SPW][4];
+#pragma unroll
+    for (int u = 0; u < SPW; ++u)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) acc[u][t] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int kc0 = 0; kc0 < K; kc0 += KCH) {
+        __syncthreads();
+        // W chunk: column kk = comp_blk X[:, l] for c = kc0 + kk = blk rc + l (wave-uniform c)
+        if (my_col < cpp) {
+            for (int kk = my_col; kk < KCH; kk += cpp) {
+                const int c = kc0 + kk;
+                double* wcol = Ws + kk * ldw;
+                if (c < K) {
+                    const int blk = (int)(((float)c + 0.5f) * inv_rc);
+                    const int l = c - blk * rc;
+                    const OpDev op = comps[blk];
+                    const double* x = X + (int64_t)l * n;
+                    const double dot = s.dots[blk * rc + l];
+                    for (int i = my_row; i < n; i += tpc) wcol[i] = op_value(op, n, i, x, dot);
+                } else {
+                    for (int i = my_row; i < n; i += tpc) wcol[i] = 0.0;
+                }
+            }
+        }
+        for (int t = threadIdx.x; t < KCH * nw; t += WG) {
+            const int kk = t / nw, j = t - kk * nw;
+            Bs[kk * ldb + j] = (kc0 + kk < K && j < r) ? ldg(Kt + j + (int64_t)(kc0 + kk) * r) : 0.0;
+        }
+        __syncthreads();
+        for (int ks = 0; ks < KCH / 4; ++ks) {
+            const int kr = 4 * ks + kq;
+            double b[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) b[t] = (t < tn) ? Bs[kr * ldb + t * 16 + cc] : 0.0;
+#pragma unroll
+            for (int u = 0; u < SPW; ++u) {
+                const int strip = wave + NWAVES * u;
+                if (strip < tm) {
+                    const int i = strip * 16 + cc;
+                    const double a = (i < n) ? Ws[kr * ldw + i] : 0.0;
+#pragma unroll
+                    for (int t = 0; t < 4; ++t)
+                        if (t < tn) acc[u][t] = mfma_f64(a, b[t], acc[u][t]);
+                }
+            }
+        }
+    }
+    double part = 0.0;
+#pragma unroll
+    for (int u = 0; u < SPW; ++u) {
+        const int strip = wave + NWAVES * u;
+        if (strip < tm) {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                if (t < tn) {
+                    const int col = t * 16 + cc;
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int row = strip * 16 + tile_row(lane, v);
+                        if (row < n && col < r) part += ep(row, col, acc[u][t][v]);
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+    return part;
 }
 
 // ------------------------------------------------------------------------------------
-// (M_q + lam I) p -> w, returns <p, w>
+// Composite product  out = sum_blk comp_blk X (K^blk)^T  on the matrix cores:
+// the stacked panel W[:, blk rc + l] = comp_blk X[:, l] is formed chunk by chunk in LDS
+// (wave-uniform columns), K^blk are the r x rc blocks of Kt (Kt[l + (blk rc + l') r]).
 // ------------------------------------------------------------------------------------
-__device__ double matvec(Smem& s, int q, double lam, const double* p, double* w) {
+template <class EP>
+__device__ double comp_gemm(const OpDev* comps, int nblk, int n, int rc, const double* X,
+                            const double* Kt, const EP& ep) {
+    Smem& s = SMEM;
+    const int r = s.pb.r;
+    const int K = nblk * rc;
+    const int tm = (n + 15) >> 4;
+    {
+        // fast path: five-tap composites, chunks of KCH <= rc columns, everything in LDS
+        bool five = n >= 3 && rc >= 4 && tm <= 4 * NWAVES;
+        for (int b = 0; b < nblk; ++b)
+            five = five && (comps[b].kind == CP_OP_IDENTITY || comps[b].kind == CP_OP_DIAG ||
+                            (comps[b].kind == CP_OP_BAND && comps[b].hbw <= 2));
+        const int KCHf = min(16, rc & ~3);
+        const int ldbf = ((r + 15) >> 4) * 16 + 1;
+        const int need = ((n * rc + 1) & ~1) + (((n + 1) * KCHf + 1) & ~1) + ((ldbf * KCHf + 1) & ~1) + 10 * n;
+        if (five && need <= SCRATCH) {
+            if (tm <= NWAVES) return comp_gemm_fast<1>(comps, nblk, n, rc, X, Kt, KCHf, ep);
+            if (tm <= 2 * NWAVES) return comp_gemm_fast<2>(comps, nblk, n, rc, X, Kt, KCHf, ep);
+            return comp_gemm_fast<4>(comps, nblk, n, rc, X, Kt, KCHf, ep);
+        }
+    }
+    for (int b = 0; b < nblk; ++b)
+        if (comps[b].kind == CP_OP_RANK1) wg_coldots(n, rc, comps[b].data + n, X, n, s.dots + b * rc);
+    const int ldb = ((r + 15) >> 4) * 16 + 1;
+    int KCH = 32;
+    while (KCH >= 4 && (n + 1) * KCH + 2 + KCH * ldb > SCRATCH) KCH >>= 1;
+    if (KCH >= 4 && tm <= 4 * NWAVES) {
+        if (tm <= NWAVES) return comp_gemm_chunked<1>(comps, n, rc, X, Kt, K, KCH, ep);
+        if (tm <= 2 * NWAVES) return comp_gemm_chunked<2>(comps, n, rc, X, Kt, K, KCH, ep);
+        return comp_gemm_chunked<4>(comps, n, rc, X, Kt, K, KCH, ep);
+    }
+    OpApplyF af{comps, n, rc, X, s.dots};
+    return panel_gemm<4, 2>(n, r, K, af, Kt, r, ep, s.scratch);
+}
+
+// w = (M_q + lam I) p written to w; returns <p, w>.
+struct ShiftDotEp {
+    double* w;
+    const double* p;
+    double lam;
+    int ld;
+    __device__ __forceinline__ double operator()(int row, int col, double v) const {
+        const int64_t o = row + (int64_t)col * ld;
+        const double pv = ldg(p + o);
+        const double wv = fma(lam, pv, v);
+        stg(w + o, wv);
+        return pv * wv;
+    }
+};
+
+__device__ __forceinline__ double matvec(int q, double lam, const double* p, double* w) {
+    Smem& s = SMEM;
     const Problem& pb = s.pb;
     const int n = pb.n[q], r = pb.r, m = pb.mA[q];
-    apply_ops_fwd(s, pb.opA[q], m, n, r, p, n, pb.P);
-    // Z[:, a-block] = sum_b T_b (C^{ab})^T  ->  Z = T Cm^T
-    wg_gemm<false, true>(n, m * r, m * r, 1.0, pb.P, n, pb.Cm, m * r, 0.0, pb.Z, n);
-    __syncthreads();
-    return apply_ops_t_sum(s, pb.opA[q], m, n, r, pb.Z, lam, p, w);
+    const double part = comp_gemm(pb.compAA[q], m * m, n, r, p, pb.Cm, ShiftDotEp{w, p, lam, n});
+    return wg_sum(part, s.red);
 }
 
-// z = r Hinv (each grid row multiplied by the symmetric Hinv); returns <r, z>.
-__device__ double precond(Smem& s, int n, const double* rv, double* zv) {
+// z = r Hinv (each grid row times the symmetric Hinv); returns <r, z>.
+struct StoreDotEp {
+    double* z;
+    const double* rv;
+    int ld;
+    __device__ __forceinline__ double operator()(int row, int col, double v) const {
+        const int64_t o = row + (int64_t)col * ld;
+        stg(z + o, v);
+        return ldg(rv + o) * v;
+    }
+};
+
+__device__ __noinline__ double precond(int n, const double* rv, double* zv) {
+    Smem& s = SMEM;
     const Problem& pb = s.pb;
     const int r = pb.r;
-    wg_gemm<false, false>(n, r, r, 1.0, rv, n, pb.Hinv, r, 0.0, zv, n);
-    __syncthreads();
-    double part = 0.0;
-    for (int t = threadIdx.x; t < n * r; t += WG) part = fma(rv[t], zv[t], part);
+    const double part = panel_gemm<4, 2>(n, r, r, PanelA{rv, n}, pb.Hinv, r, StoreDotEp{zv, rv, n}, s.scratch);
     return wg_sum(part, s.red);
 }
 
 // ------------------------------------------------------------------------------------
 // one dimension update; returns ||Delta f_q||^2 and accumulates pcg iterations / flags
 // ------------------------------------------------------------------------------------
-__device__ double update_dim(Smem& s, int q, int r0, int& pcg_iters, uint32_t& flags) {
+__device__ double update_dim(int q, int r0, int& pcg_iters, uint32_t& flags) {
+    Smem& s = SMEM;
     const Problem& pb = s.pb;
     const int n = pb.n[q], r = pb.r, m = pb.mA[q], mb = pb.mB[q];
     const int nr = n * r;
     double* Uq = pb.U + pb.offU[q];
 
-    const double trM = assemble(s, q, r0);
+    const double trM = assemble(q, r0);
     const double lam = pb.eps_reg * trM / (double)nr;
 
-    // right-hand side b = sum_a (O^a)^T [Q_q D^T]_a
-    wg_gemm<false, true>(n, m * r, mb * r0, 1.0, pb.Q + pb.offQ[q], n, pb.Dm, m * r, 0.0, pb.Z, n);
-    __syncthreads();
-    {
-        bool any_rank1 = false;
-        for (int a = 0; a < m; ++a) any_rank1 |= (pb.opA[q][a].kind == CP_OP_RANK1);
-        if (any_rank1)
-            for (int a = 0; a < m; ++a)
-                if (pb.opA[q][a].kind == CP_OP_RANK1)
-                    wg_coldots(n, r, pb.opA[q][a].data, pb.Z + (int64_t)a * r * n, n, s.dots + a * r);
-        for (int a = 0; a < m; ++a) {
-            if (a == 0) apply_op_t<false>(pb.opA[q][a], n, r, pb.Z, n, pb.vb, n, s.dots + a * r);
-            else apply_op_t<true>(pb.opA[q][a], n, r, pb.Z + (int64_t)a * r * n, n, pb.vb, n, s.dots + a * r);
-        }
-        __syncthreads();
-    }
+    // right-hand side b = sum_{a,b'} (O_A^a)^T O_B^b' V_q (D^{a b'})^T
+    comp_gemm(pb.compAB[q], m * mb, n, r0, pb.V + pb.offV[q], pb.Dm, StoreEp{pb.vb, n});
 
-    flags |= factor_precond(s, lam);
+    flags |= factor_precond(lam);
 
     // PCG from the current factor
     double* x = pb.vx;
@@ -297,34 +774,34 @@ __device__ double update_dim(Smem& s, int q, int r0, int& pcg_iters, uint32_t& f
     double* z = pb.vz;
     double* p = pb.vp;
     double* w = pb.vw;
-    for (int t = threadIdx.x; t < nr; t += WG) x[t] = Uq[t];
+    for (int t = threadIdx.x; t < nr; t += WG) stg(x + t, ldg(Uq + t));
     __syncthreads();
     // Stopping test in the preconditioned (energy-like) norm: r^T P^{-1} r <= tol^2 b^T P^{-1} b.
     // Since P ~ J_q^T J_q, this bounds the change of the represented tensor, also along
     // near-singular directions of H_q where the plain residual norm says little.
-    const double bz = precond(s, n, pb.vb, z);
-    matvec(s, q, lam, x, w);
-    for (int t = threadIdx.x; t < nr; t += WG) rv[t] = pb.vb[t] - w[t];
+    const double bz = precond(n, pb.vb, z);
+    matvec(q, lam, x, w);
+    for (int t = threadIdx.x; t < nr; t += WG) stg(rv + t, ldg(pb.vb + t) - ldg(w + t));
     __syncthreads();
-    double rz = precond(s, n, rv, z);
+    double rz = precond(n, rv, z);
     const double stop = pb.pcg_tol * pb.pcg_tol * bz;
     int it = 0;
     if (rz > stop) {
-        for (int t = threadIdx.x; t < nr; t += WG) p[t] = z[t];
+        for (int t = threadIdx.x; t < nr; t += WG) stg(p + t, ldg(z + t));
         __syncthreads();
         for (it = 1; it <= pb.pcg_max; ++it) {
-            const double pw = matvec(s, q, lam, p, w);
+            const double pw = matvec(q, lam, p, w);
             const double alpha = rz / pw;
             for (int t = threadIdx.x; t < nr; t += WG) {
-                x[t] = fma(alpha, p[t], x[t]);
-                rv[t] = fma(-alpha, w[t], rv[t]);
+                stg(x + t, fma(alpha, ldg(p + t), ldg(x + t)));
+                stg(rv + t, fma(-alpha, ldg(w + t), ldg(rv + t)));
             }
             __syncthreads();
-            const double rzn = precond(s, n, rv, z);
+            const double rzn = precond(n, rv, z);
             if (rzn <= stop || !(pw > 0.0)) break;
             const double beta = rzn / rz;
             rz = rzn;
-            for (int t = threadIdx.x; t < nr; t += WG) p[t] = fma(beta, p[t], z[t]);
+            for (int t = threadIdx.x; t < nr; t += WG) stg(p + t, fma(beta, ldg(p + t), ldg(z + t)));
             __syncthreads();
         }
         if (it > pb.pcg_max) {
@@ -335,15 +812,13 @@ __device__ double update_dim(Smem& s, int q, int r0, int& pcg_iters, uint32_t& f
     pcg_iters += it;
 
     // ||Delta f_q||^2 = sum((dU^T dU) o H0), dU = x - U_q; then U_q <- x
-    for (int t = threadIdx.x; t < nr; t += WG) w[t] = x[t] - Uq[t];
-    __syncthreads();
-    wg_gemm<true, false>(r, r, n, 1.0, w, n, w, n, 0.0, pb.S, r);
-    for (int t = threadIdx.x; t < nr; t += WG) Uq[t] = x[t];
+    gram_lds(n, r, 0, DiffF{x, Uq, n}, DiffF{x, Uq, n}, pb.S, r, nullptr, 0, s.scratch);
+    for (int t = threadIdx.x; t < nr; t += WG) stg(Uq + t, ldg(x + t));
     __syncthreads();
     double part = 0.0;
     for (int t = threadIdx.x; t < r * r; t += WG) part = fma(pb.S[t], pb.H0[t], part);
     const double delta2 = wg_sum(part, s.red);
-    refresh_dim(s, q, r0);
+    refresh_dim(q, r0);
     return delta2;
 }
 
@@ -352,7 +827,8 @@ __device__ double update_dim(Smem& s, int q, int r0, int& pcg_iters, uint32_t& f
 // ------------------------------------------------------------------------------------
 
 // Column norms from the panels themselves -> s.colnorm[k*r + l]
-__device__ void panel_colnorms(Smem& s) {
+__device__ void panel_colnorms() {
+    Smem& s = SMEM;
     const Problem& pb = s.pb;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int r = pb.r;
@@ -368,7 +844,8 @@ __device__ void panel_colnorms(Smem& s) {
 }
 
 // Column norms from the Gram diagonals G_k[0,0][l,l].
-__device__ void gram_colnorms(Smem& s) {
+__device__ void gram_colnorms() {
+    Smem& s = SMEM;
     const Problem& pb = s.pb;
     const int r = pb.r;
     for (int kl = threadIdx.x; kl < pb.d * r; kl += WG) {
@@ -380,7 +857,8 @@ __device__ void gram_colnorms(Smem& s) {
 }
 
 // colnorm -> scale factors (in place); a column with a zero factor keeps scale 1.
-__device__ void balance_scales(Smem& s) {
+__device__ void balance_scales() {
+    Smem& s = SMEM;
     const Problem& pb = s.pb;
     const int r = pb.r, d = pb.d;
     for (int l = threadIdx.x; l < r; l += WG) {
@@ -400,7 +878,8 @@ __device__ void balance_scales(Smem& s) {
     __syncthreads();
 }
 
-__device__ void scale_panels(Smem& s) {
+__device__ void scale_panels() {
+    Smem& s = SMEM;
     const Problem& pb = s.pb;
     const int r = pb.r;
     for (int k = 0; k < pb.d; ++k) {
@@ -412,7 +891,8 @@ __device__ void scale_panels(Smem& s) {
 }
 
 // After a sweep: rescale panels and, consistently, the Grams and cross-Grams.
-__device__ void scale_grams(Smem& s, int r0) {
+__device__ void scale_grams(int r0) {
+    Smem& s = SMEM;
     const Problem& pb = s.pb;
     const int r = pb.r;
     for (int k = 0; k < pb.d; ++k) {
@@ -434,8 +914,7 @@ __device__ void scale_grams(Smem& s, int r0) {
 // the persistent kernel
 // ------------------------------------------------------------------------------------
 __global__ void __launch_bounds__(WG) als_persistent(const Problem* __restrict__ problems, int count) {
-    extern __shared__ unsigned char smem_raw[];
-    Smem& s = *reinterpret_cast<Smem*>(smem_raw);
+    Smem& s = SMEM;
     const int pid = blockIdx.x;
     if (pid >= count) return;
     // problem descriptor -> LDS
@@ -460,11 +939,11 @@ __global__ void __launch_bounds__(WG) als_persistent(const Problem* __restrict__
             }
             __syncthreads();
         }
-        for (int k = 0; k < d; ++k) compute_Q(s, k, r0);
-        panel_colnorms(s);
-        balance_scales(s);
-        scale_panels(s);
-        for (int k = 0; k < d; ++k) refresh_dim(s, k, r0);
+        for (int k = 0; k < d; ++k) compute_Q(k, r0);
+        panel_colnorms();
+        balance_scales();
+        scale_panels();
+        for (int k = 0; k < d; ++k) refresh_dim(k, r0);
 
         int sweeps = 0, pcg_iters = 0;
         uint32_t flags = CP_FLAG_NOT_CONVERGED;
@@ -472,7 +951,7 @@ __global__ void __launch_bounds__(WG) als_persistent(const Problem* __restrict__
         for (int sw = 1; sw <= pb.max_sweeps; ++sw) {
             double dmax2 = 0.0;
             for (int q = 0; q < d; ++q) {
-                const double d2 = update_dim(s, q, r0, pcg_iters, flags);
+                const double d2 = update_dim(q, r0, pcg_iters, flags);
                 dmax2 = fmax(dmax2, d2);
             }
             // ||f||^2 = sum o_k U_k^T U_k
@@ -487,10 +966,10 @@ __global__ void __launch_bounds__(WG) als_persistent(const Problem* __restrict__
             fnorm = sqrt(fmax(f2, 0.0));
             const double dmax = sqrt(fmax(dmax2, 0.0));
             eps = fnorm > 0.0 ? dmax / fnorm : dmax;
-            gram_colnorms(s);
-            balance_scales(s);
-            scale_panels(s);
-            scale_grams(s, r0);
+            gram_colnorms();
+            balance_scales();
+            scale_panels();
+            scale_grams(r0);
             sweeps = sw;
             if (!isfinite(eps)) {
                 flags |= CP_FLAG_NONFINITE;

@@ -221,6 +221,117 @@ double frob(const cp_op1d& a, const cp_op1d& b) {
     return s;
 }
 
+// Sparse rows of a non-rank-1 operator: rows[i] = (column, value) with duplicates merged.
+std::vector<std::vector<std::pair<int, double>>> op_rows(const cp_op1d& o) {
+    const int n = o.n;
+    std::vector<std::vector<std::pair<int, double>>> rows(n);
+    auto add = [&](int i, int j, double v) {
+        for (auto& e : rows[i])
+            if (e.first == j) { e.second += v; return; }
+        rows[i].push_back({j, v});
+    };
+    for (int i = 0; i < n; ++i) {
+        switch (o.kind) {
+            case CP_OP_IDENTITY: add(i, i, 1.0); break;
+            case CP_OP_DIAG: add(i, i, o.data[i]); break;
+            case CP_OP_BAND:
+                for (int jj = 0; jj <= 2 * o.half_bw; ++jj) add(i, ((i + jj - o.half_bw) % n + n) % n, o.data[(size_t)jj * n + i]);
+                break;
+            default: break;
+        }
+    }
+    return rows;
+}
+
+// y = O^T x for any operator kind (host).
+std::vector<double> op_apply_t(const cp_op1d& o, const std::vector<double>& x) {
+    const int n = o.n;
+    std::vector<double> y(n, 0.0);
+    if (o.kind == CP_OP_RANK1) {
+        double s = 0.0;
+        for (int k = 0; k < n; ++k) s += o.data[k] * x[k];
+        for (int j = 0; j < n; ++j) y[j] = o.data[n + j] * s;
+        return y;
+    }
+    auto rows = op_rows(o);
+    for (int k = 0; k < n; ++k)
+        for (auto& e : rows[k]) y[e.first] += e.second * x[k];
+    return y;
+}
+
+// Internal composite operator (a^T b) in the device kinds.
+struct CompOp {
+    int kind = CP_OP_IDENTITY;
+    int hbw = 0;
+    std::vector<double> data;
+};
+
+cp_status compose_t(cp_handle h, const cp_op1d& a, const cp_op1d& b, CompOp& out) {
+    const int n = a.n;
+    out = CompOp();
+    if (a.kind == CP_OP_IDENTITY && b.kind == CP_OP_IDENTITY) return CP_OK;
+    if (a.kind == CP_OP_RANK1 || b.kind == CP_OP_RANK1) {
+        std::vector<double> m(n), w(n);
+        if (a.kind == CP_OP_RANK1 && b.kind == CP_OP_RANK1) {
+            double s = 0.0;
+            for (int i = 0; i < n; ++i) s += a.data[i] * b.data[i];
+            for (int i = 0; i < n; ++i) { m[i] = s * a.data[n + i]; w[i] = b.data[n + i]; }
+        } else if (a.kind == CP_OP_RANK1) {
+            // (m_a w_a^T)^T B = w_a (B^T m_a)^T
+            std::vector<double> ma(a.data, a.data + n);
+            std::vector<double> bt = op_apply_t(b, ma);
+            for (int i = 0; i < n; ++i) { m[i] = a.data[n + i]; w[i] = bt[i]; }
+        } else {
+            // A^T (m_b w_b^T) = (A^T m_b) w_b^T
+            std::vector<double> mb(b.data, b.data + n);
+            std::vector<double> at = op_apply_t(a, mb);
+            for (int i = 0; i < n; ++i) { m[i] = at[i]; w[i] = b.data[n + i]; }
+        }
+        out.kind = CP_OP_RANK1;
+        out.data.resize(2 * (size_t)n);
+        for (int i = 0; i < n; ++i) { out.data[i] = m[i]; out.data[n + i] = w[i]; }
+        return CP_OK;
+    }
+    auto ra = op_rows(a), rb = op_rows(b);
+    std::vector<std::vector<std::pair<int, double>>> c(n);
+    for (int k = 0; k < n; ++k)
+        for (auto& ea : ra[k])
+            for (auto& eb : rb[k]) {
+                const int i = ea.first, j = eb.first;
+                bool found = false;
+                for (auto& e : c[i])
+                    if (e.first == j) { e.second += ea.second * eb.second; found = true; break; }
+                if (!found) c[i].push_back({j, ea.second * eb.second});
+            }
+    int hb = 0;
+    bool diag = true;
+    for (int i = 0; i < n; ++i)
+        for (auto& e : c[i]) {
+            int off = ((e.first - i) % n + n) % n;
+            if (off > n / 2) off -= n;
+            hb = std::max(hb, std::abs(off));
+            if (e.first != i) diag = false;
+        }
+    if (diag) {
+        out.kind = CP_OP_DIAG;
+        out.data.assign(n, 0.0);
+        for (int i = 0; i < n; ++i)
+            for (auto& e : c[i]) out.data[i] += e.second;
+        return CP_OK;
+    }
+    if (2 * hb + 1 > 64) return fail(h, CP_ERR_UNSUPPORTED, "composite operator bandwidth above 31");
+    out.kind = CP_OP_BAND;
+    out.hbw = hb;
+    out.data.assign((size_t)(2 * hb + 1) * n, 0.0);
+    for (int i = 0; i < n; ++i)
+        for (auto& e : c[i]) {
+            int off = ((e.first - i) % n + n) % n;
+            if (off > n / 2) off -= n;
+            out.data[(size_t)(off + hb) * n + i] += e.second;
+        }
+    return CP_OK;
+}
+
 // Byte layout of one problem's device region.
 struct Layout {
     size_t problem, opdata, pairsC, pairsD, U, V, Q, G, X, P, Z, Cm, Dm, H0, Hinv, S, vec, reports, total;
@@ -276,6 +387,25 @@ cp_status pack_problem(cp_handle h, const HostOp& A, const HostOp& B, const cp_t
             }
         }
     }
+    // composite operators (a^T b) per dim, appended to the operator data
+    std::vector<size_t> offAA[CP_MAX_DIMS], offAB[CP_MAX_DIMS];
+    std::vector<int> kindAA[CP_MAX_DIMS], kindAB[CP_MAX_DIMS], hbAA[CP_MAX_DIMS], hbAB[CP_MAX_DIMS];
+    for (int k = 0; k < d; ++k) {
+        for (int side = 0; side < 2; ++side) {
+            const HostOp& R = side == 0 ? A : B;
+            for (int b = 0; b < R.m[k]; ++b)
+                for (int a = 0; a < A.m[k]; ++a) {
+                    CompOp co;
+                    cp_status st = compose_t(h, A.ops[k][a], R.ops[k][b], co);
+                    if (st != CP_OK) return st;
+                    (side == 0 ? offAA : offAB)[k].push_back(pk.opdata.size());
+                    (side == 0 ? kindAA : kindAB)[k].push_back(co.kind);
+                    (side == 0 ? hbAA : hbAB)[k].push_back(co.hbw);
+                    pk.opdata.insert(pk.opdata.end(), co.data.begin(), co.data.end());
+                    while (pk.opdata.size() % 4) pk.opdata.push_back(0.0);
+                }
+        }
+    }
     // Frobenius products of A's ops per dim
     for (int q = 0; q < d; ++q)
         for (int a = 0; a < A.m[q]; ++a)
@@ -285,6 +415,14 @@ cp_status pack_problem(cp_handle h, const HostOp& A, const HostOp& B, const cp_t
     pk.pairsD.clear();
     for (int q = 0; q < d; ++q) {
         const int mq = A.m[q];
+        int MM = 1, MX = 1;
+        for (int k = 0; k < d; ++k)
+            if (k != q) {
+                MM = std::max(MM, A.m[k] * A.m[k]);
+                MX = std::max(MX, A.m[k] * B.m[k]);
+            }
+        pb.MMq[q] = MM;
+        pb.MXq[q] = MX;
         for (int blk = 0; blk < mq * mq; ++blk) {
             pb.offC[q][blk] = (int32_t)pk.pairsC.size();
             for (int e = 0; e < A.T; ++e)
@@ -294,9 +432,9 @@ cp_status pack_problem(cp_handle h, const HostOp& A, const HostOp& B, const cp_t
                     PairRec pr;
                     std::memset(&pr, 0, sizeof(pr));
                     pr.coef = A.coef[e] * A.coef[z];
-                    for (int k = 0; k < d; ++k) {
-                        pr.a[k] = (uint8_t)A.idx[(size_t)e * d + k];
-                        pr.b[k] = (uint8_t)A.idx[(size_t)z * d + k];
+                    for (int k = 0, j = 0; k < d; ++k) {
+                        if (k == q) continue;
+                        pr.slot[j++] = (uint8_t)(A.idx[(size_t)e * d + k] + A.idx[(size_t)z * d + k] * A.m[k]);
                     }
                     pk.pairsC.push_back(pr);
                 }
@@ -312,9 +450,9 @@ cp_status pack_problem(cp_handle h, const HostOp& A, const HostOp& B, const cp_t
                     PairRec pr;
                     std::memset(&pr, 0, sizeof(pr));
                     pr.coef = A.coef[e] * B.coef[z];
-                    for (int k = 0; k < d; ++k) {
-                        pr.a[k] = (uint8_t)A.idx[(size_t)e * d + k];
-                        pr.b[k] = (uint8_t)B.idx[(size_t)z * d + k];
+                    for (int k = 0, j = 0; k < d; ++k) {
+                        if (k == q) continue;
+                        pr.slot[j++] = (uint8_t)(A.idx[(size_t)e * d + k] + B.idx[(size_t)z * d + k] * A.m[k]);
                     }
                     pk.pairsD.push_back(pr);
                 }
@@ -372,6 +510,16 @@ cp_status pack_problem(cp_handle h, const HostOp& A, const HostOp& B, const cp_t
     pb.precision = o.precision;
     // op descriptors get device pointers at rebase time; remember offsets in elements
     for (int k = 0; k < d; ++k) {
+        for (int i = 0; i < A.m[k] * A.m[k]; ++i) {
+            pb.compAA[k][i].kind = kindAA[k][i];
+            pb.compAA[k][i].hbw = hbAA[k][i];
+            pb.compAA[k][i].data = reinterpret_cast<const double*>(offAA[k][i]);
+        }
+        for (int i = 0; i < A.m[k] * B.m[k]; ++i) {
+            pb.compAB[k][i].kind = kindAB[k][i];
+            pb.compAB[k][i].hbw = hbAB[k][i];
+            pb.compAB[k][i].data = reinterpret_cast<const double*>(offAB[k][i]);
+        }
         for (int a = 0; a < A.m[k]; ++a) {
             pb.opA[k][a].kind = A.ops[k][a].kind;
             pb.opA[k][a].hbw = A.ops[k][a].half_bw;
@@ -393,6 +541,12 @@ void rebase(Packed& pk, char* base, double* traj) {
     const Layout& L = pk.lay;
     double* opd = reinterpret_cast<double*>(base + L.opdata);
     for (int k = 0; k < pb.d; ++k) {
+        for (int i = 0; i < pb.mA[k] * pb.mA[k]; ++i)
+            pb.compAA[k][i].data = pb.compAA[k][i].kind == CP_OP_IDENTITY ? nullptr
+                                   : opd + reinterpret_cast<size_t>(pb.compAA[k][i].data);
+        for (int i = 0; i < pb.mA[k] * pb.mB[k]; ++i)
+            pb.compAB[k][i].data = pb.compAB[k][i].kind == CP_OP_IDENTITY ? nullptr
+                                   : opd + reinterpret_cast<size_t>(pb.compAB[k][i].data);
         for (int a = 0; a < pb.mA[k]; ++a)
             pb.opA[k][a].data = pb.opA[k][a].kind == CP_OP_IDENTITY ? nullptr
                                 : opd + reinterpret_cast<size_t>(pb.opA[k][a].data);

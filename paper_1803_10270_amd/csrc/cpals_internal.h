@@ -5,7 +5,7 @@
 
 namespace cpals {
 
-constexpr int WG = 1024;          // threads of the persistent ALS workgroup (16 waves)
+constexpr int WG = 512;           // threads of the persistent ALS workgroup (8 waves)
 constexpr int NWAVES = WG / 64;
 
 // One distinct 1-D operator on the device.
@@ -15,13 +15,12 @@ struct OpDev {
     const double* data;  // device pointer into the problem blob (null for identity)
 };
 
-// Pair record (e, z) for the Hadamard assembly of one block of C (or D): the product
-// coefficient and, per dimension k, the block (a[k], b[k]) of G_k (or X_k) it multiplies in
-// (entries for k == q are unused).
+// Pair record (e, z) for the Hadamard assembly of one block of C (or D) of dimension q:
+// the product coefficient and, for the j-th dimension k != q (increasing k), the index
+// a + b * mA[k] of the block (a, b) of G_k (or X_k) that it multiplies in.
 struct PairRec {
     double coef;
-    uint8_t a[CP_MAX_DIMS];
-    uint8_t b[CP_MAX_DIMS];
+    uint8_t slot[CP_MAX_DIMS];
 };
 
 // Everything one ALS problem needs on the device (lives in device memory; copied to LDS
@@ -34,12 +33,18 @@ struct Problem {
     OpDev opA[CP_MAX_DIMS][CP_MAX_OPS];
     OpDev opB[CP_MAX_DIMS][CP_MAX_OPS];
     double trOO[CP_MAX_DIMS][CP_MAX_OPS * CP_MAX_OPS];  // <O^a, O^b>_F of A's ops, dim q
+    // composite operators of dimension q: compAA[q][a + b mA] = (O_A^a)^T O_A^b,
+    // compAB[q][a + b mA] = (O_A^a)^T O_B^b (band, diagonal, identity or rank-1)
+    OpDev compAA[CP_MAX_DIMS][CP_MAX_OPS * CP_MAX_OPS];
+    OpDev compAB[CP_MAX_DIMS][CP_MAX_OPS * CP_MAX_OPS];
     // Hadamard pair lists, per q: C blocks (mA x mA, column-major block index a + b*mA),
     // then D blocks (mA x mB, index a + b*mA).  *_off[q][blk] .. *_off[q][blk+1].
     const PairRec* pairsC;
     const PairRec* pairsD;
     int32_t offC[CP_MAX_DIMS][CP_MAX_OPS * CP_MAX_OPS + 1];
     int32_t offD[CP_MAX_DIMS][CP_MAX_OPS * CP_MAX_OPS + 1];
+    // staging strides of the assembly: max_{k != q} mA[k]^2 and max_{k != q} mA[k] mB[k]
+    int32_t MMq[CP_MAX_DIMS], MXq[CP_MAX_DIMS];
     // state (device, doubles): offsets in elements from the base pointers
     double* U;  int64_t offU[CP_MAX_DIMS];   // n_k x r
     double* V;  int64_t offV[CP_MAX_DIMS];   // n_k x r0
@@ -49,8 +54,8 @@ struct Problem {
     // scratch
     double* P;     // n_max x mA_max r  (applied panel / matvec T)
     double* Z;     // n_max x mA_max r  (matvec Z, RHS Y)
-    double* Cm;    // (mA_max r)^2
-    double* Dm;    // (mA_max r) x (mB_max r0)
+    double* Cm;    // r x (mA^2 r): Cm[l + (blk r + l') r] = C^{blk}[l, l'], blk = a + b mA
+    double* Dm;    // r x (mA mB r0): Dm[l + (blk r0 + l0) r] = D^{blk}[l, l0]
     double* H0;    // r x r
     double* Hinv;  // r x r
     double* S;     // r x r

@@ -6,6 +6,15 @@
 
 namespace cpals {
 
+// Loads and stores of device (global) memory.  Pointers reach the kernels through
+// descriptors, so the compiler cannot prove their address space by itself; without these
+// casts every access would become a FLAT instruction, whose completion also gates the
+// LDS wait counter.
+typedef const double __attribute__((address_space(1)))* gcdp;
+typedef double __attribute__((address_space(1)))* gdp;
+__device__ __forceinline__ double ldg(const double* p) { return *(gcdp)p; }
+__device__ __forceinline__ void stg(double* p, double v) { *(gdp)p = v; }
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
@@ -49,11 +58,11 @@ __device__ __forceinline__ void wg_sum2(double& a, double& b, double* red) {
 
 // out[l] = sum_i a[i] * B[i + l*ldb], l < ncol (one wave per column, rows strided by lane).
 // Result in LDS `out`.  Ends with a barrier.
-__device__ void wg_coldots(int n, int ncol, const double* a, const double* B, int ldb, double* out) {
+__device__ __forceinline__ void wg_coldots(int n, int ncol, const double* a, const double* B, int ldb, double* out) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int l = wave; l < ncol; l += NWAVES) {
         double s = 0.0;
-        for (int i = lane; i < n; i += 64) s = fma(a[i], B[i + (int64_t)l * ldb], s);
+        for (int i = lane; i < n; i += 64) s = fma(ldg(a + i), B[i + (int64_t)l * ldb], s);
         s = wave_sum(s);
         if (lane == 0) out[l] = s;
     }
@@ -71,8 +80,8 @@ __device__ __forceinline__ void apply_op(const OpDev& op, int n, int r, const do
         const double* xc = x + (int64_t)l * ldx;
         double v;
         switch (op.kind) {
-            case CP_OP_IDENTITY: v = xc[i]; break;
-            case CP_OP_DIAG: v = op.data[i] * xc[i]; break;
+            case CP_OP_IDENTITY: v = ldg(xc + i); break;
+            case CP_OP_DIAG: v = ldg(op.data + i) * ldg(xc + i); break;
             case CP_OP_BAND: {
                 v = 0.0;
                 const int h = op.hbw;
@@ -80,13 +89,13 @@ __device__ __forceinline__ void apply_op(const OpDev& op, int n, int r, const do
                     int c = i + j - h;
                     c %= n;
                     if (c < 0) c += n;
-                    v = fma(op.data[j * n + i], xc[c], v);
+                    v = fma(ldg(op.data + j * n + i), ldg(xc + c), v);
                 }
                 break;
             }
-            default: v = op.data[i] * dots[l]; break;  // rank-1: m[i] * (w^T x_l)
+            default: v = ldg(op.data + i) * dots[l]; break;  // rank-1: m[i] * (w^T x_l)
         }
-        y[i + (int64_t)l * ldy] = v;
+        stg(y + i + (int64_t)l * ldy, v);
     }
 }
 
