@@ -85,6 +85,51 @@ def cpu_baseline(p, sweeps_per_step, n_sweeps=4):
                           n_sweeps, dt, per_sweep, sweeps_per_step, cores)}
 
 
+def bench_batched(args):
+    """Batched form: uneven advection instances (d in {4,6}, n in {64..512}, rank caps 4..48) in one
+    persistent launch, against the same instances advanced one at a time (a seeded sample of
+    them, scaled by the instances' cost model)."""
+    import torch
+    from paper_1803_10270_amd import binding as B
+    from paper_1803_10270_amd import workloads as W
+    probs = W.batched_instances(args.batch_count, n_steps=args.batch_steps)
+    h = B.Handle()
+    opts = B.default_opts(tol=1e-8, max_sweeps=args.max_sweeps)
+
+    def cost(p):
+        return sum(n * len(ops) ** 2 * p.rank_cap ** 2 for n, ops in zip(p.A.dims(), p.A.ops))
+
+    fi = [B.to_device(p.f0) for p in probs]
+    fo = [B.to_device(p.guess) for p in probs]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = B.cp_als_run_batched(h, [p.A for p in probs], [p.B for p in probs], fi, fo, args.batch_steps, opts)
+    torch.cuda.synchronize()
+    t_batched = time.perf_counter() - t0
+    steps_total = args.batch_count * args.batch_steps
+    sample = list(range(0, args.batch_count, max(1, args.batch_count // args.plain_sample)))[:args.plain_sample]
+    t_plain_sample = 0.0
+    for i in sample:
+        p = probs[i]
+        v, u = B.to_device(p.f0), B.to_device(p.guess)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        B.cp_als_run(h, p.A, p.B, v, u, args.batch_steps, opts)
+        torch.cuda.synchronize()
+        t_plain_sample += time.perf_counter() - t1
+    scale = sum(cost(p) for p in probs) / sum(cost(probs[i]) for i in sample)
+    t_plain = t_plain_sample * scale
+    sweeps = [r["sweeps"] for rr in reps for r in rr]
+    out = {"form": "batched", "instances": args.batch_count, "steps_each": args.batch_steps,
+           "batched_s": t_batched, "batched_steps_per_s": steps_total / t_batched,
+           "plain_sample": len(sample), "plain_s_sample": t_plain_sample, "plain_s_estimated": t_plain,
+           "plain_steps_per_s": steps_total / t_plain, "speedup": t_plain / t_batched,
+           "mean_sweeps_per_step": float(np.mean(sweeps)),
+           "converged_steps": int(sum(1 for rr in reps for r in rr if not (r["flags"] & B.FLAG_NOT_CONVERGED)))}
+    print(json.dumps(out), flush=True)
+    h.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -93,6 +138,10 @@ def main():
     ap.add_argument("--max-sweeps", type=int, default=200)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--form", default="plain", choices=["plain", "batched"])
+    ap.add_argument("--batch-count", type=int, default=256)
+    ap.add_argument("--batch-steps", type=int, default=20)
+    ap.add_argument("--plain-sample", type=int, default=16)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only (the multi-GPU sharding is a design, not code); "
@@ -105,6 +154,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.form == "batched":
+        bench_batched(args)
+        return
     p = W.advection_ie_variable(seed=args.seed)
     h = B.Handle()
     opts = B.default_opts(tol=p.tol, max_sweeps=args.max_sweeps)

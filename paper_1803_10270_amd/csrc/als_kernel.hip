@@ -117,7 +117,7 @@ struct DiffF {
 
 // w^T X[:, l] for every rank-1 operator among ops[0..m) -> s.dots[a*r + l].  Uniform; ends
 // with a barrier when there is any rank-1 operator.
-__device__ void rank1_dots_fwd(const OpDev* ops, int m, int n, int r, const double* X) {
+__device__ __forceinline__ void rank1_dots_fwd(const OpDev* ops, int m, int n, int r, const double* X) {
     Smem& s = SMEM;
     for (int a = 0; a < m; ++a)
         if (ops[a].kind == CP_OP_RANK1) wg_coldots(n, r, ops[a].data + n, X, n, s.dots + a * r);
@@ -128,7 +128,7 @@ __device__ void rank1_dots_fwd(const OpDev* ops, int m, int n, int r, const doub
 // ------------------------------------------------------------------------------------
 
 // out[:, a*r:(a+1)*r] = O^a in (n x r panel, ld ldin), for the m operators ops[0..m).
-__device__ void apply_ops_fwd(const OpDev* ops, int m, int n, int r, const double* in, int ldin,
+__device__ __forceinline__ void apply_ops_fwd(const OpDev* ops, int m, int n, int r, const double* in, int ldin,
                               double* out) {
     Smem& s = SMEM;
     bool any_rank1 = false;
@@ -142,7 +142,7 @@ __device__ void apply_ops_fwd(const OpDev* ops, int m, int n, int r, const doubl
 }
 
 // w = sum_a (O^a)^T Z[:, a-block] + lam * p ; returns <p, w> (all threads).
-__device__ double apply_ops_t_sum(const OpDev* ops, int m, int n, int r, const double* Z,
+__device__ __forceinline__ double apply_ops_t_sum(const OpDev* ops, int m, int n, int r, const double* Z,
                                   double lam, const double* p, double* w) {
     Smem& s = SMEM;
     bool any_rank1 = false;
@@ -187,7 +187,7 @@ __device__ double apply_ops_t_sum(const OpDev* ops, int m, int n, int r, const d
 // Gram refresh of one dimension: G_k = P_k^T P_k, X_k = P_k^T Q_k with P_k = [O^a U_k]_a
 // formed row chunk by row chunk in LDS (never stored).
 // ------------------------------------------------------------------------------------
-__device__ __noinline__ void refresh_dim(int k, int r0) {
+__device__ __forceinline__ void refresh_dim(int k, int r0, bool lowp) {
     Smem& s = SMEM;
     const Problem& pb = s.pb;
     const int n = pb.n[k], r = pb.r, m = pb.mA[k], mb = pb.mB[k];
@@ -195,10 +195,11 @@ __device__ __noinline__ void refresh_dim(int k, int r0) {
     rank1_dots_fwd(pb.opA[k], m, n, r, Uk);
     OpApplyF fa{pb.opA[k], n, r, Uk, s.dots};
     ColF fb{pb.Q + pb.offQ[k], n};
-    gram_lds(n, m * r, mb * r0, fa, fb, pb.G + pb.offG[k], m * r, pb.X + pb.offX[k], m * r, s.scratch);
+    if (lowp) gram_lds<true>(n, m * r, mb * r0, fa, fb, pb.G + pb.offG[k], m * r, pb.X + pb.offX[k], m * r, s.scratch);
+    else gram_lds<false>(n, m * r, mb * r0, fa, fb, pb.G + pb.offG[k], m * r, pb.X + pb.offX[k], m * r, s.scratch);
 }
 
-__device__ void compute_Q(int k, int r0) {
+__device__ __forceinline__ void compute_Q(int k, int r0) {
     Smem& s = SMEM;
     const Problem& pb = s.pb;
     const int n = pb.n[k];
@@ -222,7 +223,7 @@ __device__ void compute_Q(int k, int r0) {
 // of a block in a fixed order.  With WITH_H0 also H0 = prod_j src_k[slot 0] and the trace
 // sum_blk trace(C^blk) <O^a, O^b>_F are produced.
 template <bool WITH_H0, int EPT>
-__device__ __noinline__ double hadamard_pass(int q, int rc, int MM, const double* src, int nblk,
+__device__ __forceinline__ double hadamard_pass(int q, int rc, int MM, const double* src, int nblk,
                                 const int32_t* off, const PairRec* pairs_g, double* out, const double* trOO) {
     Smem& s = SMEM;
     const Problem& pb = s.pb;
@@ -368,7 +369,7 @@ __device__ __noinline__ double hadamard_pass(int q, int rc, int MM, const double
     return trpart;
 }
 
-__device__ double assemble(int q, int r0) {
+__device__ __forceinline__ double assemble(int q, int r0) {
     Smem& s = SMEM;
     const Problem& pb = s.pb;
     const int d = pb.d, r = pb.r, mq = pb.mA[q], mbq = pb.mB[q];
@@ -416,7 +417,7 @@ __device__ double assemble(int q, int r0) {
 // diagonal pivots (H0 + lam I is symmetric positive definite), all positions of the r x r
 // matrix updated in parallel, two barriers per pivot.  Returns flags.
 // ------------------------------------------------------------------------------------
-__device__ __noinline__ uint32_t factor_precond(double lam) {
+__device__ __forceinline__ uint32_t factor_precond(double lam) {
     Smem& s = SMEM;
     const Problem& pb = s.pb;
     const int r = pb.r, rr = r * r;
@@ -475,8 +476,8 @@ __device__ __noinline__ uint32_t factor_precond(double lam) {
 // every chunk of KCH columns of the stacked panel the (at most two) composite operators
 // it touches are staged in LDS as five-tap stencils, so the panel chunk is formed from
 // LDS only (no dependent device-memory loads).  Requires rc >= KCH >= 4.
-template <int SPW, class EP>
-__device__ __noinline__ double comp_gemm_fast(const OpDev* comps, int nblk, int n, int rc, const double* X,
+template <bool F32, int SPW, class EP>
+__device__ __forceinline__ double comp_gemm_fast(const OpDev* comps, int nblk, int n, int rc, const double* X,
                                               const double* Kt, int KCH, const EP& ep) {
     Smem& s = SMEM;
     const int r = s.pb.r;
@@ -491,11 +492,11 @@ __device__ __noinline__ double comp_gemm_fast(const OpDev* comps, int nblk, int 
     double* Ds = Bs + ((ldb * KCH + 1) & ~1);   // two five-tap stencils, 5 n each
     __syncthreads();
     for (int t = threadIdx.x; t < n * rc; t += WG) Xs[t] = ldg(X + t);
-    d4 acc[SPW][4];
+    Tile<F32> acc[SPW][4];
 #pragma unroll
     for (int u = 0; u < SPW; ++u)
 #pragma unroll
-        for (int t = 0; t < 4; ++t) acc[u][t] = d4{0.0, 0.0, 0.0, 0.0};
+        for (int t = 0; t < 4; ++t) acc[u][t].zero();
     for (int kc0 = 0; kc0 < K; kc0 += KCH) {
         const int blk0 = kc0 / rc;
         __syncthreads();
@@ -553,7 +554,7 @@ __device__ __noinline__ double comp_gemm_fast(const OpDev* comps, int nblk, int 
                     const double a = (i < n) ? Ws[kr * ldw + i] : 0.0;
 #pragma unroll
                     for (int t = 0; t < 4; ++t)
-                        if (t < tn) acc[u][t] = mfma_f64(a, b[t], acc[u][t]);
+                        if (t < tn) acc[u][t].step(a, b[t]);
                 }
             }
         }
@@ -569,8 +570,8 @@ __device__ __noinline__ double comp_gemm_fast(const OpDev* comps, int nblk, int 
                     const int col = t * 16 + cc;
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
-                        const int row = strip * 16 + tile_row(lane, v);
-                        if (row < n && col < r) part += ep(row, col, acc[u][t][v]);
+                        const int row = strip * 16 + Tile<F32>::row(lane, v);
+                        if (row < n && col < r) part += ep(row, col, acc[u][t].get(v));
                     }
                 }
             }
@@ -582,8 +583,8 @@ __device__ __noinline__ double comp_gemm_fast(const OpDev* comps, int nblk, int 
 
 // General composite product (any operator kinds, any sizes that fit): the stacked panel
 // chunk is formed from device memory, column by column.
-template <int SPW, class EP>
-__device__ __noinline__ double comp_gemm_chunked(const OpDev* comps, int n, int rc, const double* X, const double* Kt,
+template <bool F32, int SPW, class EP>
+__device__ __forceinline__ double comp_gemm_chunked(const OpDev* comps, int n, int rc, const double* X, const double* Kt,
                                     int K, int KCH, const EP& ep) {
     Smem& s = SMEM;
     const int r = s.pb.r;
@@ -597,11 +598,11 @@ __device__ __noinline__ double comp_gemm_chunked(const OpDev* comps, int n, int 
     const int cpp = WG / tpc;                          // columns per pass
     const int my_col = threadIdx.x / tpc, my_row = threadIdx.x - my_col * tpc;
     const float inv_rc = __frcp_rn((float)rc);
-    d4 acc[SPW][4];
+    Tile<F32> acc[SPW][4];
 #pragma unroll
     for (int u = 0; u < SPW; ++u)
 #pragma unroll
-        for (int t = 0; t < 4; ++t) acc[u][t] = d4{0.0, 0.0, 0.0, 0.0};
+        for (int t = 0; t < 4; ++t) acc[u][t].zero();
     for (int kc0 = 0; kc0 < K; kc0 += KCH) {
         __syncthreads();
         // W chunk: column kk = comp_blk X[:, l] for c = kc0 + kk = blk rc + l (wave-uniform c)
@@ -639,7 +640,7 @@ __device__ __noinline__ double comp_gemm_chunked(const OpDev* comps, int n, int 
                     const double a = (i < n) ? Ws[kr * ldw + i] : 0.0;
 #pragma unroll
                     for (int t = 0; t < 4; ++t)
-                        if (t < tn) acc[u][t] = mfma_f64(a, b[t], acc[u][t]);
+                        if (t < tn) acc[u][t].step(a, b[t]);
                 }
             }
         }
@@ -655,8 +656,8 @@ __device__ __noinline__ double comp_gemm_chunked(const OpDev* comps, int n, int 
                     const int col = t * 16 + cc;
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
-                        const int row = strip * 16 + tile_row(lane, v);
-                        if (row < n && col < r) part += ep(row, col, acc[u][t][v]);
+                        const int row = strip * 16 + Tile<F32>::row(lane, v);
+                        if (row < n && col < r) part += ep(row, col, acc[u][t].get(v));
                     }
                 }
             }
@@ -671,8 +672,8 @@ __device__ __noinline__ double comp_gemm_chunked(const OpDev* comps, int n, int 
 // the stacked panel W[:, blk rc + l] = comp_blk X[:, l] is formed chunk by chunk in LDS
 // (wave-uniform columns), K^blk are the r x rc blocks of Kt (Kt[l + (blk rc + l') r]).
 // ------------------------------------------------------------------------------------
-template <class EP>
-__device__ double comp_gemm(const OpDev* comps, int nblk, int n, int rc, const double* X,
+template <bool F32, class EP>
+__device__ __forceinline__ double comp_gemm(const OpDev* comps, int nblk, int n, int rc, const double* X,
                             const double* Kt, const EP& ep) {
     Smem& s = SMEM;
     const int r = s.pb.r;
@@ -688,9 +689,9 @@ __device__ double comp_gemm(const OpDev* comps, int nblk, int n, int rc, const d
         const int ldbf = ((r + 15) >> 4) * 16 + 1;
         const int need = ((n * rc + 1) & ~1) + (((n + 1) * KCHf + 1) & ~1) + ((ldbf * KCHf + 1) & ~1) + 10 * n;
         if (five && need <= SCRATCH) {
-            if (tm <= NWAVES) return comp_gemm_fast<1>(comps, nblk, n, rc, X, Kt, KCHf, ep);
-            if (tm <= 2 * NWAVES) return comp_gemm_fast<2>(comps, nblk, n, rc, X, Kt, KCHf, ep);
-            return comp_gemm_fast<4>(comps, nblk, n, rc, X, Kt, KCHf, ep);
+            if (tm <= NWAVES) return comp_gemm_fast<F32, 1>(comps, nblk, n, rc, X, Kt, KCHf, ep);
+            if (tm <= 2 * NWAVES) return comp_gemm_fast<F32, 2>(comps, nblk, n, rc, X, Kt, KCHf, ep);
+            return comp_gemm_fast<F32, 4>(comps, nblk, n, rc, X, Kt, KCHf, ep);
         }
     }
     for (int b = 0; b < nblk; ++b)
@@ -699,12 +700,12 @@ __device__ double comp_gemm(const OpDev* comps, int nblk, int n, int rc, const d
     int KCH = 32;
     while (KCH >= 4 && (n + 1) * KCH + 2 + KCH * ldb > SCRATCH) KCH >>= 1;
     if (KCH >= 4 && tm <= 4 * NWAVES) {
-        if (tm <= NWAVES) return comp_gemm_chunked<1>(comps, n, rc, X, Kt, K, KCH, ep);
-        if (tm <= 2 * NWAVES) return comp_gemm_chunked<2>(comps, n, rc, X, Kt, K, KCH, ep);
-        return comp_gemm_chunked<4>(comps, n, rc, X, Kt, K, KCH, ep);
+        if (tm <= NWAVES) return comp_gemm_chunked<F32, 1>(comps, n, rc, X, Kt, K, KCH, ep);
+        if (tm <= 2 * NWAVES) return comp_gemm_chunked<F32, 2>(comps, n, rc, X, Kt, K, KCH, ep);
+        return comp_gemm_chunked<F32, 4>(comps, n, rc, X, Kt, K, KCH, ep);
     }
     OpApplyF af{comps, n, rc, X, s.dots};
-    return panel_gemm<4, 2>(n, r, K, af, Kt, r, ep, s.scratch);
+    return panel_gemm<F32, 4, 2>(n, r, K, af, Kt, r, ep, s.scratch);
 }
 
 // w = (M_q + lam I) p written to w; returns <p, w>.
@@ -722,11 +723,12 @@ struct ShiftDotEp {
     }
 };
 
-__device__ __forceinline__ double matvec(int q, double lam, const double* p, double* w) {
+__device__ __forceinline__ double matvec(int q, double lam, const double* p, double* w, bool lowp) {
     Smem& s = SMEM;
     const Problem& pb = s.pb;
     const int n = pb.n[q], r = pb.r, m = pb.mA[q];
-    const double part = comp_gemm(pb.compAA[q], m * m, n, r, p, pb.Cm, ShiftDotEp{w, p, lam, n});
+    const double part = lowp ? comp_gemm<true>(pb.compAA[q], m * m, n, r, p, pb.Cm, ShiftDotEp{w, p, lam, n})
+                             : comp_gemm<false>(pb.compAA[q], m * m, n, r, p, pb.Cm, ShiftDotEp{w, p, lam, n});
     return wg_sum(part, s.red);
 }
 
@@ -742,18 +744,20 @@ struct StoreDotEp {
     }
 };
 
-__device__ __noinline__ double precond(int n, const double* rv, double* zv) {
+__device__ __forceinline__ double precond(int n, const double* rv, double* zv) {
     Smem& s = SMEM;
     const Problem& pb = s.pb;
     const int r = pb.r;
-    const double part = panel_gemm<4, 2>(n, r, r, PanelA{rv, n}, pb.Hinv, r, StoreDotEp{zv, rv, n}, s.scratch);
+    const double part = panel_gemm<false, 4, 2>(n, r, r, PanelA{rv, n}, pb.Hinv, r, StoreDotEp{zv, rv, n}, s.scratch);
     return wg_sum(part, s.red);
 }
 
 // ------------------------------------------------------------------------------------
 // one dimension update; returns ||Delta f_q||^2 and accumulates pcg iterations / flags
 // ------------------------------------------------------------------------------------
-__device__ double update_dim(int q, int r0, int& pcg_iters, uint32_t& flags) {
+// lowp: the Gram, right-hand-side and matvec contractions on FP32 matrix cores (the
+// mixed-precision form); the preconditioner, the increment and all scalars stay FP64.
+__device__ __forceinline__ double update_dim(int q, int r0, int& pcg_iters, uint32_t& flags, bool lowp) {
     Smem& s = SMEM;
     const Problem& pb = s.pb;
     const int n = pb.n[q], r = pb.r, m = pb.mA[q], mb = pb.mB[q];
@@ -764,7 +768,8 @@ __device__ double update_dim(int q, int r0, int& pcg_iters, uint32_t& flags) {
     const double lam = pb.eps_reg * trM / (double)nr;
 
     // right-hand side b = sum_{a,b'} (O_A^a)^T O_B^b' V_q (D^{a b'})^T
-    comp_gemm(pb.compAB[q], m * mb, n, r0, pb.V + pb.offV[q], pb.Dm, StoreEp{pb.vb, n});
+    if (lowp) comp_gemm<true>(pb.compAB[q], m * mb, n, r0, pb.V + pb.offV[q], pb.Dm, StoreEp{pb.vb, n});
+    else comp_gemm<false>(pb.compAB[q], m * mb, n, r0, pb.V + pb.offV[q], pb.Dm, StoreEp{pb.vb, n});
 
     flags |= factor_precond(lam);
 
@@ -780,17 +785,19 @@ __device__ double update_dim(int q, int r0, int& pcg_iters, uint32_t& flags) {
     // Since P ~ J_q^T J_q, this bounds the change of the represented tensor, also along
     // near-singular directions of H_q where the plain residual norm says little.
     const double bz = precond(n, pb.vb, z);
-    matvec(q, lam, x, w);
+    matvec(q, lam, x, w, lowp);
     for (int t = threadIdx.x; t < nr; t += WG) stg(rv + t, ldg(pb.vb + t) - ldg(w + t));
     __syncthreads();
     double rz = precond(n, rv, z);
-    const double stop = pb.pcg_tol * pb.pcg_tol * bz;
+    // FP32 contractions cannot resolve the system below ~1e-7; the FP64 sweeps finish it
+    const double ptol = lowp ? fmax(pb.pcg_tol, 1e-6) : pb.pcg_tol;
+    const double stop = ptol * ptol * bz;
     int it = 0;
     if (rz > stop) {
         for (int t = threadIdx.x; t < nr; t += WG) stg(p + t, ldg(z + t));
         __syncthreads();
         for (it = 1; it <= pb.pcg_max; ++it) {
-            const double pw = matvec(q, lam, p, w);
+            const double pw = matvec(q, lam, p, w, lowp);
             const double alpha = rz / pw;
             for (int t = threadIdx.x; t < nr; t += WG) {
                 stg(x + t, fma(alpha, ldg(p + t), ldg(x + t)));
@@ -812,13 +819,13 @@ __device__ double update_dim(int q, int r0, int& pcg_iters, uint32_t& flags) {
     pcg_iters += it;
 
     // ||Delta f_q||^2 = sum((dU^T dU) o H0), dU = x - U_q; then U_q <- x
-    gram_lds(n, r, 0, DiffF{x, Uq, n}, DiffF{x, Uq, n}, pb.S, r, nullptr, 0, s.scratch);
+    gram_lds<false>(n, r, 0, DiffF{x, Uq, n}, DiffF{x, Uq, n}, pb.S, r, nullptr, 0, s.scratch);
     for (int t = threadIdx.x; t < nr; t += WG) stg(Uq + t, ldg(x + t));
     __syncthreads();
     double part = 0.0;
     for (int t = threadIdx.x; t < r * r; t += WG) part = fma(pb.S[t], pb.H0[t], part);
     const double delta2 = wg_sum(part, s.red);
-    refresh_dim(q, r0);
+    refresh_dim(q, r0, lowp);
     return delta2;
 }
 
@@ -827,7 +834,7 @@ __device__ double update_dim(int q, int r0, int& pcg_iters, uint32_t& flags) {
 // ------------------------------------------------------------------------------------
 
 // Column norms from the panels themselves -> s.colnorm[k*r + l]
-__device__ void panel_colnorms() {
+__device__ __forceinline__ void panel_colnorms() {
     Smem& s = SMEM;
     const Problem& pb = s.pb;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -844,7 +851,7 @@ __device__ void panel_colnorms() {
 }
 
 // Column norms from the Gram diagonals G_k[0,0][l,l].
-__device__ void gram_colnorms() {
+__device__ __forceinline__ void gram_colnorms() {
     Smem& s = SMEM;
     const Problem& pb = s.pb;
     const int r = pb.r;
@@ -857,7 +864,7 @@ __device__ void gram_colnorms() {
 }
 
 // colnorm -> scale factors (in place); a column with a zero factor keeps scale 1.
-__device__ void balance_scales() {
+__device__ __forceinline__ void balance_scales() {
     Smem& s = SMEM;
     const Problem& pb = s.pb;
     const int r = pb.r, d = pb.d;
@@ -878,7 +885,7 @@ __device__ void balance_scales() {
     __syncthreads();
 }
 
-__device__ void scale_panels() {
+__device__ __forceinline__ void scale_panels() {
     Smem& s = SMEM;
     const Problem& pb = s.pb;
     const int r = pb.r;
@@ -891,7 +898,7 @@ __device__ void scale_panels() {
 }
 
 // After a sweep: rescale panels and, consistently, the Grams and cross-Grams.
-__device__ void scale_grams(int r0) {
+__device__ __forceinline__ void scale_grams(int r0) {
     Smem& s = SMEM;
     const Problem& pb = s.pb;
     const int r = pb.r;
@@ -943,15 +950,22 @@ __global__ void __launch_bounds__(WG) als_persistent(const Problem* __restrict__
         panel_colnorms();
         balance_scales();
         scale_panels();
-        for (int k = 0; k < d; ++k) refresh_dim(k, r0);
+        // mixed-precision form: sweeps with FP32 contractions until the increment reaches the
+        // FP32 floor (or the sweep budget is nearly spent), then one FP64 refinement sweep
+        const bool mixed = pb.precision == CP_PREC_MIXED;
+        bool lowp = mixed && pb.max_sweeps > 1;
+        // (with tol = 0 the caller asks for exactly max_sweeps sweeps: FP32 until the last one)
+        const double tol_low = pb.tol > 0.0 ? fmax(pb.tol, 1e-6) : 0.0;
+        for (int k = 0; k < d; ++k) refresh_dim(k, r0, lowp);
 
         int sweeps = 0, pcg_iters = 0;
         uint32_t flags = CP_FLAG_NOT_CONVERGED;
         double eps = 0.0, fnorm = 0.0;
         for (int sw = 1; sw <= pb.max_sweeps; ++sw) {
+            const bool was_low = lowp;
             double dmax2 = 0.0;
             for (int q = 0; q < d; ++q) {
-                const double d2 = update_dim(q, r0, pcg_iters, flags);
+                const double d2 = update_dim(q, r0, pcg_iters, flags, lowp);
                 dmax2 = fmax(dmax2, d2);
             }
             // ||f||^2 = sum o_k U_k^T U_k
@@ -975,10 +989,19 @@ __global__ void __launch_bounds__(WG) als_persistent(const Problem* __restrict__
                 flags |= CP_FLAG_NONFINITE;
                 break;
             }
+            if (was_low) {
+                if (eps <= tol_low || sw + 1 >= pb.max_sweeps) {
+                    // switch to FP64: recompute every Gram in FP64, then the refinement sweep
+                    lowp = false;
+                    for (int k = 0; k < d; ++k) refresh_dim(k, r0, false);
+                }
+                continue;
+            }
             if (eps <= pb.tol) {
                 flags &= ~CP_FLAG_NOT_CONVERGED;
                 break;
             }
+            if (mixed) break;   // the single FP64 refinement sweep is done
         }
         if (threadIdx.x == 0) {
             cp_als_report rep;

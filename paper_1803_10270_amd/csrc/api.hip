@@ -591,7 +591,6 @@ cp_status check_opts(cp_handle h, const cp_als_opts* o) {
         return fail(h, CP_ERR_INVALID_ARG, "bad ALS options");
     if (o->precision != CP_PREC_FP64 && o->precision != CP_PREC_MIXED)
         return fail(h, CP_ERR_INVALID_ARG, "bad precision");
-    if (o->precision == CP_PREC_MIXED) return fail(h, CP_ERR_UNSUPPORTED, "mixed precision is not built yet");
     return CP_OK;
 }
 

@@ -130,49 +130,4 @@ __device__ __forceinline__ void apply_op_t(const OpDev& op, int n, int r, const 
     }
 }
 
-// C (M x N) = alpha * op(A) * op(B) + beta * C, column-major, all in global memory.
-// op(A)(i,k) = TA ? A[k + i*lda] : A[i + k*lda];  op(B)(k,j) = TB ? B[j + k*ldb] : B[k + j*ldb].
-// Register micro-tiles of 4 x 4 per thread.  No barrier.
-template <bool TA, bool TB>
-__device__ void wg_gemm(int M, int N, int K, double alpha, const double* __restrict__ A, int lda,
-                        const double* __restrict__ B, int ldb, double beta, double* __restrict__ C, int ldc) {
-    constexpr int TM = 4, TN = 4;
-    const int mt = (M + TM - 1) / TM, nt = (N + TN - 1) / TN;
-    for (int t = threadIdx.x; t < mt * nt; t += WG) {
-        const int i0 = (t % mt) * TM, j0 = (t / mt) * TN;
-        double acc[TM][TN];
-#pragma unroll
-        for (int a = 0; a < TM; ++a)
-#pragma unroll
-            for (int b = 0; b < TN; ++b) acc[a][b] = 0.0;
-        for (int k = 0; k < K; ++k) {
-            double av[TM], bv[TN];
-#pragma unroll
-            for (int a = 0; a < TM; ++a) {
-                const int i = i0 + a;
-                av[a] = (i < M) ? (TA ? A[k + (int64_t)i * lda] : A[i + (int64_t)k * lda]) : 0.0;
-            }
-#pragma unroll
-            for (int b = 0; b < TN; ++b) {
-                const int j = j0 + b;
-                bv[b] = (j < N) ? (TB ? B[j + (int64_t)k * ldb] : B[k + (int64_t)j * ldb]) : 0.0;
-            }
-#pragma unroll
-            for (int a = 0; a < TM; ++a)
-#pragma unroll
-                for (int b = 0; b < TN; ++b) acc[a][b] = fma(av[a], bv[b], acc[a][b]);
-        }
-#pragma unroll
-        for (int a = 0; a < TM; ++a)
-#pragma unroll
-            for (int b = 0; b < TN; ++b) {
-                const int i = i0 + a, j = j0 + b;
-                if (i < M && j < N) {
-                    double* cp = C + i + (int64_t)j * ldc;
-                    *cp = (beta == 0.0) ? alpha * acc[a][b] : fma(beta, *cp, alpha * acc[a][b]);
-                }
-            }
-    }
-}
-
 }  // namespace cpals

@@ -1,8 +1,9 @@
-// Workgroup-level FP64 contractions on the gfx950 matrix cores (v_mfma_f64_16x16x4).
+// Workgroup-level contractions on the gfx950 matrix cores: v_mfma_f64_16x16x4 (FP64) or,
+// in the mixed-precision form, v_mfma_f32_16x16x4 on operands rounded to FP32.
 //
-// Lane layout of one 16x16x4 step (measured on the device): lane l supplies
-// A[l % 16][l / 16] and B[l / 16][l % 16]; accumulator element v of lane l is
-// D[(l / 16) + 4 v][l % 16].
+// Lane layouts of one 16x16x4 step (measured on the device): lane l supplies
+// A[l % 16][l / 16] and B[l / 16][l % 16] for both; accumulator element v of lane l is
+// D[(l / 16) + 4 v][l % 16] for FP64 and D[4 (l / 16) + v][l % 16] for FP32.
 #pragma once
 #include <hip/hip_runtime.h>
 #include "cpals_internal.h"
@@ -18,6 +19,32 @@ __device__ __forceinline__ d4 mfma_f64(double a, double b, d4 c) {
 
 __device__ __forceinline__ int tile_row(int lane, int v) { return (lane >> 4) + 4 * v; }
 __device__ __forceinline__ int tile_col(int lane) { return lane & 15; }
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+// One 16 x 16 output tile accumulated on the matrix cores.
+template <bool F32>
+struct Tile;
+
+template <>
+struct Tile<false> {
+    d4 v;
+    __device__ __forceinline__ void zero() { v = d4{0.0, 0.0, 0.0, 0.0}; }
+    __device__ __forceinline__ void step(double a, double b) { v = mfma_f64(a, b, v); }
+    __device__ __forceinline__ double get(int i) const { return v[i]; }
+    __device__ __forceinline__ static int row(int lane, int i) { return (lane >> 4) + 4 * i; }
+};
+
+template <>
+struct Tile<true> {
+    f4 v;
+    __device__ __forceinline__ void zero() { v = f4{0.0f, 0.0f, 0.0f, 0.0f}; }
+    __device__ __forceinline__ void step(double a, double b) {
+        v = __builtin_amdgcn_mfma_f32_16x16x4f32((float)a, (float)b, v, 0, 0, 0);
+    }
+    __device__ __forceinline__ double get(int i) const { return (double)v[i]; }
+    __device__ __forceinline__ static int row(int lane, int i) { return 4 * (lane >> 4) + i; }
+};
 
 // ---------------------------------------------------------------------------------------
 // Panel product  C (M x N) = alpha * A (M x K) * B' (K x N)
@@ -42,8 +69,8 @@ struct StoreEp {
     }
 };
 
-template <int NT, int IPW, class AF, class EP>
-__device__ double panel_gemm(int M, int N, int K, const AF& af, const double* __restrict__ Bt, int ldb,
+template <bool F32, int NT, int IPW, class AF, class EP>
+__device__ __forceinline__ double panel_gemm(int M, int N, int K, const AF& af, const double* __restrict__ Bt, int ldb,
                              const EP& ep, double* lds) {
     double part = 0.0;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -60,11 +87,11 @@ __device__ double panel_gemm(int M, int N, int K, const AF& af, const double* __
         const int pack = active ? it % packs : 0, g = active ? it / packs : 0;
         const int jt0 = g * NT;
         const int ntl = active ? min(NT, tn - jt0) : 0;
-        d4 acc[IPW][NT];
+        Tile<F32> acc[IPW][NT];
 #pragma unroll
         for (int s = 0; s < IPW; ++s)
 #pragma unroll
-            for (int t = 0; t < NT; ++t) acc[s][t] = d4{0.0, 0.0, 0.0, 0.0};
+            for (int t = 0; t < NT; ++t) acc[s][t].zero();
         for (int kc0 = 0; kc0 < K; kc0 += PG_KCH) {
             const int kc = min(PG_KCH, K - kc0);
             __syncthreads();
@@ -91,7 +118,7 @@ __device__ double panel_gemm(int M, int N, int K, const AF& af, const double* __
                         if (t < ntl && 4 * ks < kc) {
                             const double b = lds[(4 * ks + kq) * ldsw + (jt0 + t) * 16 + cc];
 #pragma unroll
-                            for (int s = 0; s < IPW; ++s) acc[s][t] = mfma_f64(a[s][ks], b, acc[s][t]);
+                            for (int s = 0; s < IPW; ++s) acc[s][t].step(a[s][ks], b);
                         }
                     }
                 }
@@ -106,8 +133,8 @@ __device__ double panel_gemm(int M, int N, int K, const AF& af, const double* __
                         const int col = (jt0 + t) * 16 + cc;
 #pragma unroll
                         for (int v = 0; v < 4; ++v) {
-                            const int row = (pack * IPW + s) * 16 + tile_row(lane, v);
-                            if (row < M && col < N) part += ep(row, col, acc[s][t][v]);
+                            const int row = (pack * IPW + s) * 16 + Tile<F32>::row(lane, v);
+                            if (row < M && col < N) part += ep(row, col, acc[s][t].get(v));
                         }
                     }
                 }
@@ -137,8 +164,8 @@ struct PanelA {
 constexpr int GRAM_KC = 16;
 constexpr int GRAM_TILES_PER_WAVE = 4;
 
-template <class FA, class FB>
-__device__ void gram_lds(int n, int M1, int N2, const FA& fa, const FB& fb, double* __restrict__ G1, int ld1,
+template <bool F32, class FA, class FB>
+__device__ __forceinline__ void gram_lds(int n, int M1, int N2, const FA& fa, const FB& fb, double* __restrict__ G1, int ld1,
                          double* __restrict__ G2, int ld2, double* lds) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int TM = (M1 + 15) >> 4, TN = (N2 + 15) >> 4;
@@ -171,9 +198,9 @@ __device__ void gram_lds(int n, int M1, int N2, const FA& fa, const FB& fb, doub
                 which[t] = 2;
             }
         }
-        d4 acc[GRAM_TILES_PER_WAVE];
+        Tile<F32> acc[GRAM_TILES_PER_WAVE];
 #pragma unroll
-        for (int t = 0; t < GRAM_TILES_PER_WAVE; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
+        for (int t = 0; t < GRAM_TILES_PER_WAVE; ++t) acc[t].zero();
         for (int i0 = 0; i0 < n; i0 += GRAM_KC) {
             __syncthreads();
             for (int t = threadIdx.x; t < GRAM_KC * TM * 16; t += WG) {
@@ -198,7 +225,7 @@ __device__ void gram_lds(int n, int M1, int N2, const FA& fa, const FB& fb, doub
                     for (int k0 = 0; k0 < GRAM_KC; k0 += 4) {
                         const double a = As[(k0 + kk) * wa + ti[t] * 16 + cc];
                         const double b = Bsrc[(k0 + kk) * wbs + tj[t] * 16 + cc];
-                        acc[t] = mfma_f64(a, b, acc[t]);
+                        acc[t].step(a, b);
                     }
                 }
             }
@@ -209,8 +236,8 @@ __device__ void gram_lds(int n, int M1, int N2, const FA& fa, const FB& fb, doub
             const int col = tj[t] * 16 + cc;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int row = ti[t] * 16 + tile_row(lane, v);
-                const double val = acc[t][v];
+                const int row = ti[t] * 16 + Tile<F32>::row(lane, v);
+                const double val = acc[t].get(v);
                 if (which[t] == 1) {
                     if (row < M1 && col < M1) {
                         stg(G1 + row + (int64_t)col * ld1, val);

@@ -228,3 +228,37 @@ def test_not_converged_flag(handle):
     p = W.advection_ie_variable(seed=0, d=3, n=16, ic_rank=2, cap=3)
     _, rep = run_gpu_step(handle, p.A, p.B, p.f0, p.guess, tol=1e-30, max_sweeps=2)
     assert rep["sweeps"] == 2 and rep["flags"] & B.FLAG_NOT_CONVERGED
+
+
+# ------------------------------------------------------------------ mixed precision
+
+@pytest.mark.parametrize("case", ["advection_cn", "kinetic"])
+def test_mixed_precision_error_vs_fp64_oracle(handle, case):
+    """Mixed-precision form: Gram, right-hand-side and matvec contractions on FP32 matrix
+    cores until the increment reaches the FP32 floor, then one FP64 refinement sweep.  Its
+    result is compared with the converged FP64 oracle solution; stated bound 1e-5 relative
+    L2 (the measured value is printed)."""
+    log("mixed", case)
+    if case == "advection_cn":
+        p = W.advection_cn_constant(seed=4, d=6, n=32, cap=2)
+    else:
+        p = W.kinetic_cn(seed=3, n=32, field_rank=3, cap=4)
+    Ug, rep = run_gpu_step(handle, p.A, p.B, p.f0, p.guess, tol=1e-10, max_sweeps=80, precision=B.PREC_MIXED)
+    Uo, ro = O.als_step(p.A, p.B, p.f0, p.guess, tol=1e-13, max_sweeps=300)
+    Uf, rf = run_gpu_step(handle, p.A, p.B, p.f0, p.guess, tol=1e-13, max_sweeps=300)
+    d_mixed = tensor_distance(Ug, Uo)
+    d_fp64 = tensor_distance(Uf, Uo)
+    log("mixed-precision distance to FP64 oracle %.3e (FP64 path %.3e, oracle sweeps %d)" % (d_mixed, d_fp64, ro["sweeps"]),
+        rep)
+    assert d_fp64 <= TOL
+    assert d_mixed <= 1e-5
+
+
+def test_mixed_precision_single_sweep_is_fp64(handle):
+    """With a budget of one sweep the mixed form does only the FP64 refinement sweep."""
+    log("mixed single sweep")
+    p = W.advection_ie_variable(seed=2, d=4, n=32, ic_rank=2, cap=4)
+    Ug, rep = run_gpu_step(handle, p.A, p.B, p.f0, p.guess, tol=0.0, max_sweeps=1, precision=B.PREC_MIXED)
+    Uo, ro = O.als_step(p.A, p.B, p.f0, p.guess, tol=0.0, max_sweeps=1)
+    assert rep["sweeps"] == 1
+    assert tensor_distance(Ug, Uo) <= TOL
