@@ -12,19 +12,23 @@
 // of the stacked Grams G_k = P_k^T P_k, X_k = P_k^T Q_k, P_k = [O^a U_k]_a, Q_k = [F^b V_k]_b.
 //
 // The (n r) x (n r) system is solved by preconditioned conjugate gradients with the
-// preconditioner (H_q + lambda_q I) (x) I_n, H_q = o_{k != q} U_k^T U_k (its inverse is the
-// r x r Cholesky-based solve).  For A = I + skew the preconditioned spectrum lies in
-// [sigma_min(A)^2, sigma_max(A)^2], so a handful of iterations reach FP64 accuracy.
+// preconditioner (H_q + lambda_q I) (x) I_n, H_q = o_{k != q} U_k^T U_k.
+//
+// Code layout: the kernel body is a small state machine (step set-up, Gram refresh,
+// assembly, one composite product, increment, sweep end, report).  Every heavy routine is
+// inlined at exactly one place, so the code a dimension update executes stays small
+// (instruction-cache resident) and the register allocator sees one routine at a time.
 #include <hip/hip_runtime.h>
 #include <math.h>
+#include <type_traits>
 #include "device_common.h"
 #include "mfma_f64.h"
 
 namespace cpals {
 
-constexpr int SCRATCH = 15616;   // doubles of LDS shared by the phases of one dimension update
+constexpr int SCRATCH = 16384;   // doubles of LDS shared by the phases of one dimension update
 constexpr int LDS_PAIRS = 384;   // pair records of one dimension kept in LDS during assembly
-constexpr int MAX_ITEMS = 48;    // work items of one Hadamard pass
+constexpr int CG_TAPS = 5;       // stencils up to half bandwidth 2 keep their coefficients in registers
 
 struct StageSlot {               // one staged Gram block of the assembly
     int64_t base;                // element offset of entry (0, 0) of the block
@@ -32,336 +36,326 @@ struct StageSlot {               // one staged Gram block of the assembly
     int32_t pad;
 };
 
-struct Smem;
 extern __shared__ __attribute__((aligned(16))) unsigned char cpals_smem[];
 
 struct Smem {
     Problem pb;
+    OpDev ident;                 // the identity operator (preconditioner products)
     double red[2 * NWAVES];
     double dots[CP_MAX_OPS * CP_MAX_OPS * CP_MAX_RANK];
     double colnorm[CP_MAX_DIMS * CP_MAX_RANK];
     double scratch[SCRATCH];
     PairRec pairs[LDS_PAIRS];
     StageSlot slots[(CP_MAX_DIMS - 1) * CP_MAX_OPS * CP_MAX_OPS];
-    int32_t items[MAX_ITEMS][3];
-    int32_t blk_item[CP_MAX_OPS * CP_MAX_OPS + 1];
-    int32_t iscal[8];
+    uint32_t iflag;
 };
+static_assert(sizeof(Smem) <= 160 * 1024, "LDS budget of one workgroup");
 
 // The workgroup's LDS state, reached through the LDS symbol itself so that every access
-// compiles to LDS instructions, also inside non-inlined functions.
+// compiles to LDS instructions.
 #define SMEM (*reinterpret_cast<Smem*>(cpals_smem))
 
+// Workgroup-uniform copies (the values are equal in every lane; this tells the compiler).
+__device__ __forceinline__ int ufirst(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ double ufirst(double v) {
+    const long long b = __double_as_longlong(v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(b & 0xffffffffll));
+    const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)((unsigned long long)b >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
 
-// Row index i + o of a periodic grid of n points, for |o| small (one or two wraps).
+// Row index i of a periodic grid of n points, for i a few periods off.
 __device__ __forceinline__ int wrap_idx(int i, int n) {
-    if (i < 0) {
-        i += n;
-        while (i < 0) i += n;
-    } else if (i >= n) {
-        i -= n;
-        while (i >= n) i -= n;
-    }
+    while (i < 0) i += n;
+    while (i >= n) i -= n;
     return i;
 }
 
-// Value of (O x)[i] for one 1-D operator and one column x (ld irrelevant).  For a rank-1
-// operator O = m w^T, `dot` must hold w^T x.
-// x is a column in device memory.
-__device__ __forceinline__ double op_value(const OpDev& op, int n, int i, const double* x, double dot) {
-    switch (op.kind) {
-        case CP_OP_IDENTITY: return ldg(x + i);
-        case CP_OP_DIAG: return ldg(op.data + i) * ldg(x + i);
-        case CP_OP_BAND: {
-            double v = 0.0;
-            const int h = op.hbw;
-            for (int j = 0; j <= 2 * h; ++j) v = fma(ldg(op.data + j * n + i), ldg(x + wrap_idx(i + j - h, n)), v);
-            return v;
-        }
-        default: return ldg(op.data + i) * dot;
-    }
-}
-
-// Element (i, c) of the stacked applied panel [O^0 X, O^1 X, ...] (column c = a*r + l).
-// For a rank-1 operator O^a = m w^T, dots[a*r + l] must hold w^T X[:, l].
-struct OpApplyF {
-    const OpDev* ops;
-    int n, r;
-    const double* X;
-    const double* dots;
-    __device__ __forceinline__ double operator()(int i, int c) const {
-        // c / r through a float reciprocal (exact for c < 2^16, r <= 64)
-        const int a = (int)(((float)c + 0.5f) * __frcp_rn((float)r));
-        const int l = c - a * r;
-        return op_value(ops[a], n, i, X + (int64_t)l * n, dots[a * r + l]);
-    }
-};
-
 // Plain column-major panel element (i, c).
 struct ColF {
+    typedef double raw_t;
     const double* X;
     int ld;
-    __device__ __forceinline__ double operator()(int i, int c) const { return ldg(X + i + (int64_t)c * ld); }
+    __device__ __forceinline__ static raw_t zero() { return 0.0; }
+    __device__ __forceinline__ raw_t raw(int i, int c) const { return ldg(X + i + (int64_t)c * ld); }
+    __device__ __forceinline__ double val(raw_t v) const { return v; }
 };
 
 // x - u elementwise (the increment of one factor).
 struct DiffF {
+    typedef double2 raw_t;
     const double* x;
     const double* u;
     int ld;
-    __device__ __forceinline__ double operator()(int i, int c) const {
+    __device__ __forceinline__ static raw_t zero() { return double2{0.0, 0.0}; }
+    __device__ __forceinline__ raw_t raw(int i, int c) const {
         const int64_t o = i + (int64_t)c * ld;
-        return ldg(x + o) - ldg(u + o);
+        return double2{ldg(x + o), ldg(u + o)};
     }
+    __device__ __forceinline__ double val(raw_t v) const { return v.x - v.y; }
 };
 
-// w^T X[:, l] for every rank-1 operator among ops[0..m) -> s.dots[a*r + l].  Uniform; ends
-// with a barrier when there is any rank-1 operator.
-__device__ __forceinline__ void rank1_dots_fwd(const OpDev* ops, int m, int n, int r, const double* X) {
+// The stacked applied panel P = [O^0 X, O^1 X, ...] (n x m r, column a r + l) into `out`.
+// For each batch of elements every tap and coefficient load is issued before the sums are
+// formed.  Ends with a barrier.
+__device__ __forceinline__ void apply_panel(const OpDev* ops, int m, int n, int r, const double* X, double* out) {
     Smem& s = SMEM;
     for (int a = 0; a < m; ++a)
         if (ops[a].kind == CP_OP_RANK1) wg_coldots(n, r, ops[a].data + n, X, n, s.dots + a * r);
-}
-
-// ------------------------------------------------------------------------------------
-// applied panels
-// ------------------------------------------------------------------------------------
-
-// out[:, a*r:(a+1)*r] = O^a in (n x r panel, ld ldin), for the m operators ops[0..m).
-__device__ __forceinline__ void apply_ops_fwd(const OpDev* ops, int m, int n, int r, const double* in, int ldin,
-                              double* out) {
-    Smem& s = SMEM;
-    bool any_rank1 = false;
-    for (int a = 0; a < m; ++a) any_rank1 |= (ops[a].kind == CP_OP_RANK1);
-    if (any_rank1) {
-        for (int a = 0; a < m; ++a)
-            if (ops[a].kind == CP_OP_RANK1) wg_coldots(n, r, ops[a].data + n, in, ldin, s.dots + a * r);
-    }
-    for (int a = 0; a < m; ++a) apply_op(ops[a], n, r, in, ldin, out + (int64_t)a * r * n, n, s.dots + a * r);
-    __syncthreads();
-}
-
-// w = sum_a (O^a)^T Z[:, a-block] + lam * p ; returns <p, w> (all threads).
-__device__ __forceinline__ double apply_ops_t_sum(const OpDev* ops, int m, int n, int r, const double* Z,
-                                  double lam, const double* p, double* w) {
-    Smem& s = SMEM;
-    bool any_rank1 = false;
-    for (int a = 0; a < m; ++a) any_rank1 |= (ops[a].kind == CP_OP_RANK1);
-    if (any_rank1) {
-        for (int a = 0; a < m; ++a)
-            if (ops[a].kind == CP_OP_RANK1)
-                wg_coldots(n, r, ops[a].data, Z + (int64_t)a * r * n, n, s.dots + a * r);
-    }
-    double part = 0.0;
-    const int total = n * r;
-    for (int t = threadIdx.x; t < total; t += WG) {
-        const int i = t % n, l = t / n;
-        const double pv = p ? p[t] : 0.0;
-        double v = lam * pv;
-        for (int a = 0; a < m; ++a) {
-            const OpDev& op = ops[a];
-            const double* zc = Z + (int64_t)a * r * n + (int64_t)l * n;
-            switch (op.kind) {
-                case CP_OP_IDENTITY: v += zc[i]; break;
-                case CP_OP_DIAG: v = fma(op.data[i], zc[i], v); break;
-                case CP_OP_BAND: {
-                    const int h = op.hbw;
-                    for (int j = 0; j <= 2 * h; ++j) {
-                        int k = i - j + h;
-                        k %= n;
-                        if (k < 0) k += n;
-                        v = fma(op.data[j * n + k], zc[k], v);
+    const int total = n * m * r;
+    const float invn = __frcp_rn((float)n), invr = __frcp_rn((float)r);
+    constexpr int U = 8;
+    for (int t0 = tid_here(); t0 < total; t0 += U * WG) {
+        double xv[U][CG_TAPS], cv[U][CG_TAPS];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int t = t0 + u * WG;
+#pragma unroll
+            for (int j = 0; j < CG_TAPS; ++j) xv[u][j] = cv[u][j] = 0.0;
+            if (t < total) {
+                const int c = fdiv(t, invn), i = t - c * n;
+                const int a = fdiv(c, invr), l = c - a * r;
+                const int kind = ops[a].kind, h = ops[a].hbw;
+                const double* data = ops[a].data;
+                const double* x = X + (int64_t)l * n;
+                if (kind == CP_OP_IDENTITY) {
+                    xv[u][0] = ldg(x + i);
+                    cv[u][0] = 1.0;
+                } else if (kind == CP_OP_DIAG) {
+                    xv[u][0] = ldg(x + i);
+                    cv[u][0] = ldg(data + i);
+                } else if (kind == CP_OP_RANK1) {
+                    xv[u][0] = s.dots[a * r + l];
+                    cv[u][0] = ldg(data + i);
+                } else if (h <= 2) {
+#pragma unroll
+                    for (int j = 0; j < CG_TAPS; ++j) {
+                        if (j <= 2 * h) {
+                            xv[u][j] = ldg(x + wrap_idx(i + j - h, n));
+                            cv[u][j] = ldg(data + (int64_t)j * n + i);
+                        }
                     }
-                    break;
+                } else {
+                    double v = 0.0;
+                    for (int j = 0; j <= 2 * h; ++j) v = fma(ldg(data + (int64_t)j * n + i), ldg(x + wrap_idx(i + j - h, n)), v);
+                    xv[u][0] = v;
+                    cv[u][0] = 1.0;
                 }
-                default: v = fma(op.data[n + i], s.dots[a * r + l], v); break;
             }
         }
-        w[t] = v;
-        part = fma(pv, v, part);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int t = t0 + u * WG;
+            if (t < total) {
+                double v = 0.0;
+#pragma unroll
+                for (int j = 0; j < CG_TAPS; ++j) v = fma(cv[u][j], xv[u][j], v);
+                stg(out + t, v);
+            }
+        }
     }
-    return wg_sum(part, s.red);
+    __syncthreads();
 }
 
 // ------------------------------------------------------------------------------------
 // Gram refresh of one dimension: G_k = P_k^T P_k, X_k = P_k^T Q_k with P_k = [O^a U_k]_a
-// formed row chunk by row chunk in LDS (never stored).
+// (P_k formed once in the scratch panel, then both products over row chunks staged in LDS).
 // ------------------------------------------------------------------------------------
 __device__ __forceinline__ void refresh_dim(int k, int r0, bool lowp) {
     Smem& s = SMEM;
     const Problem& pb = s.pb;
     const int n = pb.n[k], r = pb.r, m = pb.mA[k], mb = pb.mB[k];
     const double* Uk = pb.U + pb.offU[k];
-    rank1_dots_fwd(pb.opA[k], m, n, r, Uk);
-    OpApplyF fa{pb.opA[k], n, r, Uk, s.dots};
+    apply_panel(pb.opA[k], m, n, r, Uk, pb.P);
+    ColF fa{pb.P, n};
     ColF fb{pb.Q + pb.offQ[k], n};
-    if (lowp) gram_lds<true>(n, m * r, mb * r0, fa, fb, pb.G + pb.offG[k], m * r, pb.X + pb.offX[k], m * r, s.scratch);
-    else gram_lds<false>(n, m * r, mb * r0, fa, fb, pb.G + pb.offG[k], m * r, pb.X + pb.offX[k], m * r, s.scratch);
+    if (lowp) gram_lds<true>(n, m * r, mb * r0, fa, fb, pb.G + pb.offG[k], m * r, pb.X + pb.offX[k], m * r, s.scratch, SCRATCH);
+    else gram_lds<false>(n, m * r, mb * r0, fa, fb, pb.G + pb.offG[k], m * r, pb.X + pb.offX[k], m * r, s.scratch, SCRATCH);
 }
 
-__device__ __forceinline__ void compute_Q(int k, int r0) {
+// Q_k = [O_B^b V_k]_b for every dimension (the fixed B-side panels of a time step).
+__device__ __forceinline__ void compute_Q_all(int r0) {
     Smem& s = SMEM;
     const Problem& pb = s.pb;
-    const int n = pb.n[k];
-    apply_ops_fwd(pb.opB[k], pb.mB[k], n, r0, pb.V + pb.offV[k], n, pb.Q + pb.offQ[k]);
+    for (int k = 0; k < pb.d; ++k) {
+        const int n = pb.n[k], mb = pb.mB[k];
+        const double* Vk = pb.V + pb.offV[k];
+        for (int b = 0; b < mb; ++b)
+            if (pb.opB[k][b].kind == CP_OP_RANK1) wg_coldots(n, r0, pb.opB[k][b].data + n, Vk, n, s.dots + b * r0);
+        for (int b = 0; b < mb; ++b) apply_op(pb.opB[k][b], n, r0, Vk, n, pb.Q + pb.offQ[k] + (int64_t)b * r0 * n, n, s.dots + b * r0);
+        __syncthreads();
+    }
 }
 
 // ------------------------------------------------------------------------------------
-// Hadamard assembly for dimension q: C (mA x mA blocks r x r), D (mA x mB blocks r x r0),
-// H0 = o_{k != q} U_k^T U_k.  Returns trace(M_q) (without the shift).
-// The Gram entries of a chunk of matrix positions are staged in LDS once (all dimensions
-// k != q, all operator blocks), then eight lanes share one position and split its pair
-// list; the partial sums meet through lane shuffles.
-// ------------------------------------------------------------------------------------
-// One Hadamard pass over the r x rc position grid of dimension q:
+// Hadamard assembly (eqs. ML, MR): one pass over the r x rc position grid of dimension q,
 //   out[l + (blk rc + lc) r] = sum over the pair records of block blk of
 //                              coef * prod_{j-th dim k != q} src_k[block slot_j][l, lc]
-// (src = G for the C blocks, X for the D blocks).  Per chunk of E positions the entries of
-// every (dimension, operator block) slot are staged in LDS; the pair list is cut into
-// work items of similar length, each wave takes items and sums them for its positions
-// (EPT per lane, identity-block factors held in registers), and a last pass adds the items
-// of a block in a fixed order.  With WITH_H0 also H0 = prod_j src_k[slot 0] and the trace
-// sum_blk trace(C^blk) <O^a, O^b>_F are produced.
-template <bool WITH_H0, int EPT>
-__device__ __forceinline__ double hadamard_pass(int q, int rc, int MM, const double* src, int nblk,
-                                const int32_t* off, const PairRec* pairs_g, double* out, const double* trOO) {
+// (src = G for the C blocks, X for the D blocks).  Per chunk of E = 64 PG positions the
+// entries of every (dimension, operator block) slot are staged in LDS; wave w takes the 64
+// positions of group w % PG and the share w / PG of every block's pair list, so that all
+// lanes of a wave walk the same pair records (uniform slot branches; slot 0 is held in
+// registers).  The shares meet in LDS and are added in a fixed order.  With H0 also
+// H0 = prod_j src_k[slot 0] and the trace sum_blk trace(C^blk) <O^a, O^b>_F are produced.
+// ------------------------------------------------------------------------------------
+__device__ __forceinline__ double hadamard_pass(int q, bool withH0, int rc, int MM, const double* src, int nblk,
+                                                const int32_t* off, const PairRec* pairs_g, double* out,
+                                                const double* trOO) {
     Smem& s = SMEM;
     const Problem& pb = s.pb;
     const int d = pb.d, r = pb.r;
-    const int nk = d - 1;
+    const int nk = ufirst(d - 1);
     const int nE = r * rc;
-    constexpr int E = 64 * EPT;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    double* st = s.scratch;
+    const int lane = tid_here() & 63, wave = tid_here() >> 6;
     const int p0 = off[0], np = off[nblk] - off[0];
     __syncthreads();
-    const PairRec* pairs = pairs_g + p0;
-    if (np <= LDS_PAIRS) {
-        for (int t = threadIdx.x; t < np; t += WG) {
+    const bool pl = np <= LDS_PAIRS;
+    if (pl) {
+        for (int t = tid_here(); t < np; t += WG) {
             const double* src_rec = reinterpret_cast<const double*>(pairs_g + p0 + t);
             double* dst_rec = reinterpret_cast<double*>(s.pairs + t);
             dst_rec[0] = ldg(src_rec);
             dst_rec[1] = ldg(src_rec + 1);
         }
-        pairs = s.pairs;
     }
-    for (int t = threadIdx.x; t < nk * MM; t += WG) {
+    for (int t = tid_here(); t < nk * MM; t += WG) {
         const int j = t / MM, ab = t % MM;
         const int k = j < q ? j : j + 1;
         const int mk = pb.mA[k];
-        const int nb = WITH_H0 ? mk : pb.mB[k];
+        const int nb = withH0 ? mk : pb.mB[k];
         StageSlot sl;
         sl.pad = 0;
         if (ab < mk * nb) {
             const int a = ab % mk, b = ab / mk;
             sl.ld = mk * r;
-            sl.base = (WITH_H0 ? pb.offG[k] : pb.offX[k]) + (int64_t)(b * rc) * sl.ld + a * r;
+            sl.base = (withH0 ? pb.offG[k] : pb.offX[k]) + (int64_t)(b * rc) * sl.ld + a * r;
         } else {
             sl.ld = 0;
             sl.base = 0;
         }
         s.slots[t] = sl;
     }
-    if (threadIdx.x == 0) {
-        int S = max(1, (np + 2 * NWAVES - 1) / (2 * NWAVES));
-        int cnt;
-        for (;;) {
-            cnt = 0;
-            for (int blk = 0; blk < nblk; ++blk) cnt += max(1, (off[blk + 1] - off[blk] + S - 1) / S);
-            if (cnt <= MAX_ITEMS) break;
-            S *= 2;
-        }
-        cnt = 0;
-        for (int blk = 0; blk < nblk; ++blk) {
-            s.blk_item[blk] = cnt;
-            const int b0 = off[blk] - p0, b1 = off[blk + 1] - p0;
-            int a = b0;
-            do {
-                const int e = min(b1, a + S);
-                s.items[cnt][0] = blk;
-                s.items[cnt][1] = a;
-                s.items[cnt][2] = e;
-                ++cnt;
-                a = e;
-            } while (a < b1);
-        }
-        s.blk_item[nblk] = cnt;
-        s.iscal[1] = cnt;
-    }
-    __syncthreads();
-    const int nitems = s.iscal[1];
+    // chunk geometry: PG groups of 64 positions, SPL = NWAVES / PG shares of the pair lists
+    int PG = NWAVES;
+    while (PG > 1 && 64 * PG * (nk * MM + (NWAVES / PG) * nblk) > SCRATCH) PG >>= 1;
+    PG = ufirst(PG);
+    const int SPL = NWAVES / PG;
+    const int E = 64 * PG;
+    const int pg = wave % PG, sp = wave / PG;
+    const int e = pg * 64 + lane;
+    double* st = s.scratch;
     double* part = st + nk * MM * E;
+    const float invr = __frcp_rn((float)r);
+    __syncthreads();
     double trpart = 0.0;
     for (int e0 = 0; e0 < nE; e0 += E) {
-        // stage the slot entries of positions e0 .. e0 + E
+        // stage the slot entries of positions e0 .. e0 + E (a thread keeps one position)
         {
-            const int e = threadIdx.x & (E - 1);
-            const int pos = e0 + e;
-            const bool ok = pos < nE;
-            const int l = ok ? pos % r : 0, lc = ok ? pos / r : 0;
-            for (int sl = threadIdx.x / E; sl < nk * MM; sl += WG / E) {
-                const StageSlot ss = s.slots[sl];
-                st[sl * E + e] = (ok && ss.ld) ? ldg(src + ss.base + (int64_t)lc * ss.ld + l) : 0.0;
-            }
-        }
-        __syncthreads();
-        // identity-block factors of this lane's positions
-        double h0r[CP_MAX_DIMS - 1][EPT];
+            const int ee = tid_here() & (E - 1);
+            const int spos = e0 + ee;
+            const int slc = fdiv(spos, invr), sl0 = spos - slc * r;
+            const bool ok = spos < nE;
+            const int nslot = nk * MM, step = WG / E;
+            for (int sb = tid_here() / E; sb < nslot; sb += 16 * step) {
+                double v[16];
 #pragma unroll
-        for (int j = 0; j < CP_MAX_DIMS - 1; ++j)
-#pragma unroll
-            for (int u = 0; u < EPT; ++u) h0r[j][u] = (j < nk) ? st[(j * MM) * E + lane + 64 * u] : 1.0;
-        if (WITH_H0 && wave == 0) {
-#pragma unroll
-            for (int u = 0; u < EPT; ++u) {
-                const int pos = e0 + lane + 64 * u;
-                double prod = 1.0;
-#pragma unroll
-                for (int j = 0; j < CP_MAX_DIMS - 1; ++j) prod *= h0r[j][u];
-                if (pos < nE) stg(pb.H0 + pos, prod);
-            }
-        }
-        for (int it = wave; it < nitems; it += NWAVES) {
-            const int i0 = s.items[it][1], i1 = s.items[it][2];
-            double acc[EPT];
-#pragma unroll
-            for (int u = 0; u < EPT; ++u) acc[u] = 0.0;
-            for (int pi = i0; pi < i1; ++pi) {
-                const double coef = pairs[pi].coef;
-                const uint64_t sw = *reinterpret_cast<const uint64_t*>(pairs[pi].slot);
-                double prod[EPT];
-#pragma unroll
-                for (int u = 0; u < EPT; ++u) prod[u] = coef;
-#pragma unroll
-                for (int j = 0; j < CP_MAX_DIMS - 1; ++j) {
-                    if (j < nk) {
-                        const int sj = (int)((sw >> (8 * j)) & 0xffu);
-                        if (sj == 0) {
-#pragma unroll
-                            for (int u = 0; u < EPT; ++u) prod[u] *= h0r[j][u];
-                        } else {
-                            const double* row = st + (j * MM + sj) * E + lane;
-#pragma unroll
-                            for (int u = 0; u < EPT; ++u) prod[u] *= row[64 * u];
-                        }
+                for (int u = 0; u < 16; ++u) {
+                    const int sl = sb + u * step;
+                    v[u] = 0.0;
+                    if (sl < nslot) {
+                        const StageSlot ss = s.slots[sl];
+                        if (ok && ss.ld) v[u] = ldg(src + ss.base + (int64_t)slc * ss.ld + sl0);
                     }
                 }
 #pragma unroll
-                for (int u = 0; u < EPT; ++u) acc[u] += prod[u];
+                for (int u = 0; u < 16; ++u) {
+                    const int sl = sb + u * step;
+                    if (sl < nslot) st[sl * E + ee] = v[u];
+                }
             }
-#pragma unroll
-            for (int u = 0; u < EPT; ++u) part[it * E + lane + 64 * u] = acc[u];
         }
         __syncthreads();
-        for (int t = threadIdx.x; t < nblk * E; t += WG) {
-            const int blk = t / E, e = t - blk * E;
-            const int pos = e0 + e;
-            if (pos < nE) {
+        const int pos = e0 + e;
+        double h0r[CP_MAX_DIMS - 1];
+#pragma unroll
+        for (int j = 0; j < CP_MAX_DIMS - 1; ++j) h0r[j] = (j < nk) ? st[(j * MM) * E + e] : 1.0;
+        if (withH0 && sp == 0 && pos < nE) {
+            double prod = 1.0;
+#pragma unroll
+            for (int j = 0; j < CP_MAX_DIMS - 1; ++j) prod *= h0r[j];
+            stg(pb.H0 + pos, prod);
+        }
+        // pair products, instantiated per number of factors so that every factor read is
+        // unconditional: four records at a time, all their LDS reads in flight together
+        auto pairs_fast = [&](auto nk_c) {
+            constexpr int NK = decltype(nk_c)::value;
+            for (int blk = 0; blk < nblk; ++blk) {
+                const int b0 = off[blk] - p0, len = off[blk + 1] - off[blk];
+                const int lo = ufirst(b0 + (len * sp) / SPL), hi = ufirst(b0 + (len * (sp + 1)) / SPL);
+                double acc4[4] = {0.0, 0.0, 0.0, 0.0};
+                for (int pi = lo; pi < hi; pi += 4) {
+                    double coef[4];
+                    uint64_t sw[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const bool ok = pi + u < hi;
+                        const int pp = ok ? pi + u : lo;
+                        coef[u] = ok ? s.pairs[pp].coef : 0.0;
+                        sw[u] = *reinterpret_cast<const uint64_t*>(s.pairs[pp].slot);
+                    }
+                    double f[4][NK > 0 ? NK : 1];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+#pragma unroll
+                        for (int j = 0; j < NK; ++j) f[u][j] = st[(j * MM + (int)((sw[u] >> (8 * j)) & 0xffu)) * E + e];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        double prod = coef[u];
+#pragma unroll
+                        for (int j = 0; j < NK; ++j) prod *= f[u][j];
+                        acc4[u] += prod;
+                    }
+                }
+                part[(sp * nblk + blk) * E + e] = (acc4[0] + acc4[1]) + (acc4[2] + acc4[3]);
+            }
+        };
+        if (pl) {
+            switch (nk) {
+                case 1: pairs_fast(std::integral_constant<int, 1>{}); break;
+                case 2: pairs_fast(std::integral_constant<int, 2>{}); break;
+                case 3: pairs_fast(std::integral_constant<int, 3>{}); break;
+                case 4: pairs_fast(std::integral_constant<int, 4>{}); break;
+                case 5: pairs_fast(std::integral_constant<int, 5>{}); break;
+                case 6: pairs_fast(std::integral_constant<int, 6>{}); break;
+                default: pairs_fast(std::integral_constant<int, 7>{}); break;
+            }
+        } else {
+            // pair list too long for LDS: records from device memory, one at a time
+            for (int blk = 0; blk < nblk; ++blk) {
+                const int b0 = off[blk] - p0, len = off[blk + 1] - off[blk];
+                const int lo = ufirst(b0 + (len * sp) / SPL), hi = ufirst(b0 + (len * (sp + 1)) / SPL);
                 double acc = 0.0;
-                for (int it = s.blk_item[blk]; it < s.blk_item[blk + 1]; ++it) acc += part[it * E + e];
-                const int l = pos % r, lc = pos / r;
+                for (int pi = lo; pi < hi; ++pi) {
+                    const double* rec = reinterpret_cast<const double*>(pairs_g + p0 + pi);
+                    const double coef = ldg(rec);
+                    const uint64_t sw = (uint64_t)__double_as_longlong(ldg(rec + 1));
+                    double prod = coef;
+                    for (int j = 0; j < nk; ++j) prod *= st[(j * MM + (int)((sw >> (8 * j)) & 0xffu)) * E + e];
+                    acc += prod;
+                }
+                part[(sp * nblk + blk) * E + e] = acc;
+            }
+        }
+        __syncthreads();
+        for (int t = tid_here(); t < nblk * E; t += WG) {
+            const int blk = t / E, ee = t & (E - 1);
+            const int p = e0 + ee;
+            if (p < nE) {
+                double acc = 0.0;
+                for (int u = 0; u < SPL; ++u) acc += part[(u * nblk + blk) * E + ee];
+                const int lc = fdiv(p, invr), l = p - lc * r;
                 stg(out + l + (int64_t)(blk * rc + lc) * r, acc);
-                if (WITH_H0 && l == lc) trpart = fma(acc, trOO[blk], trpart);
+                if (withH0 && l == lc) trpart = fma(acc, trOO[blk], trpart);
             }
         }
         __syncthreads();
@@ -369,6 +363,7 @@ __device__ __forceinline__ double hadamard_pass(int q, int rc, int MM, const dou
     return trpart;
 }
 
+// C, D and H0 of dimension q; returns trace(M_q) (without the shift).
 __device__ __forceinline__ double assemble(int q, int r0) {
     Smem& s = SMEM;
     const Problem& pb = s.pb;
@@ -376,457 +371,462 @@ __device__ __forceinline__ double assemble(int q, int r0) {
     double trpart = 0.0;
     if (d == 1) {
         // every Hadamard product over k != q is empty (all ones)
-        for (int t = threadIdx.x; t < mq * mq * r * r; t += WG) {
+        for (int t = tid_here(); t < mq * mq * r * r; t += WG) {
             const int blk = t / (r * r), e = t % (r * r);
             const int l = e % r, lp = e / r;
             double acc = 0.0;
-            for (int pi = pb.offC[q][blk]; pi < pb.offC[q][blk + 1]; ++pi) acc += pb.pairsC[pi].coef;
-            pb.Cm[l + (int64_t)(blk * r + lp) * r] = acc;
+            for (int pi = pb.offC[q][blk]; pi < pb.offC[q][blk + 1]; ++pi) acc += ldg(&pb.pairsC[pi].coef);
+            stg(pb.Cm + l + (int64_t)(blk * r + lp) * r, acc);
             if (l == lp) trpart = fma(acc, pb.trOO[q][blk], trpart);
         }
-        for (int t = threadIdx.x; t < mq * mbq * r * r0; t += WG) {
+        for (int t = tid_here(); t < mq * mbq * r * r0; t += WG) {
             const int blk = t / (r * r0), e = t % (r * r0);
             const int l = e % r, l0 = e / r;
             double acc = 0.0;
-            for (int pi = pb.offD[q][blk]; pi < pb.offD[q][blk + 1]; ++pi) acc += pb.pairsD[pi].coef;
-            pb.Dm[l + (int64_t)(blk * r0 + l0) * r] = acc;
+            for (int pi = pb.offD[q][blk]; pi < pb.offD[q][blk + 1]; ++pi) acc += ldg(&pb.pairsD[pi].coef);
+            stg(pb.Dm + l + (int64_t)(blk * r0 + l0) * r, acc);
         }
-        for (int t = threadIdx.x; t < r * r; t += WG) pb.H0[t] = 1.0;
+        for (int t = tid_here(); t < r * r; t += WG) stg(pb.H0 + t, 1.0);
         return wg_sum(trpart, s.red);
     }
-    const int nk = d - 1;
-    // positions per chunk: as many as the LDS staging area holds (items need E doubles each)
-    const int MM = pb.MMq[q], MX = pb.MXq[q];
-    if ((nk * MM + MAX_ITEMS) * 256 <= SCRATCH)
-        trpart = hadamard_pass<true, 4>(q, r, MM, pb.G, mq * mq, pb.offC[q], pb.pairsC, pb.Cm, pb.trOO[q]);
-    else if ((nk * MM + MAX_ITEMS) * 128 <= SCRATCH)
-        trpart = hadamard_pass<true, 2>(q, r, MM, pb.G, mq * mq, pb.offC[q], pb.pairsC, pb.Cm, pb.trOO[q]);
-    else
-        trpart = hadamard_pass<true, 1>(q, r, MM, pb.G, mq * mq, pb.offC[q], pb.pairsC, pb.Cm, pb.trOO[q]);
-    if ((nk * MX + MAX_ITEMS) * 256 <= SCRATCH)
-        hadamard_pass<false, 4>(q, r0, MX, pb.X, mq * mbq, pb.offD[q], pb.pairsD, pb.Dm, nullptr);
-    else if ((nk * MX + MAX_ITEMS) * 128 <= SCRATCH)
-        hadamard_pass<false, 2>(q, r0, MX, pb.X, mq * mbq, pb.offD[q], pb.pairsD, pb.Dm, nullptr);
-    else
-        hadamard_pass<false, 1>(q, r0, MX, pb.X, mq * mbq, pb.offD[q], pb.pairsD, pb.Dm, nullptr);
+    for (int pass = 0; pass < 2; ++pass) {
+        const bool c = pass == 0;
+        trpart += hadamard_pass(q, c, c ? r : r0, c ? pb.MMq[q] : pb.MXq[q], c ? pb.G : pb.X, c ? mq * mq : mq * mbq,
+                                c ? pb.offC[q] : pb.offD[q], c ? pb.pairsC : pb.pairsD, c ? pb.Cm : pb.Dm, pb.trOO[q]);
+    }
     return wg_sum(trpart, s.red);  // includes the barrier that publishes C, D, H0
 }
 
 // ------------------------------------------------------------------------------------
-// Preconditioner: Hinv = (H0 + lam I)^{-1} by in-place Gauss-Jordan elimination on the
-// diagonal pivots (H0 + lam I is symmetric positive definite), all positions of the r x r
-// matrix updated in parallel, two barriers per pivot.  Returns flags.
+// Preconditioner: Hinv = (H0 + lam I)^{-1} by Gauss-Jordan elimination on the diagonal
+// pivots (H0 + lam I is symmetric positive definite).  The r x r entries live in registers
+// spread over the workgroup (at most 8 per thread); the owners of the next pivot row and
+// column publish them to a double-buffered LDS copy, so each pivot costs one barrier.
+// Returns flags.
 // ------------------------------------------------------------------------------------
 __device__ __forceinline__ uint32_t factor_precond(double lam) {
     Smem& s = SMEM;
     const Problem& pb = s.pb;
     const int r = pb.r, rr = r * r;
-    double* H = s.scratch;
-    for (int t = threadIdx.x; t < rr; t += WG) {
-        const int i = t % r, j = t / r;
-        H[t] = ldg(pb.H0 + t) + ((i == j) ? lam : 0.0);
-    }
-    double dpart = 0.0;
-    for (int t = threadIdx.x; t < r; t += WG) dpart = fmax(dpart, ldg(pb.H0 + t + t * r) + lam);
-    dpart = wave_max(dpart);
-    __syncthreads();
-    if ((threadIdx.x & 63) == 0) s.red[threadIdx.x >> 6] = dpart;
-    __syncthreads();
-    double maxdiag = 0.0;
-    for (int w = 0; w < NWAVES; ++w) maxdiag = fmax(maxdiag, s.red[w]);
-    uint32_t fl = 0;
     constexpr int PER = (CP_MAX_RANK * CP_MAX_RANK + WG - 1) / WG;
+    double* rowb = s.scratch;             // [2][CP_MAX_RANK]
+    double* colb = s.scratch + 2 * CP_MAX_RANK;
+    const float invr = __frcp_rn((float)r);
+    double hv[PER];
+    int hi[PER], hj[PER];
+    double dmax = 0.0;
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int t = tid_here() + u * WG;
+        hj[u] = fdiv(t, invr);
+        hi[u] = t - hj[u] * r;
+        hv[u] = 0.0;
+        if (t < rr) {
+            hv[u] = ldg(pb.H0 + t) + ((hi[u] == hj[u]) ? lam : 0.0);
+            if (hi[u] == hj[u]) dmax = fmax(dmax, hv[u]);
+            if (hi[u] == 0) rowb[hj[u]] = hv[u];
+            if (hj[u] == 0) colb[hi[u]] = hv[u];
+        } else {
+            hi[u] = hj[u] = -1;
+        }
+    }
+    dmax = wave_max(dmax);
+    if ((tid_here() & 63) == 0) s.red[tid_here() >> 6] = dmax;
+    __syncthreads();
+    dmax = 0.0;
+    for (int w = 0; w < NWAVES; ++w) dmax = fmax(dmax, s.red[w]);
+    uint32_t fl = 0;
     for (int p = 0; p < r; ++p) {
-        double piv = H[p + p * r];
-        if (!(piv > 1e-12 * maxdiag)) fl |= CP_FLAG_REGULARIZED;
+        const int cur = (p & 1) * CP_MAX_RANK, nxt = CP_MAX_RANK - cur;
+        double piv = colb[cur + p];
+        if (!(piv > 1e-12 * dmax)) fl |= CP_FLAG_REGULARIZED;
         if (!(piv > 0.0)) piv = (lam > 0.0) ? lam : 1e-300;
         const double ip = 1.0 / piv;
-        double nv[PER];
 #pragma unroll
         for (int u = 0; u < PER; ++u) {
-            const int t = threadIdx.x + u * WG;
-            nv[u] = 0.0;
-            if (t < rr) {
-                const int i = t % r, j = t / r;
-                const double hip = H[i + p * r], hpj = H[p + j * r];
-                if (i == p) nv[u] = (j == p) ? ip : hpj * ip;
-                else if (j == p) nv[u] = -hip * ip;
-                else nv[u] = fma(-hip * ip, hpj, H[t]);
+            const int i = hi[u], j = hj[u];
+            if (i >= 0) {
+                const double hip = colb[cur + i], hpj = rowb[cur + j];
+                double nv;
+                if (i == p) nv = (j == p) ? ip : hpj * ip;
+                else if (j == p) nv = -hip * ip;
+                else nv = fma(-hip * ip, hpj, hv[u]);
+                hv[u] = nv;
+                if (i == p + 1) rowb[nxt + j] = nv;
+                if (j == p + 1) colb[nxt + i] = nv;
             }
         }
         __syncthreads();
+    }
+    // symmetrise (the preconditioner of CG must be symmetric): through LDS
+    double* Hm = s.scratch + 4 * CP_MAX_RANK;
 #pragma unroll
-        for (int u = 0; u < PER; ++u) {
-            const int t = threadIdx.x + u * WG;
-            if (t < rr) H[t] = nv[u];
-        }
-        __syncthreads();
-    }
-    // symmetrise (the preconditioner of CG must be symmetric)
-    for (int t = threadIdx.x; t < rr; t += WG) {
-        const int i = t % r, j = t / r;
-        stg(pb.Hinv + t, 0.5 * (H[t] + H[j + i * r]));
-    }
+    for (int u = 0; u < PER; ++u)
+        if (hi[u] >= 0) Hm[hi[u] + hj[u] * r] = hv[u];
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < PER; ++u)
+        if (hi[u] >= 0) stg(pb.Hinv + hi[u] + hj[u] * r, 0.5 * (hv[u] + Hm[hj[u] + hi[u] * r]));
     __syncthreads();
     return fl;
 }
 
-// Fast composite product for operators that are all band/diagonal/identity with half
-// bandwidth <= 2 (the usual finite-difference case): X is copied to LDS once, and for
-// every chunk of KCH columns of the stacked panel the (at most two) composite operators
-// it touches are staged in LDS as five-tap stencils, so the panel chunk is formed from
-// LDS only (no dependent device-memory loads).  Requires rc >= KCH >= 4.
-template <bool F32, int SPW, class EP>
-__device__ __forceinline__ double comp_gemm_fast(const OpDev* comps, int nblk, int n, int rc, const double* X,
-                                              const double* Kt, int KCH, const EP& ep) {
+// ------------------------------------------------------------------------------------
+// Composite product on the matrix cores:
+//   out[i, j] = sum_blk sum_{l < rc} (comp_blk X)[i, l] Kt[j + (blk rc + l) r]   (i < n, j < r)
+// then, with `shift`, out += lam X and, with `dot`, the return value sum_ij X[i, j] out[i, j]
+// (per thread; both need rc == r).  Used for the right-hand side (comp = (O_A^a)^T O_B^b, Kt = D blocks),
+// the matvec (M_q + lam I) p (comp = (O^a)^T O^b, Kt = C blocks) and the preconditioner
+// r Hinv (comp = I, Kt = Hinv).
+//
+// X is staged in LDS pass by pass (up to 16 SPW NWAVES rows plus a halo of the widest
+// stencil); each lane forms the A fragment it feeds to the matrix core directly from the
+// staged rows and its stencil coefficients (held in registers), so the stacked panel
+// [comp_blk X] is never stored.  The r x rc block of Kt of the next operator block is
+// prefetched into registers while the current one is consumed from LDS.
+//
+// The panel is produced by the transform xf while it is staged (v = a + beta b, written back
+// to wv, and x2 += alpha2 p2 on the same elements): the conjugate-gradient vector updates
+// ride along with the product that consumes their result.
+// ------------------------------------------------------------------------------------
+struct Xform {
+    const double* a;
+    const double* b;     // optional
+    double beta;
+    double* wv;          // optional: v is written here
+    double* x2;          // optional: x2 += alpha2 * p2
+    const double* p2;
+    double alpha2;
+};
+
+// Transform of the own rows of a panel of `total` elements (contiguous, ld n): all loads of
+// a batch are issued before any store.  MODE 0: v = a; 1: v = a, wv = v; 2: v = a + beta b,
+// wv = v; 3: as 2 and x2 += alpha2 p2.  With `lds`, v goes to Xs[l ldx + H + i].
+template <int MODE>
+__device__ __forceinline__ void xform_rows(const Xform& xf, int total, int n, bool lds, double* Xs, int ldx, int H) {
+    constexpr int U = 8;
+    const float invn = __frcp_rn((float)n);
+    for (int t0 = tid_here(); t0 < total; t0 += U * WG) {
+        double va[U], vb[U], vx[U], vp[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int t = t0 + u * WG;
+            const bool ok = t < total;
+            va[u] = ok ? ldg(xf.a + t) : 0.0;
+            vb[u] = (MODE >= 2 && ok) ? ldg(xf.b + t) : 0.0;
+            vx[u] = (MODE == 3 && ok) ? ldg(xf.x2 + t) : 0.0;
+            vp[u] = (MODE == 3 && ok) ? ldg(xf.p2 + t) : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int t = t0 + u * WG;
+            if (t < total) {
+                const double v = (MODE >= 2) ? fma(xf.beta, vb[u], va[u]) : va[u];
+                if (MODE >= 1) stg(xf.wv + t, v);
+                if (MODE == 3) stg(xf.x2 + t, fma(xf.alpha2, vp[u], vx[u]));
+                if (lds) {
+                    const int l = fdiv(t, invn);
+                    Xs[l * ldx + H + (t - l * n)] = v;
+                }
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ void xform_dispatch(const Xform& xf, int total, int n, bool lds, double* Xs, int ldx, int H) {
+    const int mode = xf.x2 ? 3 : (xf.b ? 2 : (xf.wv ? 1 : 0));
+    switch (ufirst(mode)) {
+        case 0: xform_rows<0>(xf, total, n, lds, Xs, ldx, H); break;
+        case 1: xform_rows<1>(xf, total, n, lds, Xs, ldx, H); break;
+        case 2: xform_rows<2>(xf, total, n, lds, Xs, ldx, H); break;
+        default: xform_rows<3>(xf, total, n, lds, Xs, ldx, H); break;
+    }
+}
+
+
+template <bool F32, int TN>
+__device__ __forceinline__ double cgemm(int n, int r, const OpDev* comps, int nblk, int rc, Xform xf,
+                                        const double* Kt, double* out, double lam, bool shift, bool dot) {
+    constexpr int SPW = (TN == 4) ? 2 : 4;   // 16-row strips per wave and pass
+    constexpr int LDB = TN * 16 + 1;
+    constexpr int PF = (64 * TN * 16 + WG - 1) / WG;
     Smem& s = SMEM;
-    const int r = s.pb.r;
-    const int K = nblk * rc;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = tid_here() & 63, wave = tid_here() >> 6;
     const int kq = lane >> 4, cc = lane & 15;
-    const int tm = (n + 15) >> 4, tn = (r + 15) >> 4;
-    const int nw = tn * 16, ldb = nw + 1, ldw = n + 1;
+    const int rc4 = (rc + 3) & ~3;
+    const int ktsz = rc4 * LDB;
+    int H = 0;
+    bool any_r1 = false;
+    for (int b = 0; b < nblk; ++b) {
+        if (comps[b].kind == CP_OP_BAND) H = max(H, comps[b].hbw);
+        any_r1 |= comps[b].kind == CP_OP_RANK1;
+    }
+    H = ufirst(H);
+    // rows per pass: as many strips as the waves hold, limited by the LDS staging area
+    int RP = min((n + 15) >> 4, NWAVES * SPW) * 16;
+    auto ldx_of = [&](int rp) { return ((rp + 2 * H + 15) & ~31) + 16; };   // odd multiple of 16
+    while (RP > 16 && ldx_of(RP) * rc + 2 * ktsz + 2 * CG_TAPS * RP > SCRATCH) RP -= 16;
+    RP = ufirst(RP);
+    const int ldx = ldx_of(RP);
+    const int R = RP + 2 * H;
+    const int npass = (n + RP - 1) / RP;
     double* Xs = s.scratch;
-    double* Ws = Xs + ((n * rc + 1) & ~1);
-    double* Bs = Ws + ((ldw * KCH + 1) & ~1);
-    double* Ds = Bs + ((ldb * KCH + 1) & ~1);   // two five-tap stencils, 5 n each
+    double* KtS = s.scratch + ldx * rc;
+    double* CfS = KtS + 2 * ktsz;           // [2][CG_TAPS][RP] stencil coefficients of the pass rows
+    const bool xw = xf.wv != nullptr || xf.x2 != nullptr;
     __syncthreads();
-    for (int t = threadIdx.x; t < n * rc; t += WG) Xs[t] = ldg(X + t);
-    Tile<F32> acc[SPW][4];
-#pragma unroll
-    for (int u = 0; u < SPW; ++u)
-#pragma unroll
-        for (int t = 0; t < 4; ++t) acc[u][t].zero();
-    for (int kc0 = 0; kc0 < K; kc0 += KCH) {
-        const int blk0 = kc0 / rc;
+    if (xw && npass > 1) {
+        // several passes: apply the transform to the whole panel first
+        xform_dispatch(xf, n * rc, n, false, nullptr, 0, 0);
         __syncthreads();
-        // stencils of the blocks touched by this chunk
-        for (int t = threadIdx.x; t < 2 * 5 * n; t += WG) {
-            const int which = t / (5 * n), rem = t - which * 5 * n;
-            const int j = rem / n, i = rem - j * n;
-            const int blk = blk0 + which;
-            double v = 0.0;
-            if (blk < nblk) {
-                const OpDev op = comps[blk];
-                if (op.kind == CP_OP_IDENTITY) v = (j == 2) ? 1.0 : 0.0;
-                else if (op.kind == CP_OP_DIAG) v = (j == 2) ? ldg(op.data + i) : 0.0;
-                else {
-                    const int jj = j - 2 + op.hbw;   // tap j sits at offset j - 2
-                    v = (jj >= 0 && jj <= 2 * op.hbw) ? ldg(op.data + jj * n + i) : 0.0;
-                }
-            }
-            Ds[t] = v;
-        }
-        for (int t = threadIdx.x; t < KCH * nw; t += WG) {
-            const int kk = t / nw, j = t - kk * nw;
-            Bs[kk * ldb + j] = (kc0 + kk < K && j < r) ? ldg(Kt + j + (int64_t)(kc0 + kk) * r) : 0.0;
-        }
-        __syncthreads();
-        for (int t = threadIdx.x; t < KCH * n; t += WG) {
-            const int kk = t / n, i = t - kk * n;
-            const int c = kc0 + kk;
-            double v = 0.0;
-            if (c < K) {
-                const int blk = c / rc, l = c - blk * rc;
-                const double* d5 = Ds + (blk - blk0) * 5 * n;
-                const double* x = Xs + l * n;
-#pragma unroll
-                for (int j = 0; j < 5; ++j) {
-                    int ci = i + j - 2;
-                    ci += (ci < 0) ? n : 0;
-                    ci -= (ci >= n) ? n : 0;
-                    v = fma(d5[j * n + i], x[ci], v);
-                }
-            }
-            Ws[kk * ldw + i] = v;
-        }
-        __syncthreads();
-        for (int ks = 0; ks < KCH / 4; ++ks) {
-            const int kr = 4 * ks + kq;
-            double b[4];
-#pragma unroll
-            for (int t = 0; t < 4; ++t) b[t] = (t < tn) ? Bs[kr * ldb + t * 16 + cc] : 0.0;
-#pragma unroll
-            for (int u = 0; u < SPW; ++u) {
-                const int strip = wave + NWAVES * u;
-                if (strip < tm) {
-                    const int i = strip * 16 + cc;
-                    const double a = (i < n) ? Ws[kr * ldw + i] : 0.0;
-#pragma unroll
-                    for (int t = 0; t < 4; ++t)
-                        if (t < tn) acc[u][t].step(a, b[t]);
-                }
+        xf.a = xf.wv;
+        xf.b = nullptr;
+        xf.wv = nullptr;
+        xf.x2 = nullptr;
+    }
+    if (any_r1 && npass > 1) {
+        // rank-1 blocks: dots[blk rc + l] = w_blk^T X[:, l] from the full panel
+        for (int b = 0; b < nblk; ++b) {
+            if (comps[b].kind != CP_OP_RANK1) continue;
+            const double* w = comps[b].data + n;
+            for (int l = wave; l < rc; l += NWAVES) {
+                double acc = 0.0;
+                for (int i = lane; i < n; i += 64) acc = fma(ldg(w + i), ldg(xf.a + i + (int64_t)l * n), acc);
+                acc = wave_sum(acc);
+                if (lane == 0) s.dots[b * rc + l] = acc;
             }
         }
     }
     double part = 0.0;
-#pragma unroll
-    for (int u = 0; u < SPW; ++u) {
-        const int strip = wave + NWAVES * u;
-        if (strip < tm) {
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                if (t < tn) {
-                    const int col = t * 16 + cc;
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        const int row = strip * 16 + Tile<F32>::row(lane, v);
-                        if (row < n && col < r) part += ep(row, col, acc[u][t].get(v));
+    for (int i0 = 0; i0 < n; i0 += RP) {
+        const int tid = tid_here();
+        const int lane = tid & 63, wave = tid >> 6;
+        const int kq = lane >> 4, cc = lane & 15;
+        const int nrow = min(RP, n - i0);
+        const int nsp = (nrow + 15) >> 4;
+        // stage X rows i0 - H .. i0 + RP + H (periodic); in a single pass the halo is copied
+        // from the staged rows afterwards (they may be rewritten by the transform)
+        if (npass == 1) {
+            xform_dispatch(xf, n * rc, n, true, Xs, ldx, H);
+        } else {
+            const float invR = __frcp_rn((float)R);
+            batched_loop<8>(
+                R * rc,
+                [&](int t) {
+                    const int l = fdiv(t, invR);
+                    const int g = wrap_idx(i0 - H + (t - l * R), n);
+                    return ldg(xf.a + g + (int64_t)l * n);
+                },
+                [&](int t, double v) {
+                    const int l = fdiv(t, invR);
+                    Xs[l * ldx + (t - l * R)] = v;
+                });
+        }
+        __syncthreads();
+        if (npass == 1) {
+            // halo rows 0..H-1 and H+n..R-1 from the staged rows
+            const int nh = R - n;
+            const float invh = __frcp_rn((float)max(nh, 1));
+            for (int t = tid; t < nh * rc; t += WG) {
+                const int l = fdiv(t, invh), j = t - l * nh;
+                const int ir = j < H ? j : j + n;
+                Xs[l * ldx + ir] = Xs[l * ldx + H + wrap_idx(ir - H, n)];
+            }
+            if (any_r1) {
+                for (int b = 0; b < nblk; ++b) {
+                    if (comps[b].kind != CP_OP_RANK1) continue;
+                    const double* w = comps[b].data + n;
+                    for (int l = wave; l < rc; l += NWAVES) {
+                        double acc = 0.0;
+                        for (int i = lane; i < n; i += 64) acc = fma(ldg(w + i), Xs[l * ldx + H + i], acc);
+                        acc = wave_sum(acc);
+                        if (lane == 0) s.dots[b * rc + l] = acc;
                     }
                 }
             }
         }
-    }
-    __syncthreads();
-    return part;
-}
-
-// General composite product (any operator kinds, any sizes that fit): the stacked panel
-// chunk is formed from device memory, column by column.
-template <bool F32, int SPW, class EP>
-__device__ __forceinline__ double comp_gemm_chunked(const OpDev* comps, int n, int rc, const double* X, const double* Kt,
-                                    int K, int KCH, const EP& ep) {
-    Smem& s = SMEM;
-    const int r = s.pb.r;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int kq = lane >> 4, cc = lane & 15;
-    const int tm = (n + 15) >> 4, tn = (r + 15) >> 4;
-    const int nw = tn * 16, ldb = nw + 1, ldw = n + 1;
-    double* Ws = s.scratch;
-    double* Bs = s.scratch + ((ldw * KCH + 1) & ~1);
-    const int tpc = min(WG, ((n + 63) / 64) * 64);   // threads per panel column (multiple of 64)
-    const int cpp = WG / tpc;                          // columns per pass
-    const int my_col = threadIdx.x / tpc, my_row = threadIdx.x - my_col * tpc;
-    const float inv_rc = __frcp_rn((float)rc);
-    Tile<F32> acc[SPW][4];
-#pragma unroll
-    for (int u = 0; u < SPW; ++u)
-#pragma unroll
-        for (int t = 0; t < 4; ++t) acc[u][t].zero();
-    for (int kc0 = 0; kc0 < K; kc0 += KCH) {
+        // Kt block 0
+        batched_loop<4>(
+            rc4 * TN * 16,
+            [&](int t) {
+                const int k = t / (TN * 16), j = t - k * (TN * 16);
+                return (k < rc && j < r) ? ldg(Kt + j + (int64_t)k * r) : 0.0;
+            },
+            [&](int t, double v) { KtS[(t / (TN * 16)) * LDB + t % (TN * 16)] = v; });
         __syncthreads();
-        // W chunk: column kk = comp_blk X[:, l] for c = kc0 + kk = blk rc + l (wave-uniform c)
-        if (my_col < cpp) {
-            for (int kk = my_col; kk < KCH; kk += cpp) {
-                const int c = kc0 + kk;
-                double* wcol = Ws + kk * ldw;
-                if (c < K) {
-                    const int blk = (int)(((float)c + 0.5f) * inv_rc);
-                    const int l = c - blk * rc;
-                    const OpDev op = comps[blk];
-                    const double* x = X + (int64_t)l * n;
-                    const double dot = s.dots[blk * rc + l];
-                    for (int i = my_row; i < n; i += tpc) wcol[i] = op_value(op, n, i, x, dot);
-                } else {
-                    for (int i = my_row; i < n; i += tpc) wcol[i] = 0.0;
-                }
+        Tile<F32> acc[SPW][TN];
+#pragma unroll
+        for (int u = 0; u < SPW; ++u)
+#pragma unroll
+            for (int t = 0; t < TN; ++t) acc[u][t].zero();
+        // stencil coefficients of the pass rows for operator block b, CfS[buf][j][row]; a
+        // thread holds at most PFC of them between the load and the LDS store
+        constexpr int PFC = (CG_TAPS * NWAVES * SPW * 16 + WG - 1) / WG;
+        const float invRP = __frcp_rn((float)RP);
+        auto load_cf = [&](int b, double (&cv)[PFC]) {
+            const int kind = comps[b].kind, h = comps[b].hbw;
+            const double* data = comps[b].data;
+            const bool band = kind == CP_OP_BAND;
+            const int nt = (band && h <= 2) ? 2 * h + 1 : 1;
+#pragma unroll
+            for (int u = 0; u < PFC; ++u) {
+                const int t = tid + u * WG;
+                const int j = fdiv(t, invRP), i = i0 + (t - j * RP);
+                double c = 0.0;
+                if (j < nt && i < n && !(band && h > 2)) c = (kind == CP_OP_IDENTITY) ? 1.0 : ldg(data + (int64_t)j * n + i);
+                cv[u] = c;
             }
-        }
-        for (int t = threadIdx.x; t < KCH * nw; t += WG) {
-            const int kk = t / nw, j = t - kk * nw;
-            Bs[kk * ldb + j] = (kc0 + kk < K && j < r) ? ldg(Kt + j + (int64_t)(kc0 + kk) * r) : 0.0;
+        };
+        auto store_cf = [&](int buf, const double (&cv)[PFC]) {
+#pragma unroll
+            for (int u = 0; u < PFC; ++u) {
+                const int t = tid + u * WG;
+                if (t < CG_TAPS * RP) CfS[buf * CG_TAPS * RP + t] = cv[u];
+            }
+        };
+        {
+            double cv[PFC];
+            load_cf(0, cv);
+            store_cf(0, cv);
         }
         __syncthreads();
-        for (int ks = 0; ks < KCH / 4; ++ks) {
-            const int kr = 4 * ks + kq;
-            double b[4];
+        for (int blk = 0; blk < nblk; ++blk) {
+            const int cur = blk & 1;
+            const bool more = blk + 1 < nblk;
+            double pf[PF], pc[PFC];
 #pragma unroll
-            for (int t = 0; t < 4; ++t) b[t] = (t < tn) ? Bs[kr * ldb + t * 16 + cc] : 0.0;
-#pragma unroll
-            for (int u = 0; u < SPW; ++u) {
-                const int strip = wave + NWAVES * u;
-                if (strip < tm) {
-                    const int i = strip * 16 + cc;
-                    const double a = (i < n) ? Ws[kr * ldw + i] : 0.0;
-#pragma unroll
-                    for (int t = 0; t < 4; ++t)
-                        if (t < tn) acc[u][t].step(a, b[t]);
-                }
+            for (int u = 0; u < PF; ++u) {
+                const int t = tid + u * WG;
+                const int k = t / (TN * 16), j = t - k * (TN * 16);
+                pf[u] = (more && k < rc && j < r) ? ldg(Kt + j + (int64_t)((blk + 1) * rc + k) * r) : 0.0;
             }
+            if (more) load_cf(blk + 1, pc);
+            const int kind = ufirst(comps[blk].kind);
+            const int h = ufirst(comps[blk].hbw);
+            const double* data = comps[blk].data;
+            const bool r1 = kind == CP_OP_RANK1;
+            const bool band = kind == CP_OP_BAND;
+            const bool fast = !band || h <= 2;
+            const int nt = band ? 2 * h + 1 : 1;
+            const int off0 = band ? H - h : H;
+            const double* bsrc = KtS + cur * ktsz;
+            double cf[SPW][CG_TAPS];
+#pragma unroll
+            for (int u = 0; u < SPW; ++u)
+#pragma unroll
+                for (int j = 0; j < CG_TAPS; ++j)
+                    cf[u][j] = (j < nt && wave + NWAVES * u < nsp) ? CfS[(cur * CG_TAPS + j) * RP + (wave + NWAVES * u) * 16 + cc] : 0.0;
+            // one k-step: every lane forms the A elements of its strips (all LDS reads of the
+            // step in flight together), then the matrix-core steps.  The tap count is fixed per
+            // operator block, so the loop is instantiated per stencil width.
+            auto ksteps = [&](auto ntap_c) {
+                constexpr int NTAP = decltype(ntap_c)::value;
+                constexpr int NV = NTAP > 0 ? NTAP : 1;
+                // operands of one k-step: B fragments and the taps of every strip
+                auto load_step = [&](int ks, double (&b)[TN], double (&xv)[SPW][NV]) {
+                    const int l = min(ks + kq, rc - 1);
+#pragma unroll
+                    for (int t = 0; t < TN; ++t) b[t] = bsrc[(ks + kq) * LDB + t * 16 + cc];
+#pragma unroll
+                    for (int u = 0; u < SPW; ++u) {
+                        if (NTAP == 0) {
+                            xv[u][0] = s.dots[blk * rc + l];   // rank-1 block: m_i (w^T X[:, l])
+                        } else if (NTAP > 0) {
+                            const double* xr = Xs + l * ldx + (wave + NWAVES * u) * 16 + cc + off0;
+#pragma unroll
+                            for (int j = 0; j < NV; ++j) xv[u][j] = xr[j];
+                        } else {
+                            const int strip = wave + NWAVES * u;
+                            const int i = i0 + strip * 16 + cc;
+                            double v = 0.0;
+                            if (i < n && strip < nsp) {
+                                const double* xr = Xs + l * ldx + strip * 16 + cc + off0;
+                                for (int j = 0; j < nt; ++j) v = fma(ldg(data + (int64_t)j * n + i), xr[j], v);
+                            }
+                            xv[u][0] = v;
+                        }
+                    }
+                };
+                double bc[TN], xc[SPW][NV];
+                load_step(0, bc, xc);
+                for (int ks = 0; ks < rc4; ks += 4) {
+                    // the next step's LDS reads are issued before this step's matrix-core work
+                    double bn[TN], xn[SPW][NV];
+                    load_step(min(ks + 4, rc4 - 4), bn, xn);
+                    const bool lv = ks + kq < rc;
+#pragma unroll
+                    for (int u = 0; u < SPW; ++u) {
+                        double a = 0.0;
+                        if (NTAP > 0) {
+#pragma unroll
+                            for (int j = 0; j < NV; ++j) a = fma(cf[u][j], xc[u][j], a);
+                        } else if (NTAP == 0) {
+                            a = cf[u][0] * xc[u][0];
+                        } else {
+                            a = xc[u][0];
+                        }
+                        a = lv ? a : 0.0;
+                        if (wave + NWAVES * u < nsp) {
+                            // operands swapped: the tile holds out^T, so a lane's four results
+                            // are four columns of sixteen consecutive rows (coalesced stores)
+#pragma unroll
+                            for (int t = 0; t < TN; ++t) acc[u][t].step(bc[t], a);
+                        }
+                    }
+#pragma unroll
+                    for (int t = 0; t < TN; ++t) bc[t] = bn[t];
+#pragma unroll
+                    for (int u = 0; u < SPW; ++u)
+#pragma unroll
+                        for (int j = 0; j < NV; ++j) xc[u][j] = xn[u][j];
+                }
+            };
+            if (r1) ksteps(std::integral_constant<int, 0>{});
+            else if (!fast) ksteps(std::integral_constant<int, -1>{});
+            else if (nt == 1) ksteps(std::integral_constant<int, 1>{});
+            else if (nt == 3) ksteps(std::integral_constant<int, 3>{});
+            else ksteps(std::integral_constant<int, 5>{});
+            if (more) {
+#pragma unroll
+                for (int u = 0; u < PF; ++u) {
+                    const int t = tid + u * WG;
+                    if (t < rc4 * TN * 16) {
+                        const int k = t / (TN * 16), j = t - k * (TN * 16);
+                        KtS[(cur ^ 1) * ktsz + k * LDB + j] = pf[u];
+                    }
+                }
+                store_cf(cur ^ 1, pc);
+            }
+            __syncthreads();
         }
-    }
-    double part = 0.0;
+        // epilogue
 #pragma unroll
-    for (int u = 0; u < SPW; ++u) {
-        const int strip = wave + NWAVES * u;
-        if (strip < tm) {
+        for (int u = 0; u < SPW; ++u) {
+            const int strip = wave + NWAVES * u;
+            if (strip < nsp) {
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                if (t < tn) {
-                    const int col = t * 16 + cc;
+                for (int t = 0; t < TN; ++t) {
+                    const int lr = strip * 16 + cc;
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
-                        const int row = strip * 16 + Tile<F32>::row(lane, v);
-                        if (row < n && col < r) part += ep(row, col, acc[u][t].get(v));
+                        const int col = t * 16 + Tile<F32>::row(lane, v);
+                        if (lr < nrow && col < r) {
+                            double val = acc[u][t].get(v);
+                            if (shift || dot) {
+                                const double xv = Xs[col * ldx + H + lr];
+                                if (shift) val = fma(lam, xv, val);
+                                if (dot) part = fma(xv, val, part);
+                            }
+                            stg(out + (i0 + lr) + (int64_t)col * n, val);
+                        }
                     }
                 }
             }
         }
-    }
-    __syncthreads();
-    return part;
-}
-
-// ------------------------------------------------------------------------------------
-// Composite product  out = sum_blk comp_blk X (K^blk)^T  on the matrix cores:
-// the stacked panel W[:, blk rc + l] = comp_blk X[:, l] is formed chunk by chunk in LDS
-// (wave-uniform columns), K^blk are the r x rc blocks of Kt (Kt[l + (blk rc + l') r]).
-// ------------------------------------------------------------------------------------
-template <bool F32, class EP>
-__device__ __forceinline__ double comp_gemm(const OpDev* comps, int nblk, int n, int rc, const double* X,
-                            const double* Kt, const EP& ep) {
-    Smem& s = SMEM;
-    const int r = s.pb.r;
-    const int K = nblk * rc;
-    const int tm = (n + 15) >> 4;
-    {
-        // fast path: five-tap composites, chunks of KCH <= rc columns, everything in LDS
-        bool five = n >= 3 && rc >= 4 && tm <= 4 * NWAVES;
-        for (int b = 0; b < nblk; ++b)
-            five = five && (comps[b].kind == CP_OP_IDENTITY || comps[b].kind == CP_OP_DIAG ||
-                            (comps[b].kind == CP_OP_BAND && comps[b].hbw <= 2));
-        const int KCHf = min(16, rc & ~3);
-        const int ldbf = ((r + 15) >> 4) * 16 + 1;
-        const int need = ((n * rc + 1) & ~1) + (((n + 1) * KCHf + 1) & ~1) + ((ldbf * KCHf + 1) & ~1) + 10 * n;
-        if (five && need <= SCRATCH) {
-            if (tm <= NWAVES) return comp_gemm_fast<F32, 1>(comps, nblk, n, rc, X, Kt, KCHf, ep);
-            if (tm <= 2 * NWAVES) return comp_gemm_fast<F32, 2>(comps, nblk, n, rc, X, Kt, KCHf, ep);
-            return comp_gemm_fast<F32, 4>(comps, nblk, n, rc, X, Kt, KCHf, ep);
-        }
-    }
-    for (int b = 0; b < nblk; ++b)
-        if (comps[b].kind == CP_OP_RANK1) wg_coldots(n, rc, comps[b].data + n, X, n, s.dots + b * rc);
-    const int ldb = ((r + 15) >> 4) * 16 + 1;
-    int KCH = 32;
-    while (KCH >= 4 && (n + 1) * KCH + 2 + KCH * ldb > SCRATCH) KCH >>= 1;
-    if (KCH >= 4 && tm <= 4 * NWAVES) {
-        if (tm <= NWAVES) return comp_gemm_chunked<F32, 1>(comps, n, rc, X, Kt, K, KCH, ep);
-        if (tm <= 2 * NWAVES) return comp_gemm_chunked<F32, 2>(comps, n, rc, X, Kt, K, KCH, ep);
-        return comp_gemm_chunked<F32, 4>(comps, n, rc, X, Kt, K, KCH, ep);
-    }
-    OpApplyF af{comps, n, rc, X, s.dots};
-    return panel_gemm<F32, 4, 2>(n, r, K, af, Kt, r, ep, s.scratch);
-}
-
-// w = (M_q + lam I) p written to w; returns <p, w>.
-struct ShiftDotEp {
-    double* w;
-    const double* p;
-    double lam;
-    int ld;
-    __device__ __forceinline__ double operator()(int row, int col, double v) const {
-        const int64_t o = row + (int64_t)col * ld;
-        const double pv = ldg(p + o);
-        const double wv = fma(lam, pv, v);
-        stg(w + o, wv);
-        return pv * wv;
-    }
-};
-
-__device__ __forceinline__ double matvec(int q, double lam, const double* p, double* w, bool lowp) {
-    Smem& s = SMEM;
-    const Problem& pb = s.pb;
-    const int n = pb.n[q], r = pb.r, m = pb.mA[q];
-    const double part = lowp ? comp_gemm<true>(pb.compAA[q], m * m, n, r, p, pb.Cm, ShiftDotEp{w, p, lam, n})
-                             : comp_gemm<false>(pb.compAA[q], m * m, n, r, p, pb.Cm, ShiftDotEp{w, p, lam, n});
-    return wg_sum(part, s.red);
-}
-
-// z = r Hinv (each grid row times the symmetric Hinv); returns <r, z>.
-struct StoreDotEp {
-    double* z;
-    const double* rv;
-    int ld;
-    __device__ __forceinline__ double operator()(int row, int col, double v) const {
-        const int64_t o = row + (int64_t)col * ld;
-        stg(z + o, v);
-        return ldg(rv + o) * v;
-    }
-};
-
-__device__ __forceinline__ double precond(int n, const double* rv, double* zv) {
-    Smem& s = SMEM;
-    const Problem& pb = s.pb;
-    const int r = pb.r;
-    const double part = panel_gemm<false, 4, 2>(n, r, r, PanelA{rv, n}, pb.Hinv, r, StoreDotEp{zv, rv, n}, s.scratch);
-    return wg_sum(part, s.red);
-}
-
-// ------------------------------------------------------------------------------------
-// one dimension update; returns ||Delta f_q||^2 and accumulates pcg iterations / flags
-// ------------------------------------------------------------------------------------
-// lowp: the Gram, right-hand-side and matvec contractions on FP32 matrix cores (the
-// mixed-precision form); the preconditioner, the increment and all scalars stay FP64.
-__device__ __forceinline__ double update_dim(int q, int r0, int& pcg_iters, uint32_t& flags, bool lowp) {
-    Smem& s = SMEM;
-    const Problem& pb = s.pb;
-    const int n = pb.n[q], r = pb.r, m = pb.mA[q], mb = pb.mB[q];
-    const int nr = n * r;
-    double* Uq = pb.U + pb.offU[q];
-
-    const double trM = assemble(q, r0);
-    const double lam = pb.eps_reg * trM / (double)nr;
-
-    // right-hand side b = sum_{a,b'} (O_A^a)^T O_B^b' V_q (D^{a b'})^T
-    if (lowp) comp_gemm<true>(pb.compAB[q], m * mb, n, r0, pb.V + pb.offV[q], pb.Dm, StoreEp{pb.vb, n});
-    else comp_gemm<false>(pb.compAB[q], m * mb, n, r0, pb.V + pb.offV[q], pb.Dm, StoreEp{pb.vb, n});
-
-    flags |= factor_precond(lam);
-
-    // PCG from the current factor
-    double* x = pb.vx;
-    double* rv = pb.vr;
-    double* z = pb.vz;
-    double* p = pb.vp;
-    double* w = pb.vw;
-    for (int t = threadIdx.x; t < nr; t += WG) stg(x + t, ldg(Uq + t));
-    __syncthreads();
-    // Stopping test in the preconditioned (energy-like) norm: r^T P^{-1} r <= tol^2 b^T P^{-1} b.
-    // Since P ~ J_q^T J_q, this bounds the change of the represented tensor, also along
-    // near-singular directions of H_q where the plain residual norm says little.
-    const double bz = precond(n, pb.vb, z);
-    matvec(q, lam, x, w, lowp);
-    for (int t = threadIdx.x; t < nr; t += WG) stg(rv + t, ldg(pb.vb + t) - ldg(w + t));
-    __syncthreads();
-    double rz = precond(n, rv, z);
-    // FP32 contractions cannot resolve the system below ~1e-7; the FP64 sweeps finish it
-    const double ptol = lowp ? fmax(pb.pcg_tol, 1e-6) : pb.pcg_tol;
-    const double stop = ptol * ptol * bz;
-    int it = 0;
-    if (rz > stop) {
-        for (int t = threadIdx.x; t < nr; t += WG) stg(p + t, ldg(z + t));
         __syncthreads();
-        for (it = 1; it <= pb.pcg_max; ++it) {
-            const double pw = matvec(q, lam, p, w, lowp);
-            const double alpha = rz / pw;
-            for (int t = threadIdx.x; t < nr; t += WG) {
-                stg(x + t, fma(alpha, ldg(p + t), ldg(x + t)));
-                stg(rv + t, fma(-alpha, ldg(w + t), ldg(rv + t)));
-            }
-            __syncthreads();
-            const double rzn = precond(n, rv, z);
-            if (rzn <= stop || !(pw > 0.0)) break;
-            const double beta = rzn / rz;
-            rz = rzn;
-            for (int t = threadIdx.x; t < nr; t += WG) stg(p + t, fma(beta, ldg(p + t), ldg(z + t)));
-            __syncthreads();
-        }
-        if (it > pb.pcg_max) {
-            flags |= CP_FLAG_PCG_MAXITER;
-            it = pb.pcg_max;
-        }
     }
-    pcg_iters += it;
-
-    // ||Delta f_q||^2 = sum((dU^T dU) o H0), dU = x - U_q; then U_q <- x
-    gram_lds<false>(n, r, 0, DiffF{x, Uq, n}, DiffF{x, Uq, n}, pb.S, r, nullptr, 0, s.scratch);
-    for (int t = threadIdx.x; t < nr; t += WG) stg(Uq + t, ldg(x + t));
-    __syncthreads();
-    double part = 0.0;
-    for (int t = threadIdx.x; t < r * r; t += WG) part = fma(pb.S[t], pb.H0[t], part);
-    const double delta2 = wg_sum(part, s.red);
-    refresh_dim(q, r0, lowp);
-    return delta2;
+    return part;
 }
 
 // ------------------------------------------------------------------------------------
@@ -837,13 +837,16 @@ __device__ __forceinline__ double update_dim(int q, int r0, int& pcg_iters, uint
 __device__ __forceinline__ void panel_colnorms() {
     Smem& s = SMEM;
     const Problem& pb = s.pb;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = tid_here() & 63, wave = tid_here() >> 6;
     const int r = pb.r;
     for (int kl = wave; kl < pb.d * r; kl += NWAVES) {
         const int k = kl / r, l = kl % r;
         const double* u = pb.U + pb.offU[k] + (int64_t)l * pb.n[k];
         double acc = 0.0;
-        for (int i = lane; i < pb.n[k]; i += 64) acc = fma(u[i], u[i], acc);
+        for (int i = lane; i < pb.n[k]; i += 64) {
+            const double v = ldg(u + i);
+            acc = fma(v, v, acc);
+        }
         acc = wave_sum(acc);
         if (lane == 0) s.colnorm[kl] = sqrt(acc);
     }
@@ -855,10 +858,10 @@ __device__ __forceinline__ void gram_colnorms() {
     Smem& s = SMEM;
     const Problem& pb = s.pb;
     const int r = pb.r;
-    for (int kl = threadIdx.x; kl < pb.d * r; kl += WG) {
+    for (int kl = tid_here(); kl < pb.d * r; kl += WG) {
         const int k = kl / r, l = kl % r;
         const int ld = pb.mA[k] * r;
-        s.colnorm[kl] = sqrt(fmax(pb.G[pb.offG[k] + (int64_t)l * ld + l], 0.0));
+        s.colnorm[kl] = sqrt(fmax(ldg(pb.G + pb.offG[k] + (int64_t)l * ld + l), 0.0));
     }
     __syncthreads();
 }
@@ -868,7 +871,7 @@ __device__ __forceinline__ void balance_scales() {
     Smem& s = SMEM;
     const Problem& pb = s.pb;
     const int r = pb.r, d = pb.d;
-    for (int l = threadIdx.x; l < r; l += WG) {
+    for (int l = tid_here(); l < r; l += WG) {
         bool zero = false;
         double lsum = 0.0;
         for (int k = 0; k < d; ++k) {
@@ -892,12 +895,14 @@ __device__ __forceinline__ void scale_panels() {
     for (int k = 0; k < pb.d; ++k) {
         const int n = pb.n[k];
         double* u = pb.U + pb.offU[k];
-        for (int t = threadIdx.x; t < n * r; t += WG) u[t] *= s.colnorm[k * r + t / n];
+        const float invn = __frcp_rn((float)n);
+        batched_loop<8>(n * r, [&](int t) { return ldg(u + t); },
+                        [&](int t, double v) { stg(u + t, v * s.colnorm[k * r + fdiv(t, invn)]); });
     }
     __syncthreads();
 }
 
-// After a sweep: rescale panels and, consistently, the Grams and cross-Grams.
+// After a sweep: rescale the Grams and cross-Grams consistently with the panels.
 __device__ __forceinline__ void scale_grams(int r0) {
     Smem& s = SMEM;
     const Problem& pb = s.pb;
@@ -906,13 +911,20 @@ __device__ __forceinline__ void scale_grams(int r0) {
         const int ld = pb.mA[k] * r;
         const double* sc = s.colnorm + k * r;
         double* G = pb.G + pb.offG[k];
-        for (int t = threadIdx.x; t < ld * ld; t += WG) {
-            const int i = t % ld, j = t / ld;
-            G[t] *= sc[i % r] * sc[j % r];
-        }
+        const float invld = __frcp_rn((float)ld), invr = __frcp_rn((float)r);
+        auto modr = [&](int v) { return v - fdiv(v, invr) * r; };
+        batched_loop<8>(ld * ld, [&](int t) { return ldg(G + t); },
+                        [&](int t, double v) {
+                            const int j = fdiv(t, invld), i = t - j * ld;
+                            stg(G + t, v * sc[modr(i)] * sc[modr(j)]);
+                        });
         double* X = pb.X + pb.offX[k];
         const int nx = ld * pb.mB[k] * r0;
-        for (int t = threadIdx.x; t < nx; t += WG) X[t] *= sc[(t % ld) % r];
+        batched_loop<8>(nx, [&](int t) { return ldg(X + t); },
+                        [&](int t, double v) {
+                            const int j = fdiv(t, invld), i = t - j * ld;
+                            stg(X + t, v * sc[modr(i)]);
+                        });
     }
     __syncthreads();
 }
@@ -920,63 +932,197 @@ __device__ __forceinline__ void scale_grams(int r0) {
 // ------------------------------------------------------------------------------------
 // the persistent kernel
 // ------------------------------------------------------------------------------------
+enum : int { OP_STEP, OP_REFRESH, OP_UPDATE, OP_CG, OP_DELTA, OP_SWEEP, OP_REPORT, OP_DONE };
+// phases of one dimension update's composite products
+enum : int { PH_RHS, PH_PRE_B, PH_MV_X, PH_PRE_R0, PH_MV_P0, PH_PRE_R, PH_MV_P };
+
 __global__ void __launch_bounds__(WG) als_persistent(const Problem* __restrict__ problems, int count) {
     Smem& s = SMEM;
     const int pid = blockIdx.x;
     if (pid >= count) return;
-    // problem descriptor -> LDS
     {
         const uint32_t* src = reinterpret_cast<const uint32_t*>(problems + pid);
         uint32_t* dst = reinterpret_cast<uint32_t*>(&s.pb);
-        for (int t = threadIdx.x; t < (int)(sizeof(Problem) / 4); t += WG) dst[t] = src[t];
+        for (int t = tid_here(); t < (int)(sizeof(Problem) / 4); t += WG) dst[t] = src[t];
+        if (tid_here() == 0) {
+            s.ident.kind = CP_OP_IDENTITY;
+            s.ident.hbw = 0;
+            s.ident.data = nullptr;
+        }
     }
     __syncthreads();
     const Problem& pb = s.pb;
-    const int d = pb.d, r = pb.r;
-    int64_t total_u = 0;
-    for (int k = 0; k < d; ++k) total_u += (int64_t)pb.n[k] * r;
+    const int d = ufirst(pb.d), r = ufirst(pb.r);
+    const int n_steps = ufirst(pb.n_steps), max_sweeps = ufirst(pb.max_sweeps);
+    const bool mixed = pb.precision == CP_PREC_MIXED;
+    // mixed-precision form: sweeps with FP32 contractions until the increment reaches the
+    // FP32 floor (or the sweep budget is nearly spent), then one FP64 refinement sweep
+    // (with tol = 0 the caller asks for exactly max_sweeps sweeps: FP32 until the last one)
+    const double tol_low = pb.tol > 0.0 ? fmax(pb.tol, 1e-6) : 0.0;
 
-    for (int step = 0; step < pb.n_steps; ++step) {
-        const int r0 = (step == 0) ? pb.r0 : r;
-        if (step > 0) {
-            // f_n <- previous result (same packed layout, rank r)
-            for (int k = 0; k < d; ++k) {
-                const int64_t cnt = (int64_t)pb.n[k] * r;
-                for (int64_t t = threadIdx.x; t < cnt; t += WG) pb.V[pb.offV[k] + t] = pb.U[pb.offU[k] + t];
-            }
-            __syncthreads();
-        }
-        for (int k = 0; k < d; ++k) compute_Q(k, r0);
-        panel_colnorms();
-        balance_scales();
-        scale_panels();
-        // mixed-precision form: sweeps with FP32 contractions until the increment reaches the
-        // FP32 floor (or the sweep budget is nearly spent), then one FP64 refinement sweep
-        const bool mixed = pb.precision == CP_PREC_MIXED;
-        bool lowp = mixed && pb.max_sweeps > 1;
-        // (with tol = 0 the caller asks for exactly max_sweeps sweeps: FP32 until the last one)
-        const double tol_low = pb.tol > 0.0 ? fmax(pb.tol, 1e-6) : 0.0;
-        for (int k = 0; k < d; ++k) refresh_dim(k, r0, lowp);
+    int op = OP_STEP;
+    int step = 0, r0 = 0, q = 0, k = 0, k_end = 0, after = OP_UPDATE, sw = 1, ph = PH_RHS, it = 0;
+    int pcg_iters = 0;
+    uint32_t flags = 0;
+    bool lowp = false;
+    double lam = 0.0, bz = 0.0, stop = 0.0, rz = 0.0, pw = 0.0, alpha = 0.0, beta = 0.0;
+    double dmax2 = 0.0, eps = 0.0, fnorm = 0.0;
 
-        int sweeps = 0, pcg_iters = 0;
-        uint32_t flags = CP_FLAG_NOT_CONVERGED;
-        double eps = 0.0, fnorm = 0.0;
-        for (int sw = 1; sw <= pb.max_sweeps; ++sw) {
-            const bool was_low = lowp;
-            double dmax2 = 0.0;
-            for (int q = 0; q < d; ++q) {
-                const double d2 = update_dim(q, r0, pcg_iters, flags, lowp);
-                dmax2 = fmax(dmax2, d2);
+    while (op != OP_DONE) {
+        op = ufirst(op);
+        if (op == OP_STEP) {
+            r0 = (step == 0) ? pb.r0 : r;
+            if (step > 0) {
+                // f_n <- previous result (same packed layout, rank r)
+                for (int kk = 0; kk < d; ++kk) {
+                    const double* src = pb.U + pb.offU[kk];
+                    double* dst = pb.V + pb.offV[kk];
+                    batched_loop<8>(pb.n[kk] * r, [&](int t) { return ldg(src + t); }, [&](int t, double v) { stg(dst + t, v); });
+                }
+                __syncthreads();
             }
+            compute_Q_all(r0);
+            panel_colnorms();
+            balance_scales();
+            scale_panels();
+            lowp = mixed && max_sweeps > 1;
+            pcg_iters = 0;
+            flags = CP_FLAG_NOT_CONVERGED;
+            eps = fnorm = dmax2 = 0.0;
+            sw = 1;
+            q = 0;
+            k = 0;
+            k_end = d;
+            after = OP_UPDATE;
+            op = OP_REFRESH;
+        } else if (op == OP_REFRESH) {
+            refresh_dim(k, r0, lowp);
+            ++k;
+            if (k >= k_end) op = after;
+        } else if (op == OP_UPDATE) {
+            const double trM = assemble(q, r0);
+            lam = ufirst(pb.eps_reg * trM / (double)(pb.n[q] * r));
+            ph = PH_RHS;
+            op = OP_CG;
+        } else if (op == OP_CG) {
+            const int n = ufirst(pb.n[q]);
+            const int m = pb.mA[q];
+            const int64_t oq = pb.offU[q];
+            const bool mv = ph == PH_MV_X || ph == PH_MV_P0 || ph == PH_MV_P;
+            const bool pre = ph == PH_PRE_B || ph == PH_PRE_R0 || ph == PH_PRE_R;
+            const OpDev* comps = pre ? &s.ident : (mv ? pb.compAA[q] : pb.compAB[q]);
+            const int nblk = pre ? 1 : (mv ? m * m : m * pb.mB[q]);
+            const int rc = ph == PH_RHS ? r0 : r;
+            const double* Kt = pre ? pb.Hinv : (mv ? pb.Cm : pb.Dm);
+            double* outp = pre ? pb.vz : (mv ? pb.vw : pb.vb);
+            Xform xf{nullptr, nullptr, 0.0, nullptr, nullptr, nullptr, 0.0};
+            switch (ph) {
+                case PH_RHS: xf.a = pb.V + pb.offV[q]; break;
+                case PH_PRE_B: xf.a = pb.vb; break;
+                case PH_MV_X: xf.a = pb.U + oq; xf.wv = pb.vx; break;                 // x <- U_q
+                case PH_PRE_R0: xf.a = pb.vb; xf.b = pb.vw; xf.beta = -1.0; xf.wv = pb.vr; break;  // r = b - A x
+                case PH_MV_P0: xf.a = pb.vz; xf.wv = pb.vp; break;                    // p = z
+                case PH_PRE_R:                                                        // r -= alpha w, x += alpha p
+                    xf.a = pb.vr; xf.b = pb.vw; xf.beta = -alpha; xf.wv = pb.vr;
+                    xf.x2 = pb.vx; xf.p2 = pb.vp; xf.alpha2 = alpha;
+                    break;
+                default: xf.a = pb.vz; xf.b = pb.vp; xf.beta = beta; xf.wv = pb.vp; break;  // p = z + beta p
+            }
+            const bool dot = ph != PH_RHS && ph != PH_MV_X;
+            const bool f32 = lowp && !pre;
+            const int tn = (r + 15) >> 4;
+            double part;
+            if (f32) {
+                if (tn == 1) part = cgemm<true, 1>(n, r, comps, nblk, rc, xf, Kt, outp, lam, mv, dot);
+                else if (tn == 2) part = cgemm<true, 2>(n, r, comps, nblk, rc, xf, Kt, outp, lam, mv, dot);
+                else part = cgemm<true, 4>(n, r, comps, nblk, rc, xf, Kt, outp, lam, mv, dot);
+            } else {
+                if (tn == 1) part = cgemm<false, 1>(n, r, comps, nblk, rc, xf, Kt, outp, lam, mv, dot);
+                else if (tn == 2) part = cgemm<false, 2>(n, r, comps, nblk, rc, xf, Kt, outp, lam, mv, dot);
+                else part = cgemm<false, 4>(n, r, comps, nblk, rc, xf, Kt, outp, lam, mv, dot);
+            }
+            const double val = ufirst(wg_sum(part, s.red));
+            bool finish = false;
+            switch (ph) {
+                case PH_RHS:
+                    flags |= factor_precond(lam);
+                    ph = PH_PRE_B;
+                    break;
+                case PH_PRE_B:
+                    bz = val;
+                    ph = PH_MV_X;
+                    break;
+                case PH_MV_X:
+                    ph = PH_PRE_R0;
+                    break;
+                case PH_PRE_R0: {
+                    // Stopping test in the preconditioned (energy-like) norm:
+                    // r^T P^{-1} r <= tol^2 b^T P^{-1} b.  Since P ~ J_q^T J_q it bounds the
+                    // change of the represented tensor, also along near-singular directions.
+                    // FP32 contractions cannot resolve the system below ~1e-7; the FP64
+                    // sweeps finish it.
+                    rz = val;
+                    const double ptol = lowp ? fmax(pb.pcg_tol, 1e-6) : pb.pcg_tol;
+                    stop = ptol * ptol * bz;
+                    it = 0;
+                    if (rz <= stop) finish = true;
+                    else ph = PH_MV_P0;
+                    break;
+                }
+                case PH_MV_P0:
+                case PH_MV_P:
+                    pw = val;
+                    ++it;
+                    alpha = rz / pw;
+                    ph = PH_PRE_R;
+                    break;
+                case PH_PRE_R: {
+                    const double rzn = val;
+                    if (rzn <= stop || !(pw > 0.0)) {
+                        finish = true;
+                    } else if (it >= pb.pcg_max) {
+                        flags |= CP_FLAG_PCG_MAXITER;
+                        finish = true;
+                    } else {
+                        beta = rzn / rz;
+                        rz = rzn;
+                        ph = PH_MV_P;
+                    }
+                    break;
+                }
+                default: break;
+            }
+            if (finish) {
+                pcg_iters += it;
+                op = OP_DELTA;
+            }
+        } else if (op == OP_DELTA) {
+            // ||Delta f_q||^2 = sum((dU^T dU) o H0), dU = x - U_q; then U_q <- x
+            const int n = pb.n[q];
+            double* Uq = pb.U + pb.offU[q];
+            gram_lds<false>(n, r, 0, DiffF{pb.vx, Uq, n}, DiffF{pb.vx, Uq, n}, pb.S, r, nullptr, 0, s.scratch, SCRATCH);
+            batched_loop<8>(n * r, [&](int t) { return ldg(pb.vx + t); }, [&](int t, double v) { stg(Uq + t, v); });
+            double part = 0.0;
+            for (int t = tid_here(); t < r * r; t += WG) part = fma(ldg(pb.S + t), ldg(pb.H0 + t), part);
+            const double delta2 = ufirst(wg_sum(part, s.red));   // its barriers also publish U_q
+            dmax2 = fmax(dmax2, delta2);
+            k = q;
+            k_end = q + 1;
+            after = (q + 1 < d) ? OP_UPDATE : OP_SWEEP;
+            q = q + 1;
+            op = OP_REFRESH;
+        } else if (op == OP_SWEEP) {
             // ||f||^2 = sum o_k U_k^T U_k
             double part = 0.0;
-            for (int t = threadIdx.x; t < r * r; t += WG) {
+            for (int t = tid_here(); t < r * r; t += WG) {
                 const int l = t % r, lp = t / r;
                 double prod = 1.0;
-                for (int k = 0; k < d; ++k) prod *= pb.G[pb.offG[k] + (int64_t)lp * (pb.mA[k] * r) + l];
+#pragma unroll
+                for (int kk = 0; kk < CP_MAX_DIMS; ++kk)
+                    if (kk < d) prod *= ldg(pb.G + pb.offG[kk] + (int64_t)lp * (pb.mA[kk] * r) + l);
                 part += prod;
             }
-            const double f2 = wg_sum(part, s.red);
+            const double f2 = ufirst(wg_sum(part, s.red));
             fnorm = sqrt(fmax(f2, 0.0));
             const double dmax = sqrt(fmax(dmax2, 0.0));
             eps = fnorm > 0.0 ? dmax / fnorm : dmax;
@@ -984,45 +1130,67 @@ __global__ void __launch_bounds__(WG) als_persistent(const Problem* __restrict__
             balance_scales();
             scale_panels();
             scale_grams(r0);
-            sweeps = sw;
+            const bool was_low = lowp;
+            bool refresh_all = false;
+            bool done = false;
             if (!isfinite(eps)) {
                 flags |= CP_FLAG_NONFINITE;
-                break;
-            }
-            if (was_low) {
-                if (eps <= tol_low || sw + 1 >= pb.max_sweeps) {
+                done = true;
+            } else if (was_low) {
+                if (eps <= tol_low || sw + 1 >= max_sweeps) {
                     // switch to FP64: recompute every Gram in FP64, then the refinement sweep
                     lowp = false;
-                    for (int k = 0; k < d; ++k) refresh_dim(k, r0, false);
+                    refresh_all = true;
                 }
-                continue;
-            }
-            if (eps <= pb.tol) {
+            } else if (eps <= pb.tol) {
                 flags &= ~CP_FLAG_NOT_CONVERGED;
-                break;
+                done = true;
+            } else if (mixed) {
+                done = true;   // the single FP64 refinement sweep is done
             }
-            if (mixed) break;   // the single FP64 refinement sweep is done
-        }
-        if (threadIdx.x == 0) {
-            cp_als_report rep;
-            rep.sweeps = sweeps;
-            rep.pcg_iters = pcg_iters;
-            rep.eps_conv = eps;
-            rep.fnorm = fnorm;
-            rep.flags = flags;
-            rep.reserved = 0;
-            pb.reports[step] = rep;
-        }
-        if (pb.traj) {
-            double* dst = pb.traj + (int64_t)step * total_u;
-            int64_t o = 0;
-            for (int k = 0; k < d; ++k) {
-                const int64_t cnt = (int64_t)pb.n[k] * r;
-                for (int64_t t = threadIdx.x; t < cnt; t += WG) dst[o + t] = pb.U[pb.offU[k] + t];
-                o += cnt;
+            if (done || sw >= max_sweeps) {
+                op = OP_REPORT;
+            } else {
+                ++sw;
+                q = 0;
+                dmax2 = 0.0;
+                if (refresh_all) {
+                    k = 0;
+                    k_end = d;
+                    after = OP_UPDATE;
+                    op = OP_REFRESH;
+                } else {
+                    op = OP_UPDATE;
+                }
             }
+        } else {   // OP_REPORT
+            if (tid_here() == 0) {
+                cp_als_report rep;
+                rep.sweeps = sw;
+                rep.pcg_iters = pcg_iters;
+                rep.eps_conv = eps;
+                rep.fnorm = fnorm;
+                rep.flags = flags;
+                rep.reserved = 0;
+                pb.reports[step] = rep;
+            }
+            if (pb.traj) {
+                double* dst = pb.traj + (int64_t)step * [&] {
+                    int64_t tot = 0;
+                    for (int kk = 0; kk < d; ++kk) tot += (int64_t)pb.n[kk] * r;
+                    return tot;
+                }();
+                int64_t o = 0;
+                for (int kk = 0; kk < d; ++kk) {
+                    const int64_t cnt = (int64_t)pb.n[kk] * r;
+                    for (int64_t t = tid_here(); t < cnt; t += WG) stg(dst + o + t, ldg(pb.U + pb.offU[kk] + t));
+                    o += cnt;
+                }
+            }
+            __syncthreads();
+            ++step;
+            op = (step < n_steps) ? OP_STEP : OP_DONE;
         }
-        __syncthreads();
     }
 }
 

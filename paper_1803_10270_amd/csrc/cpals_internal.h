@@ -5,7 +5,8 @@
 
 namespace cpals {
 
-constexpr int WG = 512;           // threads of the persistent ALS workgroup (8 waves)
+constexpr int WG = 256;           // threads of the persistent ALS workgroup (4 waves: one per SIMD,
+                                  // so each wave may hold 512 registers, accumulators in AGPRs)
 constexpr int NWAVES = WG / 64;
 
 // One distinct 1-D operator on the device.

@@ -27,10 +27,42 @@ __device__ __forceinline__ double wave_max(double v) {
     return v;
 }
 
+// threadIdx.x through an opaque move: index arithmetic derived from it is recomputed where
+// it is used instead of being hoisted out of the persistent loops (where it would occupy
+// registers for the whole kernel).
+__device__ __forceinline__ int tid_here() {
+    int t;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(t) : "v"((int)threadIdx.x));
+    return t;
+}
+
+// Batched element loop over t < total (grid-stride over the workgroup): U loads are issued
+// before any result is consumed, so their latencies overlap.  ld(t) -> value, st(t, value).
+template <int U, class LD, class ST>
+__device__ __forceinline__ void batched_loop(int total, const LD& ld, const ST& st) {
+    for (int t0 = tid_here(); t0 < total; t0 += U * WG) {
+        double v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int t = t0 + u * WG;
+            v[u] = (t < total) ? ld(t) : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int t = t0 + u * WG;
+            if (t < total) st(t, v[u]);
+        }
+    }
+}
+
+// floor(t / den) for 0 <= t < 2^21, den >= 1, through a float reciprocal inv ~ 1/den
+// (exact in that range: the relative error of the product stays below 2^-22).
+__device__ __forceinline__ int fdiv(int t, float inv) { return (int)(((float)t + 0.5f) * inv); }
+
 // Sum of one value per thread over the workgroup; every thread gets the result.
 // `red` is an LDS array of at least NWAVES doubles.  Fixed reduction tree (deterministic).
 __device__ __forceinline__ double wg_sum(double v, double* red) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = tid_here() & 63, wave = tid_here() >> 6;
     v = wave_sum(v);
     __syncthreads();
     if (lane == 0) red[wave] = v;
@@ -43,7 +75,7 @@ __device__ __forceinline__ double wg_sum(double v, double* red) {
 
 // Two sums at once.
 __device__ __forceinline__ void wg_sum2(double& a, double& b, double* red) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = tid_here() & 63, wave = tid_here() >> 6;
     a = wave_sum(a);
     b = wave_sum(b);
     __syncthreads();
@@ -59,7 +91,7 @@ __device__ __forceinline__ void wg_sum2(double& a, double& b, double* red) {
 // out[l] = sum_i a[i] * B[i + l*ldb], l < ncol (one wave per column, rows strided by lane).
 // Result in LDS `out`.  Ends with a barrier.
 __device__ __forceinline__ void wg_coldots(int n, int ncol, const double* a, const double* B, int ldb, double* out) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = tid_here() & 63, wave = tid_here() >> 6;
     for (int l = wave; l < ncol; l += NWAVES) {
         double s = 0.0;
         for (int i = lane; i < n; i += 64) s = fma(ldg(a + i), B[i + (int64_t)l * ldb], s);
@@ -75,7 +107,7 @@ __device__ __forceinline__ void wg_coldots(int n, int ncol, const double* a, con
 __device__ __forceinline__ void apply_op(const OpDev& op, int n, int r, const double* x, int ldx,
                                          double* y, int ldy, const double* dots) {
     const int total = n * r;
-    for (int t = threadIdx.x; t < total; t += WG) {
+    for (int t = tid_here(); t < total; t += WG) {
         const int i = t % n, l = t / n;
         const double* xc = x + (int64_t)l * ldx;
         double v;
@@ -104,7 +136,7 @@ template <bool ACC>
 __device__ __forceinline__ void apply_op_t(const OpDev& op, int n, int r, const double* z, int ldz,
                                            double* y, int ldy, const double* dots) {
     const int total = n * r;
-    for (int t = threadIdx.x; t < total; t += WG) {
+    for (int t = tid_here(); t < total; t += WG) {
         const int i = t % n, l = t / n;
         const double* zc = z + (int64_t)l * ldz;
         double v;

@@ -73,7 +73,7 @@ template <bool F32, int NT, int IPW, class AF, class EP>
 __device__ __forceinline__ double panel_gemm(int M, int N, int K, const AF& af, const double* __restrict__ Bt, int ldb,
                              const EP& ep, double* lds) {
     double part = 0.0;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = tid_here() & 63, wave = tid_here() >> 6;
     const int tm = (M + 15) >> 4, tn = (N + 15) >> 4;
     const int groups = (tn + NT - 1) / NT;
     const int packs = (tm + IPW - 1) / IPW;
@@ -95,7 +95,7 @@ __device__ __forceinline__ double panel_gemm(int M, int N, int K, const AF& af, 
         for (int kc0 = 0; kc0 < K; kc0 += PG_KCH) {
             const int kc = min(PG_KCH, K - kc0);
             __syncthreads();
-            for (int t = threadIdx.x; t < PG_KCH * nw; t += WG) {
+            for (int t = tid_here(); t < PG_KCH * nw; t += WG) {
                 const int kk = t / nw, j = t - kk * nw;
                 lds[kk * ldsw + j] = (kk < kc && j < N) ? ldg(Bt + j + (int64_t)(kc0 + kk) * ldb) : 0.0;
             }
@@ -155,37 +155,67 @@ struct PanelA {
 // ---------------------------------------------------------------------------------------
 // Gram products over row chunks staged in LDS:
 //   G1 (M1 x M1, symmetric) = A^T A  and optionally  G2 (M1 x N2) = A^T B,
-// where row i of A (M1 values) and of B (N2 values) are produced by functors
-//   fa(i, c) (c < M1),  fb(i, c) (c < N2).
-// LDS: `lds` must hold KC * ((TM1*16 + 1) + (TN2*16 + 1)) doubles.
-// Only the upper-triangular tiles of G1 are computed; both halves are written.
-// Ends with a barrier.
+// where element (i, c) of A (c < M1) and of B (c < N2) come from panel functors with
+//   raw(i, c) -> raw_t (loads only) and val(raw_t) -> double,
+// so that a batch of loads is issued before any value is formed.
+// Only the upper-triangular tiles of G1 are computed; both halves are written.  Tiles are
+// dealt round-robin to the waves, up to GRAM_TPW per wave per pass over the rows.  Chunks
+// of 32 rows (16 when LDS is short) are staged; `lds` holds `cap` doubles, at least
+// 16 * ((TM1*16 + 1) + (TN2*16 + 1)).  Starts and ends with a barrier.
 // ---------------------------------------------------------------------------------------
-constexpr int GRAM_KC = 16;
-constexpr int GRAM_TILES_PER_WAVE = 4;
+constexpr int GRAM_TPW = 9;
+
+// Stage rows i0 .. i0 + 2^lg - 1 of a panel functor into LDS (row stride ld), `total` =
+// 2^lg * (columns rounded to 16); eight elements' loads per thread are in flight together.
+template <class F>
+__device__ __forceinline__ void gram_stage(const F& f, int n, int i0, int ncol, int total, int lg, double* dst, int ld) {
+    const int msk = (1 << lg) - 1;
+    for (int t0 = tid_here(); t0 < total; t0 += 8 * WG) {
+        typename F::raw_t v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int t = t0 + u * WG;
+            const int i = i0 + (t & msk), c = t >> lg;
+            v[u] = (t < total && i < n && c < ncol) ? f.raw(i, c) : F::zero();
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int t = t0 + u * WG;
+            if (t < total) dst[(t & msk) * ld + (t >> lg)] = f.val(v[u]);
+        }
+    }
+}
 
 template <bool F32, class FA, class FB>
-__device__ __forceinline__ void gram_lds(int n, int M1, int N2, const FA& fa, const FB& fb, double* __restrict__ G1, int ld1,
-                         double* __restrict__ G2, int ld2, double* lds) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+__device__ __forceinline__ void gram_lds(int n, int M1, int N2, const FA& fa, const FB& fb, double* __restrict__ G1,
+                                         int ld1, double* __restrict__ G2, int ld2, double* lds, int cap) {
+    constexpr int PFN = 16;   // prefetched elements per thread and operand
+    const int lane = tid_here() & 63, wave = tid_here() >> 6;
     const int TM = (M1 + 15) >> 4, TN = (N2 + 15) >> 4;
     const int wa = TM * 16 + 1, wb = TN * 16 + 1;   // LDS row strides (odd: bank spread)
-    double* As = lds;
-    double* Bs = lds + GRAM_KC * wa;
+    // chunk rows: 32 (or 16), double-buffered when the LDS area allows it; with double
+    // buffering the next chunk's loads are in flight during this chunk's matrix-core work
+    int lgKC = 5;
+    while (lgKC > 4 && 2 * (1 << lgKC) * (wa + wb) > cap) --lgKC;
+    const bool dbl = 2 * (1 << lgKC) * (wa + wb) <= cap;
+    if (!dbl) lgKC = (32 * (wa + wb) <= cap) ? 5 : 4;
+    const int KC = 1 << lgKC;
+    const int na = KC * TM * 16, nb = KC * TN * 16;
+    const bool pre = dbl && na <= PFN * WG && nb <= PFN * WG;
+    const int bufsz = KC * (wa + wb);
     const int nt1 = TM * (TM + 1) / 2;
     const int ntiles = nt1 + TM * TN;
-    const int per_pass = NWAVES * GRAM_TILES_PER_WAVE;
+    const int per_pass = NWAVES * GRAM_TPW;
     const int kk = lane >> 4, cc = lane & 15;
+    const int msk = KC - 1;
     for (int base = 0; base < ntiles; base += per_pass) {
-        // tiles of this wave in this pass: base + wave + NWAVES * t
-        int ti[GRAM_TILES_PER_WAVE], tj[GRAM_TILES_PER_WAVE], which[GRAM_TILES_PER_WAVE];
+        int ti[GRAM_TPW], tj[GRAM_TPW], which[GRAM_TPW];
 #pragma unroll
-        for (int t = 0; t < GRAM_TILES_PER_WAVE; ++t) {
+        for (int t = 0; t < GRAM_TPW; ++t) {
             int id = base + wave + NWAVES * t;
             which[t] = -1;
             ti[t] = tj[t] = 0;
             if (id < nt1) {
-                // upper-triangle enumeration: row a, col b >= a
                 int a = 0, rem = id;
                 while (rem >= TM - a) { rem -= TM - a; ++a; }
                 ti[t] = a;
@@ -198,45 +228,71 @@ __device__ __forceinline__ void gram_lds(int n, int M1, int N2, const FA& fa, co
                 which[t] = 2;
             }
         }
-        Tile<F32> acc[GRAM_TILES_PER_WAVE];
+        Tile<F32> acc[GRAM_TPW];
 #pragma unroll
-        for (int t = 0; t < GRAM_TILES_PER_WAVE; ++t) acc[t].zero();
-        for (int i0 = 0; i0 < n; i0 += GRAM_KC) {
-            __syncthreads();
-            for (int t = threadIdx.x; t < GRAM_KC * TM * 16; t += WG) {
-                const int row = t % GRAM_KC, c = t / GRAM_KC;
-                const int i = i0 + row;
-                As[row * wa + c] = (i < n && c < M1) ? fa(i, c) : 0.0;
-            }
-            if (N2 > 0) {
-                for (int t = threadIdx.x; t < GRAM_KC * TN * 16; t += WG) {
-                    const int row = t % GRAM_KC, c = t / GRAM_KC;
-                    const int i = i0 + row;
-                    Bs[row * wb + c] = (i < n && c < N2) ? fb(i, c) : 0.0;
+        for (int t = 0; t < GRAM_TPW; ++t) acc[t].zero();
+        __syncthreads();
+        gram_stage(fa, n, 0, M1, na, lgKC, lds, wa);
+        gram_stage(fb, n, 0, N2, nb, lgKC, lds + KC * wa, wb);
+        __syncthreads();
+        for (int c = 0; c * KC < n; ++c) {
+            const int buf = pre ? (c & 1) : 0;
+            const double* As = lds + buf * bufsz;
+            const double* Bs = As + KC * wa;
+            const int i1 = (c + 1) * KC;
+            const bool more = i1 < n;
+            typename FA::raw_t ra[PFN];
+            typename FB::raw_t rb[PFN];
+            if (pre && more) {
+#pragma unroll
+                for (int u = 0; u < PFN; ++u) {
+                    const int t = tid_here() + u * WG;
+                    const int i = i1 + (t & msk), col = t >> lgKC;
+                    ra[u] = (t < na && i < n && col < M1) ? fa.raw(i, col) : FA::zero();
+                    rb[u] = (t < nb && i < n && col < N2) ? fb.raw(i, col) : FB::zero();
                 }
             }
-            __syncthreads();
+            // per k-step: the operands of all of the wave's tiles are read first (branch-free;
+            // an idle tile reads tile (0, 0)), then the independent matrix-core steps
+            for (int k0 = 0; k0 < KC; k0 += 4) {
+                double av[GRAM_TPW], bv[GRAM_TPW];
 #pragma unroll
-            for (int t = 0; t < GRAM_TILES_PER_WAVE; ++t) {
-                if (which[t] > 0) {
-                    const double* Bsrc = (which[t] == 1) ? As : Bs;
-                    const int wbs = (which[t] == 1) ? wa : wb;
-#pragma unroll
-                    for (int k0 = 0; k0 < GRAM_KC; k0 += 4) {
-                        const double a = As[(k0 + kk) * wa + ti[t] * 16 + cc];
-                        const double b = Bsrc[(k0 + kk) * wbs + tj[t] * 16 + cc];
-                        acc[t].step(a, b);
-                    }
+                for (int t = 0; t < GRAM_TPW; ++t) {
+                    const bool g1 = which[t] != 2;
+                    av[t] = As[(k0 + kk) * wa + ti[t] * 16 + cc];
+                    bv[t] = g1 ? As[(k0 + kk) * wa + tj[t] * 16 + cc] : Bs[(k0 + kk) * wb + tj[t] * 16 + cc];
                 }
+                // operands swapped: the tile holds the transposed block, so a lane's results
+                // lie in one row-contiguous run (coalesced stores)
+#pragma unroll
+                for (int t = 0; t < GRAM_TPW; ++t)
+                    if (which[t] > 0) acc[t].step(bv[t], av[t]);
+            }
+            if (!more) break;
+            if (pre) {
+                double* An = lds + (buf ^ 1) * bufsz;
+                double* Bn = An + KC * wa;
+#pragma unroll
+                for (int u = 0; u < PFN; ++u) {
+                    const int t = tid_here() + u * WG;
+                    if (t < na) An[(t & msk) * wa + (t >> lgKC)] = fa.val(ra[u]);
+                    if (t < nb) Bn[(t & msk) * wb + (t >> lgKC)] = fb.val(rb[u]);
+                }
+                __syncthreads();
+            } else {
+                __syncthreads();
+                gram_stage(fa, n, i1, M1, na, lgKC, lds, wa);
+                gram_stage(fb, n, i1, N2, nb, lgKC, lds + KC * wa, wb);
+                __syncthreads();
             }
         }
 #pragma unroll
-        for (int t = 0; t < GRAM_TILES_PER_WAVE; ++t) {
+        for (int t = 0; t < GRAM_TPW; ++t) {
             if (which[t] < 0) continue;
-            const int col = tj[t] * 16 + cc;
+            const int row = ti[t] * 16 + cc;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int row = ti[t] * 16 + Tile<F32>::row(lane, v);
+                const int col = tj[t] * 16 + Tile<F32>::row(lane, v);
                 const double val = acc[t].get(v);
                 if (which[t] == 1) {
                     if (row < M1 && col < M1) {
