@@ -85,6 +85,15 @@ def lib() -> C.CDLL:
             "cp_als_run_batched": [H, C.c_int32, P(cp_operator), P(cp_operator), P(cp_tensor), P(cp_tensor),
                                    C.c_int32, P(cp_als_opts), P(cp_als_report)],
             "cp_als_default_opts": [P(cp_als_opts)],
+            # learned warm start (include/cpals_ws.h)
+            "cp_ws_create": [H, C.c_void_p, C.c_int32, C.c_int32, P(H)],
+            "cp_ws_destroy": [H],
+            "cp_ws_get_params": [H, H, C.c_void_p],
+            "cp_ws_forward": [H, H, C.c_void_p, C.c_int32, C.c_void_p],
+            "cp_ws_gradients": [H, H, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, P(C.c_float)],
+            "cp_ws_train_step": [H, H, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_int32,
+                                 C.c_float, P(C.c_float)],
+            "cp_ws_predict": [H, H, P(cp_tensor), P(cp_tensor), C.c_void_p, P(cp_tensor)],
         }
         for name, argt in sigs.items():
             f = getattr(L, name)
@@ -94,6 +103,8 @@ def lib() -> C.CDLL:
         L.cp_last_error.restype = C.c_char_p
         L.cp_version.argtypes = []
         L.cp_version.restype = C.c_char_p
+        L.cp_ws_num_params.argtypes = []
+        L.cp_ws_num_params.restype = C.c_int32
         _LIB = L
     return _LIB
 
@@ -271,3 +282,96 @@ def cp_als_run_batched(h: Handle, As, Bs, f_inits, f_ios, n_steps: int,
     h.check(lib().cp_als_run_batched(h.h, count, A_arr, B_arr, fi, fo, n_steps, C.byref(opts), reps),
             allow_not_converged=True)
     return [[reps[i * n_steps + s].as_dict() for s in range(n_steps)] for i in range(count)]
+
+
+# ----------------------------------------------------------------------------------------
+# learned warm start (include/cpals_ws.h)
+# ----------------------------------------------------------------------------------------
+
+def ws_num_params() -> int:
+    return int(lib().cp_ws_num_params())
+
+
+class WarmStartNet:
+    """The per-column CNN of include/cpals_ws.h (device memory owned by the library)."""
+
+    def __init__(self, h: Handle, params: np.ndarray, n: int, max_batch: int):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        if p.size != ws_num_params():
+            raise ValueError("expected %d parameters, got %d" % (ws_num_params(), p.size))
+        self.h = h
+        self.n = n
+        self.max_batch = max_batch
+        self.net = C.c_void_p()
+        h.check(lib().cp_ws_create(h.h, p.ctypes.data_as(C.c_void_p), n, max_batch, C.byref(self.net)))
+
+    def close(self):
+        if self.net:
+            lib().cp_ws_destroy(self.net)
+            self.net = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def params(self) -> np.ndarray:
+        out = np.empty(ws_num_params(), dtype=np.float32)
+        self.h.check(lib().cp_ws_get_params(self.h.h, self.net, out.ctypes.data_as(C.c_void_p)))
+        return out
+
+    def forward(self, x, y) -> None:
+        """y[B, n] (float32 CUDA) <- network(x[B, 3, n] float32 CUDA)."""
+        _check_f32(x, 3)
+        _check_f32(y, 2)
+        B = x.shape[0]
+        if x.shape[1:] != (3, self.n) or tuple(y.shape) != (B, self.n):
+            raise ValueError("shapes must be x [B, 3, n], y [B, n]")
+        self.h.check(lib().cp_ws_forward(self.h.h, self.net, C.c_void_p(x.data_ptr()), B, C.c_void_p(y.data_ptr())))
+
+    def gradients(self, x, target, grad) -> float:
+        """grad (float32 CUDA, n_params) <- d loss / d params; returns the loss."""
+        _check_f32(x, 3)
+        _check_f32(target, 2)
+        _check_f32(grad, 1)
+        B = x.shape[0]
+        if x.shape[1:] != (3, self.n) or tuple(target.shape) != (B, self.n) or grad.numel() != ws_num_params():
+            raise ValueError("shapes must be x [B, 3, n], target [B, n], grad [n_params]")
+        loss = C.c_float()
+        self.h.check(lib().cp_ws_gradients(self.h.h, self.net, C.c_void_p(x.data_ptr()), C.c_void_p(target.data_ptr()),
+                                           B, C.c_void_p(grad.data_ptr()), C.byref(loss)))
+        return float(loss.value)
+
+    def train_step(self, traj, samples: np.ndarray, coef: np.ndarray, lr: float) -> float:
+        """One Adam step; traj float64 CUDA [T, C, n]; samples int32 [B, 2] of (t, c); coef [C]."""
+        import torch
+        if traj.dtype != torch.float64 or not traj.is_cuda or not traj.is_contiguous() or traj.dim() != 3:
+            raise ValueError("traj must be a contiguous float64 CUDA tensor [T, C, n]")
+        T, Cc, n = traj.shape
+        if n != self.n:
+            raise ValueError("traj has n=%d, network n=%d" % (n, self.n))
+        smp = np.ascontiguousarray(samples, dtype=np.int32).reshape(-1, 2)
+        cf = np.ascontiguousarray(coef, dtype=np.float64)
+        if cf.size != Cc:
+            raise ValueError("coef needs one value per column")
+        loss = C.c_float()
+        self.h.check(lib().cp_ws_train_step(self.h.h, self.net, C.c_void_p(traj.data_ptr()), T, Cc,
+                                            smp.ctypes.data_as(C.c_void_p), cf.ctypes.data_as(C.c_void_p), smp.shape[0],
+                                            float(lr), C.byref(loss)))
+        return float(loss.value)
+
+    def predict(self, f_prev, f_cur, coef: np.ndarray, f_guess) -> None:
+        """f_guess <- the network's prediction of the next factors from (f_prev, f_cur)."""
+        cf = np.ascontiguousarray(coef, dtype=np.float64)
+        tp, tc, tg = tensor_desc(f_prev), tensor_desc(f_cur), tensor_desc(f_guess)
+        if cf.size != tc.d:
+            raise ValueError("coef needs one value per dimension")
+        self.h.check(lib().cp_ws_predict(self.h.h, self.net, C.byref(tp), C.byref(tc), cf.ctypes.data_as(C.c_void_p),
+                                         C.byref(tg)))
+
+
+def _check_f32(t, ndim):
+    import torch
+    if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous() or t.dim() != ndim:
+        raise ValueError("expected a contiguous float32 CUDA tensor with %d dimensions" % ndim)

@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcpals.so")
-SOURCES = ["api.hip", "als_kernel.hip", "basic_kernels.hip"]
+SOURCES = ["api.hip", "als_kernel.hip", "basic_kernels.hip", "warmstart.hip"]
 ARCH = "gfx950"
 
 

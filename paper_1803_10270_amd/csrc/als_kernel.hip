@@ -553,7 +553,6 @@ __device__ __forceinline__ double cgemm(int n, int r, const OpDev* comps, int nb
     constexpr int PF = (64 * TN * 16 + WG - 1) / WG;
     Smem& s = SMEM;
     const int lane = tid_here() & 63, wave = tid_here() >> 6;
-    const int kq = lane >> 4, cc = lane & 15;
     const int rc4 = (rc + 3) & ~3;
     const int ktsz = rc4 * LDB;
     int H = 0;

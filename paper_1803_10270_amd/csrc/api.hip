@@ -694,6 +694,15 @@ cp_status prepare_step(cp_handle h, const cp_operator* A, const cp_operator* B, 
 
 }  // namespace
 
+namespace cpals {
+// for the other host translation units of the library (warm start)
+hipStream_t handle_stream(cp_handle h) { return h->stream; }
+cp_status handle_fail(cp_handle h, cp_status st, const char* msg) { return fail(h, st, msg); }
+cp_status handle_check_tensor(cp_handle h, const cp_tensor* t, const char* name) {
+    return check_tensor(h, t, name, CP_MAX_N);
+}
+}  // namespace cpals
+
 extern "C" {
 
 const char* cp_version(void) { return "cpals-gfx950 0.1"; }
