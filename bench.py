@@ -8,7 +8,14 @@ increment, at most 200 sweeps per step, FP64.  Synthetic seeded inputs.
 A step is one implicit time step: the full ALS solve of A f_{n+1} = f_n (all sweeps), run
 device-resident in one persistent kernel launch per batch of steps.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+Beside the plain method (the headline value) the same run measures the two other forms at
+the same 1e-8 tolerance:
+  learned  the per-column CNN warm start, trained on solver trajectories of new seeds,
+           against the plain warm start on a held-out instance of the same workload;
+  batched  256 uneven advection instances in one persistent launch against the same
+           instances advanced one launch at a time (a seeded sample, scaled by cost).
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-forms]
 
 Prints one JSON line.
 """
@@ -85,6 +92,111 @@ def cpu_baseline(p, sweeps_per_step, n_sweeps=4):
                           n_sweeps, dt, per_sweep, sweeps_per_step, cores)}
 
 
+def kernel_source_hash():
+    """Hash of the kernel sources: a committed counter summary applies only to this code."""
+    import hashlib
+    hsh = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1803_10270_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".h")):
+            with open(os.path.join(csrc, f), "rb") as fh:
+                hsh.update(fh.read())
+    return hsh.hexdigest()[:16]
+
+
+def committed_traffic():
+    """HBM bytes per launch of the timed configuration from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE scaled by the copy-kernel calibration), or None when
+    the summary was taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", "als_persistent_traffic.json")
+    try:
+        with open(path) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_hash") != kernel_source_hash():
+        return None
+    return rec
+
+
+def bench_learned(args, log):
+    """Learned warm start vs plain warm start on held-out steps (same tolerance)."""
+    import torch
+    from paper_1803_10270_amd import binding as B
+    from paper_1803_10270_amd import warmstart as WS
+    from paper_1803_10270_amd import workloads as W
+    h = B.Handle()
+    mk = lambda s: W.advection_ie_variable(seed=s, n_steps=args.learned_train_steps + 1)
+    p0 = mk(args.seed + 300)
+    d, r, n = p0.A.d, p0.rank_cap, p0.A.dims()[0]
+    coef = np.full(d, 1e-3 * n / (2 * np.pi))
+    opts = B.default_opts(tol=p0.tol, max_sweeps=args.max_sweeps)
+
+    def trajectory(p, steps):
+        V, U = B.to_device(p.f0), B.to_device(p.guess)
+        traj = torch.zeros(steps * d * r * n, dtype=torch.float64, device="cuda")
+        reps = B.cp_als_run(h, p.A, p.B, V, U, steps, opts, traj=traj)
+        return traj.view(steps, d * r, n), reps
+
+    t0 = time.perf_counter()
+    trajs = []
+    for sd in range(args.seed + 301, args.seed + 301 + args.learned_train_seeds):
+        tr, _ = trajectory(mk(sd), args.learned_train_steps)
+        trajs.append(tr.contiguous())
+    t_data = time.perf_counter() - t0
+    net = B.WarmStartNet(h, WS.init_params(seed=9), n, max_batch=512)
+    t0 = time.perf_counter()
+    losses = []
+    for lr, steps in ((2e-3, 200), (5e-4, 200), (1e-4, 100)):
+        losses += WS.train(net, trajs, [WS.column_coef(coef, r)] * len(trajs), steps=steps, batch=512, lr=lr, seed=3)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    log("learned: %d training trajectories in %.1f s, %d Adam steps in %.1f s (loss %.2e -> %.2e)" % (
+        len(trajs), t_data, len(losses), t_train, losses[0], losses[-1]))
+    # held-out instance: warm up 2 steps (the predictor needs two levels), then K steps each way
+    K = args.learned_eval_steps
+    V, U = B.to_device(p0.f0), B.to_device(p0.guess)
+    B.cp_als_run(h, p0.A, p0.B, V, U, 1, opts)
+    lvl1 = [u.clone() for u in U]
+    B.cp_als_run(h, p0.A, p0.B, [u.clone() for u in U], U, 1, opts)
+    lvl2 = [u.clone() for u in U]
+    # plain: K steps from level 2, one step per call (the same granularity as the learned form)
+    cur = [u.clone() for u in lvl2]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plain_sweeps = []
+    for _ in range(K):
+        nxt = [u.clone() for u in cur]
+        rep = B.cp_als_step(h, p0.A, p0.B, cur, nxt, opts)
+        plain_sweeps.append(rep["sweeps"])
+        cur = nxt
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    # learned: the same K steps from the same levels
+    prev, cur = [u.clone() for u in lvl1], [u.clone() for u in lvl2]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    learned_sweeps, used, errs = [], 0, []
+    for _ in range(K):
+        out, rep = WS.learned_step(h, net, p0.A, p0.B, prev, cur, coef, opts)
+        learned_sweeps.append(rep["sweeps"])
+        used += rep["used_prediction"]
+        errs.append(rep["pred_rel_dist"])
+        prev, cur = cur, out
+    torch.cuda.synchronize()
+    t_learned = time.perf_counter() - t0
+    net.close()
+    h.close()
+    return {"form": "learned", "workload": "advection_ie_variable d=6 n=256 r=32, held-out seed %d, %d steps" % (
+                args.seed + 300, K),
+            "train": {"trajectories": len(trajs), "levels_each": args.learned_train_steps, "adam_steps": len(losses),
+                      "batch": 512, "loss_first": losses[0], "loss_last": losses[-1], "seconds": t_train},
+            "plain_steps_per_s": K / t_plain, "learned_steps_per_s": K / t_learned,
+            "speedup": t_plain / t_learned, "plain_mean_sweeps": float(np.mean(plain_sweeps)),
+            "learned_mean_sweeps": float(np.mean(learned_sweeps)), "prediction_used": used,
+            "prediction_rel_error_mean": float(np.nanmean(errs))}
+
+
 def bench_batched(args):
     """Batched form: uneven advection instances (d in {4,6}, n in {64..512}, rank caps 4..48) in one
     persistent launch, against the same instances advanced one at a time (a seeded sample of
@@ -126,14 +238,14 @@ def bench_batched(args):
            "plain_steps_per_s": steps_total / t_plain, "speedup": t_plain / t_batched,
            "mean_sweeps_per_step": float(np.mean(sweeps)),
            "converged_steps": int(sum(1 for rr in reps for r in rr if not (r["flags"] & B.FLAG_NOT_CONVERGED)))}
-    print(json.dumps(out), flush=True)
     h.close()
+    return out
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--max-sweeps", type=int, default=200)
     ap.add_argument("--seed", type=int, default=0)
@@ -141,7 +253,11 @@ def main():
     ap.add_argument("--form", default="plain", choices=["plain", "batched"])
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--batch-steps", type=int, default=20)
-    ap.add_argument("--plain-sample", type=int, default=16)
+    ap.add_argument("--plain-sample", type=int, default=8)
+    ap.add_argument("--no-forms", action="store_true", help="skip the learned and batched forms")
+    ap.add_argument("--learned-train-seeds", type=int, default=3)
+    ap.add_argument("--learned-train-steps", type=int, default=16)
+    ap.add_argument("--learned-eval-steps", type=int, default=6)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only (the multi-GPU sharding is a design, not code); "
@@ -154,8 +270,11 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
     if args.form == "batched":
-        bench_batched(args)
+        print(json.dumps(bench_batched(args)), flush=True)
         return
     p = W.advection_ie_variable(seed=args.seed)
     h = B.Handle()
@@ -206,10 +325,27 @@ def main():
         "pcg_iters_per_update": float(sum(r["pcg_iters"] for r in reports) / max(1, 6 * sum(sweeps))),
         "converged_steps": int(sum(1 for r in reports if not (r["flags"] & B.FLAG_NOT_CONVERGED))),
         "eps_conv_last": reports[-1]["eps_conv"],
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None,
-                     "kernel": "als_persistent", "flops_per_launch": flops, "launch_ms": gpu_ms},
+                     "kernel": "als_persistent", "flops_per_launch": flops, "launch_ms": gpu_ms,
+                     "source_hash": kernel_source_hash()},
     }
+    tr = committed_traffic()
+    if tr is not None and tr.get("steps") == args.steps and tr.get("max_sweeps") == args.max_sweeps:
+        out["roofline"]["traffic"] = tr["bytes_per_launch"]
+    if not args.no_forms:
+        forms = {}
+        try:
+            forms["learned"] = bench_learned(args, log)
+        except Exception as e:   # a form that cannot run is reported, the headline stands
+            forms["learned"] = {"error": repr(e)}
+        try:
+            args_b = argparse.Namespace(**vars(args))
+            args_b.batch_steps = 2
+            forms["batched"] = bench_batched(args_b)
+        except Exception as e:
+            forms["batched"] = {"error": repr(e)}
+        out["forms"] = forms
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(p, float(np.mean(sweeps)))
     print(json.dumps(out), flush=True)

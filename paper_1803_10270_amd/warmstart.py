@@ -62,6 +62,23 @@ def learned_step(h, net, A, Bop, f_prev, f_cur, coef, opts, f_out=None):
     return start, rep
 
 
+def init_params(seed=0):
+    """Seeded initial parameters in the natural order of include/cpals_ws.h: He-uniform
+    weights, zero biases, and a zero output layer (the untrained network predicts the plain
+    warm start exactly)."""
+    widths = (3, 32, 32, 32, 1)
+    rng = np.random.default_rng(seed)
+    out = []
+    for li in range(4):
+        cin, cout = widths[li], widths[li + 1]
+        bound = np.sqrt(6.0 / (cin * 5))
+        w = rng.uniform(-bound, bound, size=cout * cin * 5)
+        if li == 3:
+            w[:] = 0.0
+        out += [w, np.zeros(cout)]
+    return np.concatenate(out).astype(np.float32)
+
+
 def trajectory_columns(traj, d, r, n):
     """View a cp_als_run trajectory buffer ([T, sum_k n r] of column-major panels) as
     columns [T, d r, n] (all n_k equal)."""
