@@ -58,6 +58,8 @@ typedef enum {
 #define CP_FLAG_PCG_MAXITER 2u    /* a per-dimension solve hit pcg_max_iter            */
 #define CP_FLAG_REGULARIZED 4u    /* a Cholesky pivot of H_q fell below 1e-12 max diag */
 #define CP_FLAG_NONFINITE 8u      /* a NaN/Inf was produced                            */
+#define CP_FLAG_SYNC_TIMEOUT 16u  /* a workgroup of a cluster waited too long for the    */
+                                  /* others at a barrier; the result is not valid       */
 
 typedef struct cp_handle_s* cp_handle;
 
@@ -67,6 +69,14 @@ cp_status cp_create(cp_handle* handle, void* hip_stream);
 cp_status cp_destroy(cp_handle handle);
 cp_status cp_set_stream(cp_handle handle, void* hip_stream);
 const char* cp_last_error(cp_handle handle);
+/* Largest number of workgroups that may advance one problem together (default 16; 1 keeps
+ * every problem on one workgroup).  A call that advances a single problem (cp_als_step,
+ * cp_als_run, cp_truncate) splits its grid rows over a cluster of W workgroups, W the largest
+ * power of two <= max_workgroups with every n_k divisible by 16 W, when no operator of A or B
+ * is rank-1; batched calls always use one workgroup per problem.  The clusters meet at
+ * device-wide barriers, and partial sums are added in a fixed order, so results are
+ * deterministic for a given W (and agree across W to rounding).  INVALID_ARG outside 1..256. */
+cp_status cp_set_cluster(cp_handle handle, int32_t max_workgroups);
 /* Library version string (static storage). */
 const char* cp_version(void);
 

@@ -22,7 +22,7 @@ CP_MAX_DIMS = 8
 CP_MAX_OPS = 4
 
 CP_OK, CP_ERR_INVALID_ARG, CP_ERR_SHAPE, CP_ERR_UNSUPPORTED, CP_ERR_HIP, CP_ERR_NOT_CONVERGED = range(6)
-FLAG_NOT_CONVERGED, FLAG_PCG_MAXITER, FLAG_REGULARIZED, FLAG_NONFINITE = 1, 2, 4, 8
+FLAG_NOT_CONVERGED, FLAG_PCG_MAXITER, FLAG_REGULARIZED, FLAG_NONFINITE, FLAG_SYNC_TIMEOUT = 1, 2, 4, 8, 16
 PREC_FP64, PREC_MIXED = 0, 1
 OP_KIND = {"identity": 0, "diag": 1, "band": 2, "rank1": 3}
 
@@ -74,6 +74,7 @@ def lib() -> C.CDLL:
         P = C.POINTER
         sigs = {
             "cp_create": [P(H), C.c_void_p], "cp_destroy": [H], "cp_set_stream": [H, C.c_void_p],
+            "cp_set_cluster": [H, C.c_int32],
             "cp_inner": [H, P(cp_tensor), P(cp_tensor), C.c_void_p],
             "cp_norm": [H, P(cp_tensor), C.c_void_p],
             "cp_apply_operator": [H, P(cp_operator), P(cp_tensor), P(cp_tensor)],
@@ -190,6 +191,10 @@ class Handle:
         st = lib().cp_create(C.byref(self.h), C.c_void_p(stream.cuda_stream))
         if st != CP_OK:
             raise CpalsError(st, "cp_create failed")
+
+    def set_cluster(self, max_workgroups: int) -> None:
+        """Workgroups that may share one problem (1 = one workgroup per problem)."""
+        self.check(lib().cp_set_cluster(self.h, int(max_workgroups)))
 
     def close(self):
         if self.h:

@@ -48,6 +48,10 @@ struct Smem {
     PairRec pairs[LDS_PAIRS];
     StageSlot slots[(CP_MAX_DIMS - 1) * CP_MAX_OPS * CP_MAX_OPS];
     uint32_t iflag;
+    int32_t part, W;             // this workgroup's index in the problem's cluster, cluster size
+    uint32_t bar_target;         // arrivals the next cluster barrier waits for (thread 0)
+    uint32_t sync_ok;            // 0 once a cluster barrier timed out
+    uint32_t dcount;             // calls of cluster_sum (selects the partial buffer)
 };
 static_assert(sizeof(Smem) <= 160 * 1024, "LDS budget of one workgroup");
 
@@ -69,6 +73,64 @@ __device__ __forceinline__ int wrap_idx(int i, int n) {
     while (i < 0) i += n;
     while (i >= n) i -= n;
     return i;
+}
+
+// ------------------------------------------------------------------------------------
+// cluster of workgroups sharing one problem
+// ------------------------------------------------------------------------------------
+
+// Grid rows [rlo, rhi) of an n-row panel owned by this workgroup of the cluster.
+__device__ __forceinline__ void own_rows(int n, int& rlo, int& rhi) {
+    Smem& s = SMEM;
+    const int W = ufirst(s.W), part = ufirst(s.part);
+    const int per = n / W;
+    rlo = part * per;
+    rhi = rlo + per;
+}
+
+// Barrier of the cluster's workgroups with device-scope release/acquire (so that every
+// write before it is visible to every workgroup after it).  The arrival counter only
+// grows; a workgroup waits for W arrivals per barrier.  A wait is bounded: past the bound
+// the barrier returns and sync_ok is cleared (the caller ends the problem).
+__device__ __forceinline__ void cluster_sync() {
+    Smem& s = SMEM;
+    __syncthreads();
+    if (ufirst(s.W) == 1) return;
+    if (tid_here() == 0) {
+        const uint32_t tgt = s.bar_target + (uint32_t)s.W;
+        s.bar_target = tgt;
+        uint32_t* ctr = s.pb.bar;
+        __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        long spins = 0;
+        while (__hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < tgt) {
+            __builtin_amdgcn_s_sleep(2);
+            if (++spins > (1l << 22)) {
+                s.sync_ok = 0;
+                break;
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// Sum over the cluster of one workgroup-uniform value, in a fixed order (partials in
+// device memory, two alternating buffers so that a fast workgroup never overwrites a
+// partial that a slow one has not read).
+__device__ __forceinline__ double cluster_sum(double v) {
+    Smem& s = SMEM;
+    const int W = ufirst(s.W);
+    if (W == 1) return v;
+    const int part = ufirst(s.part);
+    const int buf = ufirst((int)(s.dcount & 1u));
+    double* base = s.pb.dpart + (int64_t)buf * W * 8;
+    if (tid_here() == 0) stg(base + part * 8, v);
+    cluster_sync();
+    double tot = 0.0;
+    for (int w = 0; w < W; ++w) tot += ldg(base + w * 8);
+    __syncthreads();
+    if (tid_here() == 0) s.dcount += 1u;
+    __syncthreads();
+    return tot;
 }
 
 // Plain column-major panel element (i, c).
@@ -95,15 +157,18 @@ struct DiffF {
     __device__ __forceinline__ double val(raw_t v) const { return v.x - v.y; }
 };
 
-// The stacked applied panel P = [O^0 X, O^1 X, ...] (n x m r, column a r + l) into `out`.
+// Rows [rlo, rhi) of the stacked applied panel P = [O^0 X, O^1 X, ...] (n x m r, column
+// a r + l) into `out`.
 // For each batch of elements every tap and coefficient load is issued before the sums are
 // formed.  Ends with a barrier.
-__device__ __forceinline__ void apply_panel(const OpDev* ops, int m, int n, int r, const double* X, double* out) {
+__device__ __forceinline__ void apply_panel(const OpDev* ops, int m, int n, int r, const double* X, double* out,
+                                            int rlo, int rhi) {
     Smem& s = SMEM;
     for (int a = 0; a < m; ++a)
         if (ops[a].kind == CP_OP_RANK1) wg_coldots(n, r, ops[a].data + n, X, n, s.dots + a * r);
-    const int total = n * m * r;
-    const float invn = __frcp_rn((float)n), invr = __frcp_rn((float)r);
+    const int nown = rhi - rlo;
+    const int total = nown * m * r;
+    const float invn = __frcp_rn((float)nown), invr = __frcp_rn((float)r);
     constexpr int U = 8;
     for (int t0 = tid_here(); t0 < total; t0 += U * WG) {
         double xv[U][CG_TAPS], cv[U][CG_TAPS];
@@ -113,7 +178,7 @@ __device__ __forceinline__ void apply_panel(const OpDev* ops, int m, int n, int 
 #pragma unroll
             for (int j = 0; j < CG_TAPS; ++j) xv[u][j] = cv[u][j] = 0.0;
             if (t < total) {
-                const int c = fdiv(t, invn), i = t - c * n;
+                const int c = fdiv(t, invn), i = rlo + (t - c * nown);
                 const int a = fdiv(c, invr), l = c - a * r;
                 const int kind = ops[a].kind, h = ops[a].hbw;
                 const double* data = ops[a].data;
@@ -150,7 +215,8 @@ __device__ __forceinline__ void apply_panel(const OpDev* ops, int m, int n, int 
                 double v = 0.0;
 #pragma unroll
                 for (int j = 0; j < CG_TAPS; ++j) v = fma(cv[u][j], xv[u][j], v);
-                stg(out + t, v);
+                const int c = fdiv(t, invn), i = rlo + (t - c * nown);
+                stg(out + i + (int64_t)c * n, v);
             }
         }
     }
@@ -166,11 +232,37 @@ __device__ __forceinline__ void refresh_dim(int k, int r0, bool lowp) {
     const Problem& pb = s.pb;
     const int n = pb.n[k], r = pb.r, m = pb.mA[k], mb = pb.mB[k];
     const double* Uk = pb.U + pb.offU[k];
-    apply_panel(pb.opA[k], m, n, r, Uk, pb.P);
+    int rlo, rhi;
+    own_rows(n, rlo, rhi);
+    apply_panel(pb.opA[k], m, n, r, Uk, pb.P, rlo, rhi);
     ColF fa{pb.P, n};
     ColF fb{pb.Q + pb.offQ[k], n};
-    if (lowp) gram_lds<true>(n, m * r, mb * r0, fa, fb, pb.G + pb.offG[k], m * r, pb.X + pb.offX[k], m * r, s.scratch, SCRATCH);
-    else gram_lds<false>(n, m * r, mb * r0, fa, fb, pb.G + pb.offG[k], m * r, pb.X + pb.offX[k], m * r, s.scratch, SCRATCH);
+    const int M1 = m * r, N2 = mb * r0;
+    const int W = ufirst(s.W);
+    double* G1 = pb.G + pb.offG[k];
+    double* G2 = pb.X + pb.offX[k];
+    if (W > 1) {
+        G1 = pb.gpart + (int64_t)ufirst(s.part) * pb.psz;
+        G2 = G1 + M1 * M1;
+    }
+    if (lowp) gram_lds<true>(rlo, rhi, M1, N2, fa, fb, G1, M1, G2, M1, s.scratch, SCRATCH);
+    else gram_lds<false>(rlo, rhi, M1, N2, fa, fb, G1, M1, G2, M1, s.scratch, SCRATCH);
+    if (W > 1) {
+        // every workgroup adds up its slice of the entries over the cluster's partials
+        cluster_sync();
+        const int tot = M1 * M1 + M1 * N2;
+        const int per = (tot + W - 1) / W;
+        const int e0 = ufirst(s.part) * per, e1 = min(tot, e0 + per);
+        double* Gk = pb.G + pb.offG[k];
+        double* Xk = pb.X + pb.offX[k];
+        for (int e = e0 + tid_here(); e < e1; e += WG) {
+            double acc = 0.0;
+            for (int w = 0; w < W; ++w) acc += ldg(pb.gpart + (int64_t)w * pb.psz + e);
+            if (e < M1 * M1) stg(Gk + e, acc);
+            else stg(Xk + (e - M1 * M1), acc);
+        }
+        cluster_sync();
+    }
 }
 
 // Q_k = [O_B^b V_k]_b for every dimension (the fixed B-side panels of a time step).
@@ -236,8 +328,10 @@ __device__ __forceinline__ double hadamard_pass(int q, bool withH0, int rc, int 
         s.slots[t] = sl;
     }
     // chunk geometry: PG groups of 64 positions, SPL = NWAVES / PG shares of the pair lists
+    const int W = ufirst(s.W), cpart = ufirst(s.part);
     int PG = NWAVES;
-    while (PG > 1 && 64 * PG * (nk * MM + (NWAVES / PG) * nblk) > SCRATCH) PG >>= 1;
+    while (PG > 1 && (64 * PG * (nk * MM + (NWAVES / PG) * nblk) > SCRATCH || (nE + 64 * PG - 1) / (64 * PG) < W))
+        PG >>= 1;
     PG = ufirst(PG);
     const int SPL = NWAVES / PG;
     const int E = 64 * PG;
@@ -248,7 +342,7 @@ __device__ __forceinline__ double hadamard_pass(int q, bool withH0, int rc, int 
     const float invr = __frcp_rn((float)r);
     __syncthreads();
     double trpart = 0.0;
-    for (int e0 = 0; e0 < nE; e0 += E) {
+    for (int e0 = cpart * E; e0 < nE; e0 += W * E) {
         // stage the slot entries of positions e0 .. e0 + E (a thread keeps one position)
         {
             const int ee = tid_here() & (E - 1);
@@ -394,7 +488,8 @@ __device__ __forceinline__ double assemble(int q, int r0) {
         trpart += hadamard_pass(q, c, c ? r : r0, c ? pb.MMq[q] : pb.MXq[q], c ? pb.G : pb.X, c ? mq * mq : mq * mbq,
                                 c ? pb.offC[q] : pb.offD[q], c ? pb.pairsC : pb.pairsD, c ? pb.Cm : pb.Dm, pb.trOO[q]);
     }
-    return wg_sum(trpart, s.red);  // includes the barrier that publishes C, D, H0
+    // (the cluster sum's barrier publishes the C, D and H0 entries of every workgroup)
+    return cluster_sum(wg_sum(trpart, s.red));
 }
 
 // ------------------------------------------------------------------------------------
@@ -467,7 +562,7 @@ __device__ __forceinline__ uint32_t factor_precond(double lam) {
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < PER; ++u)
-        if (hi[u] >= 0) stg(pb.Hinv + hi[u] + hj[u] * r, 0.5 * (hv[u] + Hm[hj[u] + hi[u] * r]));
+        if (hi[u] >= 0) stg(pb.Hinv + (int64_t)ufirst(s.part) * rr + hi[u] + hj[u] * r, 0.5 * (hv[u] + Hm[hj[u] + hi[u] * r]));
     __syncthreads();
     return fl;
 }
@@ -500,54 +595,60 @@ struct Xform {
     double alpha2;
 };
 
-// Transform of the own rows of a panel of `total` elements (contiguous, ld n): all loads of
-// a batch are issued before any store.  MODE 0: v = a; 1: v = a, wv = v; 2: v = a + beta b,
-// wv = v; 3: as 2 and x2 += alpha2 p2.  With `lds`, v goes to Xs[l ldx + H + i].
+// Transform of the rows [rlo, rlo + nown) of an n-row panel of rc columns (ld n): all loads
+// of a batch are issued before any store.  MODE 0: v = a; 1: v = a, wv = v; 2: v = a + beta b,
+// wv = v; 3: as 2 and x2 += alpha2 p2.  With `lds`, v goes to Xs[l ldx + H + (i - rlo)].
 template <int MODE>
-__device__ __forceinline__ void xform_rows(const Xform& xf, int total, int n, bool lds, double* Xs, int ldx, int H) {
+__device__ __forceinline__ void xform_rows(const Xform& xf, int n, int rlo, int nown, int rc, bool lds, double* Xs,
+                                           int ldx, int H) {
     constexpr int U = 8;
-    const float invn = __frcp_rn((float)n);
+    const int total = nown * rc;
+    const float invn = __frcp_rn((float)nown);
     for (int t0 = tid_here(); t0 < total; t0 += U * WG) {
         double va[U], vb[U], vx[U], vp[U];
+        int64_t idx[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int t = t0 + u * WG;
             const bool ok = t < total;
-            va[u] = ok ? ldg(xf.a + t) : 0.0;
-            vb[u] = (MODE >= 2 && ok) ? ldg(xf.b + t) : 0.0;
-            vx[u] = (MODE == 3 && ok) ? ldg(xf.x2 + t) : 0.0;
-            vp[u] = (MODE == 3 && ok) ? ldg(xf.p2 + t) : 0.0;
+            const int l = fdiv(t, invn);
+            idx[u] = (int64_t)(rlo + (t - l * nown)) + (int64_t)l * n;
+            va[u] = ok ? ldg(xf.a + idx[u]) : 0.0;
+            vb[u] = (MODE >= 2 && ok) ? ldg(xf.b + idx[u]) : 0.0;
+            vx[u] = (MODE == 3 && ok) ? ldg(xf.x2 + idx[u]) : 0.0;
+            vp[u] = (MODE == 3 && ok) ? ldg(xf.p2 + idx[u]) : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int t = t0 + u * WG;
             if (t < total) {
                 const double v = (MODE >= 2) ? fma(xf.beta, vb[u], va[u]) : va[u];
-                if (MODE >= 1) stg(xf.wv + t, v);
-                if (MODE == 3) stg(xf.x2 + t, fma(xf.alpha2, vp[u], vx[u]));
+                if (MODE >= 1) stg(xf.wv + idx[u], v);
+                if (MODE == 3) stg(xf.x2 + idx[u], fma(xf.alpha2, vp[u], vx[u]));
                 if (lds) {
                     const int l = fdiv(t, invn);
-                    Xs[l * ldx + H + (t - l * n)] = v;
+                    Xs[l * ldx + H + (t - l * nown)] = v;
                 }
             }
         }
     }
 }
 
-__device__ __forceinline__ void xform_dispatch(const Xform& xf, int total, int n, bool lds, double* Xs, int ldx, int H) {
+__device__ __forceinline__ void xform_dispatch(const Xform& xf, int n, int rlo, int nown, int rc, bool lds, double* Xs,
+                                               int ldx, int H) {
     const int mode = xf.x2 ? 3 : (xf.b ? 2 : (xf.wv ? 1 : 0));
     switch (ufirst(mode)) {
-        case 0: xform_rows<0>(xf, total, n, lds, Xs, ldx, H); break;
-        case 1: xform_rows<1>(xf, total, n, lds, Xs, ldx, H); break;
-        case 2: xform_rows<2>(xf, total, n, lds, Xs, ldx, H); break;
-        default: xform_rows<3>(xf, total, n, lds, Xs, ldx, H); break;
+        case 0: xform_rows<0>(xf, n, rlo, nown, rc, lds, Xs, ldx, H); break;
+        case 1: xform_rows<1>(xf, n, rlo, nown, rc, lds, Xs, ldx, H); break;
+        case 2: xform_rows<2>(xf, n, rlo, nown, rc, lds, Xs, ldx, H); break;
+        default: xform_rows<3>(xf, n, rlo, nown, rc, lds, Xs, ldx, H); break;
     }
 }
 
 
 template <bool F32, int TN>
 __device__ __forceinline__ double cgemm(int n, int r, const OpDev* comps, int nblk, int rc, Xform xf,
-                                        const double* Kt, double* out, double lam, bool shift, bool dot) {
+                                        const double* Kt, double* out, double lam, bool shift, bool dot, int rlo, int rhi) {
     constexpr int SPW = (TN == 4) ? 2 : 4;   // 16-row strips per wave and pass
     constexpr int LDB = TN * 16 + 1;
     constexpr int PF = (64 * TN * 16 + WG - 1) / WG;
@@ -563,51 +664,53 @@ __device__ __forceinline__ double cgemm(int n, int r, const OpDev* comps, int nb
     }
     H = ufirst(H);
     // rows per pass: as many strips as the waves hold, limited by the LDS staging area
-    int RP = min((n + 15) >> 4, NWAVES * SPW) * 16;
+    const int nown = rhi - rlo;
+    int RP = min((nown + 15) >> 4, NWAVES * SPW) * 16;
     auto ldx_of = [&](int rp) { return ((rp + 2 * H + 15) & ~31) + 16; };   // odd multiple of 16
     while (RP > 16 && ldx_of(RP) * rc + 2 * ktsz + 2 * CG_TAPS * RP > SCRATCH) RP -= 16;
     RP = ufirst(RP);
     const int ldx = ldx_of(RP);
     const int R = RP + 2 * H;
-    const int npass = (n + RP - 1) / RP;
+    const int npass = (nown + RP - 1) / RP;
+    // one pass over the whole grid: the halo is copied from the staged rows; otherwise own
+    // rows come from the transformed panel and halo rows are formed from the transform's
+    // inputs (never rewritten in place when there is a halo: p is double-buffered)
+    const bool single = nown == n && npass == 1;
     double* Xs = s.scratch;
     double* KtS = s.scratch + ldx * rc;
     double* CfS = KtS + 2 * ktsz;           // [2][CG_TAPS][RP] stencil coefficients of the pass rows
     const bool xw = xf.wv != nullptr || xf.x2 != nullptr;
+    const double* own_src = xw ? xf.wv : xf.a;
     __syncthreads();
-    if (xw && npass > 1) {
-        // several passes: apply the transform to the whole panel first
-        xform_dispatch(xf, n * rc, n, false, nullptr, 0, 0);
+    if (xw && !single) {
+        // apply the transform to the own rows first
+        xform_dispatch(xf, n, rlo, nown, rc, false, nullptr, 0, 0);
         __syncthreads();
-        xf.a = xf.wv;
-        xf.b = nullptr;
-        xf.wv = nullptr;
-        xf.x2 = nullptr;
     }
-    if (any_r1 && npass > 1) {
+    if (any_r1 && !single) {
         // rank-1 blocks: dots[blk rc + l] = w_blk^T X[:, l] from the full panel
         for (int b = 0; b < nblk; ++b) {
             if (comps[b].kind != CP_OP_RANK1) continue;
             const double* w = comps[b].data + n;
             for (int l = wave; l < rc; l += NWAVES) {
                 double acc = 0.0;
-                for (int i = lane; i < n; i += 64) acc = fma(ldg(w + i), ldg(xf.a + i + (int64_t)l * n), acc);
+                for (int i = lane; i < n; i += 64) acc = fma(ldg(w + i), ldg(own_src + i + (int64_t)l * n), acc);
                 acc = wave_sum(acc);
                 if (lane == 0) s.dots[b * rc + l] = acc;
             }
         }
     }
     double part = 0.0;
-    for (int i0 = 0; i0 < n; i0 += RP) {
+    for (int i0 = rlo; i0 < rhi; i0 += RP) {
         const int tid = tid_here();
         const int lane = tid & 63, wave = tid >> 6;
         const int kq = lane >> 4, cc = lane & 15;
-        const int nrow = min(RP, n - i0);
+        const int nrow = min(RP, rhi - i0);
         const int nsp = (nrow + 15) >> 4;
         // stage X rows i0 - H .. i0 + RP + H (periodic); in a single pass the halo is copied
         // from the staged rows afterwards (they may be rewritten by the transform)
-        if (npass == 1) {
-            xform_dispatch(xf, n * rc, n, true, Xs, ldx, H);
+        if (single) {
+            xform_dispatch(xf, n, 0, n, rc, true, Xs, ldx, H);
         } else {
             const float invR = __frcp_rn((float)R);
             batched_loop<8>(
@@ -615,7 +718,9 @@ __device__ __forceinline__ double cgemm(int n, int r, const OpDev* comps, int nb
                 [&](int t) {
                     const int l = fdiv(t, invR);
                     const int g = wrap_idx(i0 - H + (t - l * R), n);
-                    return ldg(xf.a + g + (int64_t)l * n);
+                    const int64_t o = g + (int64_t)l * n;
+                    if (g >= rlo && g < rhi) return ldg(own_src + o);
+                    return xf.b ? fma(xf.beta, ldg(xf.b + o), ldg(xf.a + o)) : ldg(xf.a + o);
                 },
                 [&](int t, double v) {
                     const int l = fdiv(t, invR);
@@ -623,7 +728,7 @@ __device__ __forceinline__ double cgemm(int n, int r, const OpDev* comps, int nb
                 });
         }
         __syncthreads();
-        if (npass == 1) {
+        if (single) {
             // halo rows 0..H-1 and H+n..R-1 from the staged rows
             const int nh = R - n;
             const float invh = __frcp_rn((float)max(nh, 1));
@@ -887,16 +992,24 @@ __device__ __forceinline__ void balance_scales() {
     __syncthreads();
 }
 
-__device__ __forceinline__ void scale_panels() {
+// Column scaling of the panels: every row (all_rows) or the own rows of every dimension.
+__device__ __forceinline__ void scale_panels(bool all_rows) {
     Smem& s = SMEM;
     const Problem& pb = s.pb;
     const int r = pb.r;
     for (int k = 0; k < pb.d; ++k) {
         const int n = pb.n[k];
+        int rlo = 0, rhi = n;
+        if (!all_rows) own_rows(n, rlo, rhi);
+        const int nown = rhi - rlo;
         double* u = pb.U + pb.offU[k];
-        const float invn = __frcp_rn((float)n);
-        batched_loop<8>(n * r, [&](int t) { return ldg(u + t); },
-                        [&](int t, double v) { stg(u + t, v * s.colnorm[k * r + fdiv(t, invn)]); });
+        const float invn = __frcp_rn((float)nown);
+        auto idx = [&](int t) {
+            const int l = fdiv(t, invn);
+            return (int64_t)(rlo + (t - l * nown)) + (int64_t)l * n;
+        };
+        batched_loop<8>(nown * r, [&](int t) { return ldg(u + idx(t)); },
+                        [&](int t, double v) { stg(u + idx(t), v * s.colnorm[k * r + fdiv(t, invn)]); });
     }
     __syncthreads();
 }
@@ -912,17 +1025,23 @@ __device__ __forceinline__ void scale_grams(int r0) {
         double* G = pb.G + pb.offG[k];
         const float invld = __frcp_rn((float)ld), invr = __frcp_rn((float)r);
         auto modr = [&](int v) { return v - fdiv(v, invr) * r; };
-        batched_loop<8>(ld * ld, [&](int t) { return ldg(G + t); },
+        // this workgroup's slice of the entries (all of them when alone)
+        const int W = ufirst(s.W), part = ufirst(s.part);
+        const int ng = ld * ld, perg = (ng + W - 1) / W, g0 = min(ng, part * perg), g1 = min(ng, g0 + perg);
+        batched_loop<8>(g1 - g0, [&](int t) { return ldg(G + g0 + t); },
                         [&](int t, double v) {
-                            const int j = fdiv(t, invld), i = t - j * ld;
-                            stg(G + t, v * sc[modr(i)] * sc[modr(j)]);
+                            const int e = g0 + t;
+                            const int j = fdiv(e, invld), i = e - j * ld;
+                            stg(G + e, v * sc[modr(i)] * sc[modr(j)]);
                         });
         double* X = pb.X + pb.offX[k];
         const int nx = ld * pb.mB[k] * r0;
-        batched_loop<8>(nx, [&](int t) { return ldg(X + t); },
+        const int perx = (nx + W - 1) / W, x0 = min(nx, part * perx), x1 = min(nx, x0 + perx);
+        batched_loop<8>(x1 - x0, [&](int t) { return ldg(X + x0 + t); },
                         [&](int t, double v) {
-                            const int j = fdiv(t, invld), i = t - j * ld;
-                            stg(X + t, v * sc[modr(i)]);
+                            const int e = x0 + t;
+                            const int j = fdiv(e, invld), i = e - j * ld;
+                            stg(X + e, v * sc[modr(i)]);
                         });
     }
     __syncthreads();
@@ -935,10 +1054,12 @@ enum : int { OP_STEP, OP_REFRESH, OP_UPDATE, OP_CG, OP_DELTA, OP_SWEEP, OP_REPOR
 // phases of one dimension update's composite products
 enum : int { PH_RHS, PH_PRE_B, PH_MV_X, PH_PRE_R0, PH_MV_P0, PH_PRE_R, PH_MV_P };
 
-__global__ void __launch_bounds__(WG) als_persistent(const Problem* __restrict__ problems, int count) {
+__global__ void __launch_bounds__(WG) als_persistent(const Problem* __restrict__ problems, int count, int W) {
     Smem& s = SMEM;
-    const int pid = blockIdx.x;
+    // workgroups pid W .. pid W + W - 1 advance problem pid together
+    const int pid = blockIdx.x / W;
     if (pid >= count) return;
+    const int cpart = blockIdx.x - pid * W;
     {
         const uint32_t* src = reinterpret_cast<const uint32_t*>(problems + pid);
         uint32_t* dst = reinterpret_cast<uint32_t*>(&s.pb);
@@ -947,6 +1068,11 @@ __global__ void __launch_bounds__(WG) als_persistent(const Problem* __restrict__
             s.ident.kind = CP_OP_IDENTITY;
             s.ident.hbw = 0;
             s.ident.data = nullptr;
+            s.part = cpart;
+            s.W = W;
+            s.bar_target = 0;
+            s.sync_ok = 1;
+            s.dcount = 0;
         }
     }
     __syncthreads();
@@ -966,24 +1092,42 @@ __global__ void __launch_bounds__(WG) als_persistent(const Problem* __restrict__
     bool lowp = false;
     double lam = 0.0, bz = 0.0, stop = 0.0, rz = 0.0, pw = 0.0, alpha = 0.0, beta = 0.0;
     double dmax2 = 0.0, eps = 0.0, fnorm = 0.0;
+    int psel = 0;   // which of the two search-direction buffers holds p
 
     while (op != OP_DONE) {
         op = ufirst(op);
+        if (ufirst((int)s.sync_ok) == 0) {
+            // a cluster barrier timed out: the problem is abandoned with a flag
+            if (cpart == 0 && tid_here() == 0) {
+                cp_als_report rep;
+                rep.sweeps = sw;
+                rep.pcg_iters = pcg_iters;
+                rep.eps_conv = eps;
+                rep.fnorm = fnorm;
+                rep.flags = flags | CP_FLAG_NOT_CONVERGED | CP_FLAG_SYNC_TIMEOUT;
+                rep.reserved = 0;
+                pb.reports[step < n_steps ? step : n_steps - 1] = rep;
+            }
+            break;
+        }
         if (op == OP_STEP) {
             r0 = (step == 0) ? pb.r0 : r;
-            if (step > 0) {
-                // f_n <- previous result (same packed layout, rank r)
-                for (int kk = 0; kk < d; ++kk) {
-                    const double* src = pb.U + pb.offU[kk];
-                    double* dst = pb.V + pb.offV[kk];
-                    batched_loop<8>(pb.n[kk] * r, [&](int t) { return ldg(src + t); }, [&](int t, double v) { stg(dst + t, v); });
+            if (cpart == 0) {
+                if (step > 0) {
+                    // f_n <- previous result (same packed layout, rank r)
+                    for (int kk = 0; kk < d; ++kk) {
+                        const double* src = pb.U + pb.offU[kk];
+                        double* dst = pb.V + pb.offV[kk];
+                        batched_loop<8>(pb.n[kk] * r, [&](int t) { return ldg(src + t); }, [&](int t, double v) { stg(dst + t, v); });
+                    }
+                    __syncthreads();
                 }
-                __syncthreads();
+                compute_Q_all(r0);
+                panel_colnorms();
+                balance_scales();
+                scale_panels(true);
             }
-            compute_Q_all(r0);
-            panel_colnorms();
-            balance_scales();
-            scale_panels();
+            cluster_sync();
             lowp = mixed && max_sweeps > 1;
             pcg_iters = 0;
             flags = CP_FLAG_NOT_CONVERGED;
@@ -1012,39 +1156,46 @@ __global__ void __launch_bounds__(WG) als_persistent(const Problem* __restrict__
             const OpDev* comps = pre ? &s.ident : (mv ? pb.compAA[q] : pb.compAB[q]);
             const int nblk = pre ? 1 : (mv ? m * m : m * pb.mB[q]);
             const int rc = ph == PH_RHS ? r0 : r;
-            const double* Kt = pre ? pb.Hinv : (mv ? pb.Cm : pb.Dm);
+            const double* Kt = pre ? pb.Hinv + (int64_t)cpart * r * r : (mv ? pb.Cm : pb.Dm);
             double* outp = pre ? pb.vz : (mv ? pb.vw : pb.vb);
+            double* pcur = psel ? pb.vp2 : pb.vp;
+            double* pnxt = psel ? pb.vp : pb.vp2;
+            int rlo, rhi;
+            own_rows(n, rlo, rhi);
             Xform xf{nullptr, nullptr, 0.0, nullptr, nullptr, nullptr, 0.0};
             switch (ph) {
                 case PH_RHS: xf.a = pb.V + pb.offV[q]; break;
                 case PH_PRE_B: xf.a = pb.vb; break;
                 case PH_MV_X: xf.a = pb.U + oq; xf.wv = pb.vx; break;                 // x <- U_q
                 case PH_PRE_R0: xf.a = pb.vb; xf.b = pb.vw; xf.beta = -1.0; xf.wv = pb.vr; break;  // r = b - A x
-                case PH_MV_P0: xf.a = pb.vz; xf.wv = pb.vp; break;                    // p = z
+                case PH_MV_P0: xf.a = pb.vz; xf.wv = pcur; break;                     // p = z
                 case PH_PRE_R:                                                        // r -= alpha w, x += alpha p
                     xf.a = pb.vr; xf.b = pb.vw; xf.beta = -alpha; xf.wv = pb.vr;
-                    xf.x2 = pb.vx; xf.p2 = pb.vp; xf.alpha2 = alpha;
+                    xf.x2 = pb.vx; xf.p2 = pcur; xf.alpha2 = alpha;
                     break;
-                default: xf.a = pb.vz; xf.b = pb.vp; xf.beta = beta; xf.wv = pb.vp; break;  // p = z + beta p
+                default: xf.a = pb.vz; xf.b = pcur; xf.beta = beta; xf.wv = pnxt; break;  // p' = z + beta p
             }
             const bool dot = ph != PH_RHS && ph != PH_MV_X;
             const bool f32 = lowp && !pre;
             const int tn = (r + 15) >> 4;
             double part;
             if (f32) {
-                if (tn == 1) part = cgemm<true, 1>(n, r, comps, nblk, rc, xf, Kt, outp, lam, mv, dot);
-                else if (tn == 2) part = cgemm<true, 2>(n, r, comps, nblk, rc, xf, Kt, outp, lam, mv, dot);
-                else part = cgemm<true, 4>(n, r, comps, nblk, rc, xf, Kt, outp, lam, mv, dot);
+                if (tn == 1) part = cgemm<true, 1>(n, r, comps, nblk, rc, xf, Kt, outp, lam, mv, dot, rlo, rhi);
+                else if (tn == 2) part = cgemm<true, 2>(n, r, comps, nblk, rc, xf, Kt, outp, lam, mv, dot, rlo, rhi);
+                else part = cgemm<true, 4>(n, r, comps, nblk, rc, xf, Kt, outp, lam, mv, dot, rlo, rhi);
             } else {
-                if (tn == 1) part = cgemm<false, 1>(n, r, comps, nblk, rc, xf, Kt, outp, lam, mv, dot);
-                else if (tn == 2) part = cgemm<false, 2>(n, r, comps, nblk, rc, xf, Kt, outp, lam, mv, dot);
-                else part = cgemm<false, 4>(n, r, comps, nblk, rc, xf, Kt, outp, lam, mv, dot);
+                if (tn == 1) part = cgemm<false, 1>(n, r, comps, nblk, rc, xf, Kt, outp, lam, mv, dot, rlo, rhi);
+                else if (tn == 2) part = cgemm<false, 2>(n, r, comps, nblk, rc, xf, Kt, outp, lam, mv, dot, rlo, rhi);
+                else part = cgemm<false, 4>(n, r, comps, nblk, rc, xf, Kt, outp, lam, mv, dot, rlo, rhi);
             }
-            const double val = ufirst(wg_sum(part, s.red));
+            // dot products are summed over the cluster (fixed order)
+            const double val = ufirst(dot ? cluster_sum(wg_sum(part, s.red)) : wg_sum(part, s.red));
+            if (ph == PH_MV_P) psel ^= 1;   // the new direction is now the current one
             bool finish = false;
             switch (ph) {
                 case PH_RHS:
                     flags |= factor_precond(lam);
+                    psel = 0;
                     ph = PH_PRE_B;
                     break;
                 case PH_PRE_B:
@@ -1096,14 +1247,35 @@ __global__ void __launch_bounds__(WG) als_persistent(const Problem* __restrict__
                 op = OP_DELTA;
             }
         } else if (op == OP_DELTA) {
-            // ||Delta f_q||^2 = sum((dU^T dU) o H0), dU = x - U_q; then U_q <- x
+            // ||Delta f_q||^2 = sum((dU^T dU) o H0), dU = x - U_q; then U_q <- x (own rows; the
+            // increment Gram partials of the cluster are added in a fixed order)
             const int n = pb.n[q];
             double* Uq = pb.U + pb.offU[q];
-            gram_lds<false>(n, r, 0, DiffF{pb.vx, Uq, n}, DiffF{pb.vx, Uq, n}, pb.S, r, nullptr, 0, s.scratch, SCRATCH);
-            batched_loop<8>(n * r, [&](int t) { return ldg(pb.vx + t); }, [&](int t, double v) { stg(Uq + t, v); });
+            int rlo, rhi;
+            own_rows(n, rlo, rhi);
+            const int W = ufirst(s.W);
+            double* S = W > 1 ? pb.spart + (int64_t)cpart * r * r : pb.S;
+            gram_lds<false>(rlo, rhi, r, 0, DiffF{pb.vx, Uq, n}, DiffF{pb.vx, Uq, n}, S, r, nullptr, 0, s.scratch, SCRATCH);
+            {
+                const int nown = rhi - rlo;
+                const float invn = __frcp_rn((float)nown);
+                auto idx = [&](int t) {
+                    const int l = fdiv(t, invn);
+                    return (int64_t)(rlo + (t - l * nown)) + (int64_t)l * n;
+                };
+                batched_loop<8>(nown * r, [&](int t) { return ldg(pb.vx + idx(t)); }, [&](int t, double v) { stg(Uq + idx(t), v); });
+            }
+            cluster_sync();   // (a workgroup barrier when alone) publishes U_q and the partials
             double part = 0.0;
-            for (int t = tid_here(); t < r * r; t += WG) part = fma(ldg(pb.S + t), ldg(pb.H0 + t), part);
-            const double delta2 = ufirst(wg_sum(part, s.red));   // its barriers also publish U_q
+            for (int t = tid_here(); t < r * r; t += WG) {
+                double sv = 0.0;
+                if (W > 1)
+                    for (int w = 0; w < W; ++w) sv += ldg(pb.spart + (int64_t)w * r * r + t);
+                else
+                    sv = ldg(pb.S + t);
+                part = fma(sv, ldg(pb.H0 + t), part);
+            }
+            const double delta2 = ufirst(wg_sum(part, s.red));
             dmax2 = fmax(dmax2, delta2);
             k = q;
             k_end = q + 1;
@@ -1127,8 +1299,10 @@ __global__ void __launch_bounds__(WG) als_persistent(const Problem* __restrict__
             eps = fnorm > 0.0 ? dmax / fnorm : dmax;
             gram_colnorms();
             balance_scales();
-            scale_panels();
+            cluster_sync();   // every workgroup has read G before any of them rescales it
+            scale_panels(false);
             scale_grams(r0);
+            cluster_sync();
             const bool was_low = lowp;
             bool refresh_all = false;
             bool done = false;
@@ -1163,7 +1337,7 @@ __global__ void __launch_bounds__(WG) als_persistent(const Problem* __restrict__
                 }
             }
         } else {   // OP_REPORT
-            if (tid_here() == 0) {
+            if (cpart == 0 && tid_here() == 0) {
                 cp_als_report rep;
                 rep.sweeps = sw;
                 rep.pcg_iters = pcg_iters;
@@ -1173,7 +1347,7 @@ __global__ void __launch_bounds__(WG) als_persistent(const Problem* __restrict__
                 rep.reserved = 0;
                 pb.reports[step] = rep;
             }
-            if (pb.traj) {
+            if (pb.traj && cpart == 0) {
                 double* dst = pb.traj + (int64_t)step * [&] {
                     int64_t tot = 0;
                     for (int kk = 0; kk < d; ++kk) tot += (int64_t)pb.n[kk] * r;
@@ -1195,12 +1369,12 @@ __global__ void __launch_bounds__(WG) als_persistent(const Problem* __restrict__
 
 size_t als_smem_bytes() { return sizeof(Smem); }
 
-hipError_t launch_als(const Problem* d_problems, int count, hipStream_t stream) {
+hipError_t launch_als(const Problem* d_problems, int count, int W, hipStream_t stream) {
     const size_t smem = sizeof(Smem);
     hipError_t e = hipFuncSetAttribute((const void*)als_persistent, hipFuncAttributeMaxDynamicSharedMemorySize,
                                        (int)smem);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(als_persistent, dim3(count), dim3(WG), smem, stream, d_problems, count);
+    hipLaunchKernelGGL(als_persistent, dim3(count * W), dim3(WG), smem, stream, d_problems, count, W);
     return hipGetLastError();
 }
 

@@ -18,7 +18,7 @@ int gram_chunks(const int32_t* n, int d, int32_t* chunk0);
 hipError_t launch_inner(const GramJob& job, double* partial, double* out, bool sqrt_out, hipStream_t st);
 hipError_t launch_apply(const ApplyJob& job, int max_n, hipStream_t st);
 // defined in als_kernel.hip
-hipError_t launch_als(const Problem* d_problems, int count, hipStream_t stream);
+hipError_t launch_als(const Problem* d_problems, int count, int W, hipStream_t stream);
 size_t als_smem_bytes();
 }  // namespace cpals
 
@@ -27,6 +27,7 @@ using namespace cpals;
 struct cp_handle_s {
     hipStream_t stream = nullptr;
     int device = 0;
+    int max_cluster = 16;     // workgroups that may share one problem (cp_set_cluster)
     std::string err;
     void* ws = nullptr;
     size_t ws_bytes = 0;
@@ -334,7 +335,8 @@ cp_status compose_t(cp_handle h, const cp_op1d& a, const cp_op1d& b, CompOp& out
 
 // Byte layout of one problem's device region.
 struct Layout {
-    size_t problem, opdata, pairsC, pairsD, U, V, Q, G, X, P, Z, Cm, Dm, H0, Hinv, S, vec, reports, total;
+    size_t problem, opdata, pairsC, pairsD, U, V, Q, G, X, P, Z, Cm, Dm, H0, Hinv, S, vec, reports, bar, gpart, spart, dpart,
+        total;
     size_t n_opdata, n_pairsC, n_pairsD;
     int64_t offU[CP_MAX_DIMS], offV[CP_MAX_DIMS], offQ[CP_MAX_DIMS], offG[CP_MAX_DIMS], offX[CP_MAX_DIMS];
     int nmax, mAmax, mBmax, r0max;
@@ -350,7 +352,7 @@ struct Packed {
 };
 
 cp_status pack_problem(cp_handle h, const HostOp& A, const HostOp& B, const cp_tensor* f_init, const cp_tensor* f_io,
-                       int n_steps, const cp_als_opts& o, Packed& pk) {
+                       int n_steps, const cp_als_opts& o, int W, Packed& pk) {
     const int d = f_io->d, r = f_io->r, r0 = f_init->r;
     Problem& pb = pk.pb;
     std::memset(&pb, 0, sizeof(pb));
@@ -493,10 +495,19 @@ cp_status pack_problem(cp_handle h, const HostOp& A, const HostOp& B, const cp_t
     L.Cm = take((size_t)(L.mAmax * r) * (L.mAmax * r) * 8);
     L.Dm = take((size_t)(L.mAmax * r) * (L.mBmax * L.r0max) * 8);
     L.H0 = take((size_t)r * r * 8);
-    L.Hinv = take((size_t)r * r * 8);
+    L.Hinv = take((size_t)W * r * r * 8);
     L.S = take((size_t)r * r * 8);
-    L.vec = take((size_t)6 * align_up((size_t)L.nmax * r * 8));
+    L.vec = take((size_t)7 * align_up((size_t)L.nmax * r * 8));
     L.reports = take((size_t)n_steps * sizeof(cp_als_report));
+    size_t psz = 0;
+    for (int k = 0; k < d; ++k)
+        psz = std::max(psz, (size_t)(A.m[k] * r) * (A.m[k] * r) + (size_t)(A.m[k] * r) * (B.m[k] * L.r0max));
+    pb.W = W;
+    pb.psz = (int32_t)psz;
+    L.bar = take(256);
+    L.gpart = take(W > 1 ? (size_t)W * psz * 8 : 8);
+    L.spart = take(W > 1 ? (size_t)W * r * r * 8 : 8);
+    L.dpart = take((size_t)2 * W * 8 * 8);
     L.total = off;
     L.n_opdata = pk.opdata.size();
     L.n_pairsC = pk.pairsC.size();
@@ -581,7 +592,12 @@ void rebase(Packed& pk, char* base, double* traj) {
     pb.vz = reinterpret_cast<double*>(vb + 3 * vstride);
     pb.vp = reinterpret_cast<double*>(vb + 4 * vstride);
     pb.vw = reinterpret_cast<double*>(vb + 5 * vstride);
+    pb.vp2 = reinterpret_cast<double*>(vb + 6 * vstride);
     pb.reports = reinterpret_cast<cp_als_report*>(base + L.reports);
+    pb.bar = reinterpret_cast<uint32_t*>(base + L.bar);
+    pb.gpart = reinterpret_cast<double*>(base + L.gpart);
+    pb.spart = reinterpret_cast<double*>(base + L.spart);
+    pb.dpart = reinterpret_cast<double*>(base + L.dpart);
     pb.traj = traj;
 }
 
@@ -615,8 +631,28 @@ cp_status run_problems(cp_handle h, int count, const HostOp* A, const HostOp* B,
     std::vector<Packed> pk(count);
     std::vector<size_t> base(count);
     size_t total = 0;
+    // a single problem is shared by a cluster of workgroups (grid rows split between them)
+    // when every n_k splits into 16-row strips and no rank-1 operator is present
+    int W = 1;
+    if (count == 1) {
+        bool ok = f_io[0].d > 1;
+        for (int k = 0; k < f_io[0].d; ++k) {
+            for (int a = 0; a < A[0].m[k]; ++a) ok = ok && A[0].ops[k][a].kind != CP_OP_RANK1;
+            for (int b = 0; b < B[0].m[k]; ++b) ok = ok && B[0].ops[k][b].kind != CP_OP_RANK1;
+        }
+        W = ok ? std::max(1, std::min(h->max_cluster, 256)) : 1;
+        // largest power of two <= max_cluster with n_k divisible by 16 W for every k
+        int w = 1;
+        while (2 * w <= W) w *= 2;
+        W = w;
+        for (; W > 1; W /= 2) {
+            bool div = true;
+            for (int k = 0; k < f_io[0].d; ++k) div = div && (f_io[0].n[k] % (16 * W) == 0);
+            if (div) break;
+        }
+    }
     for (int i = 0; i < count; ++i) {
-        cp_status st = pack_problem(h, A[i], B[i], &f_init[i], &f_io[i], n_steps, *o, pk[i]);
+        cp_status st = pack_problem(h, A[i], B[i], &f_init[i], &f_io[i], n_steps, *o, W, pk[i]);
         if (st != CP_OK) return st;
         base[i] = total;
         total += align_up(pk[i].lay.total);
@@ -655,12 +691,13 @@ cp_status run_problems(cp_handle h, int count, const HostOp* A, const HostOp* B,
         if (st != CP_OK) return st;
         st = copy_panels_in(h, &f_io[i], p.pb.U, p.pb.offU);
         if (st != CP_OK) return st;
+        HIP_TRY(hipMemsetAsync(p.pb.bar, 0, 256, h->stream), "hipMemsetAsync(barrier)");
     }
     for (int j = 0; j < count; ++j) descs[j] = pk[order[j]].pb;
     Problem* d_desc = reinterpret_cast<Problem*>(ws + total);
     HIP_TRY(hipMemcpyAsync(d_desc, descs.data(), (size_t)count * sizeof(Problem), hipMemcpyHostToDevice, h->stream),
             "hipMemcpyAsync(problems)");
-    HIP_TRY(launch_als(d_desc, count, h->stream), "als kernel launch");
+    HIP_TRY(launch_als(d_desc, count, W, h->stream), "als kernel launch");
     for (int i = 0; i < count; ++i) {
         st = copy_panels_out(h, pk[i].pb.U, pk[i].pb.offU, &f_io[i]);
         if (st != CP_OK) return st;
@@ -737,6 +774,13 @@ cp_status cp_set_stream(cp_handle h, void* hip_stream) {
 }
 
 const char* cp_last_error(cp_handle h) { return h ? h->err.c_str() : "null handle"; }
+
+cp_status cp_set_cluster(cp_handle h, int32_t max_workgroups) {
+    if (!h) return CP_ERR_INVALID_ARG;
+    if (max_workgroups < 1 || max_workgroups > 256) return fail(h, CP_ERR_INVALID_ARG, "max_workgroups must be in 1..256");
+    h->max_cluster = max_workgroups;
+    return CP_OK;
+}
 
 cp_status cp_als_default_opts(cp_als_opts* o) {
     if (!o) return CP_ERR_INVALID_ARG;

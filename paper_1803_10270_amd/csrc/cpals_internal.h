@@ -67,6 +67,14 @@ struct Problem {
     // outputs
     cp_als_report* reports;   // device array of n_steps
     double* traj;             // nullable: n_steps * sum_k n_k r
+    // cluster of W workgroups advancing this problem together (grid rows split between
+    // them); W = 1: one workgroup.  Partial sums meet in device memory after a barrier.
+    int32_t W, psz;           // cluster size; doubles per workgroup in the Gram partial area
+    uint32_t* bar;            // arrival counter of the cluster barrier (zero at launch)
+    double* gpart;            // [W][psz] Gram / cross-Gram partials
+    double* spart;            // [W][r r] increment-Gram partials
+    double* dpart;            // [2][W][8] scalar partials (dot products, trace), alternating
+    double* vp2;              // second search-direction buffer (p is double-buffered)
 };
 
 // Scalar product of two CP tensors: per-dimension Gram partials over row chunks.

@@ -153,7 +153,7 @@ struct PanelA {
 };
 
 // ---------------------------------------------------------------------------------------
-// Gram products over row chunks staged in LDS:
+// Gram products over the rows i_begin .. i_end - 1, in chunks staged in LDS:
 //   G1 (M1 x M1, symmetric) = A^T A  and optionally  G2 (M1 x N2) = A^T B,
 // where element (i, c) of A (c < M1) and of B (c < N2) come from panel functors with
 //   raw(i, c) -> raw_t (loads only) and val(raw_t) -> double,
@@ -187,8 +187,10 @@ __device__ __forceinline__ void gram_stage(const F& f, int n, int i0, int ncol, 
 }
 
 template <bool F32, class FA, class FB>
-__device__ __forceinline__ void gram_lds(int n, int M1, int N2, const FA& fa, const FB& fb, double* __restrict__ G1,
-                                         int ld1, double* __restrict__ G2, int ld2, double* lds, int cap) {
+__device__ __forceinline__ void gram_lds(int i_begin, int i_end, int M1, int N2, const FA& fa, const FB& fb,
+                                         double* __restrict__ G1, int ld1, double* __restrict__ G2, int ld2, double* lds,
+                                         int cap) {
+    const int n = i_end;   // rows i_begin .. i_end - 1
     constexpr int PFN = 16;   // prefetched elements per thread and operand
     const int lane = tid_here() & 63, wave = tid_here() >> 6;
     const int TM = (M1 + 15) >> 4, TN = (N2 + 15) >> 4;
@@ -232,14 +234,14 @@ __device__ __forceinline__ void gram_lds(int n, int M1, int N2, const FA& fa, co
 #pragma unroll
         for (int t = 0; t < GRAM_TPW; ++t) acc[t].zero();
         __syncthreads();
-        gram_stage(fa, n, 0, M1, na, lgKC, lds, wa);
-        gram_stage(fb, n, 0, N2, nb, lgKC, lds + KC * wa, wb);
+        gram_stage(fa, n, i_begin, M1, na, lgKC, lds, wa);
+        gram_stage(fb, n, i_begin, N2, nb, lgKC, lds + KC * wa, wb);
         __syncthreads();
-        for (int c = 0; c * KC < n; ++c) {
+        for (int c = 0; i_begin + c * KC < n; ++c) {
             const int buf = pre ? (c & 1) : 0;
             const double* As = lds + buf * bufsz;
             const double* Bs = As + KC * wa;
-            const int i1 = (c + 1) * KC;
+            const int i1 = i_begin + (c + 1) * KC;
             const bool more = i1 < n;
             typename FA::raw_t ra[PFN];
             typename FB::raw_t rb[PFN];

@@ -186,11 +186,43 @@ def test_batched_matches_single(handle):
     fo = [dev(p.guess) for p in probs]
     opts = B.default_opts(tol=1e-8, max_sweeps=30)
     reps = B.cp_als_run_batched(handle, [p.A for p in probs], [p.B for p in probs], fi, fo, 2, opts)
-    for p, f, rb in zip(probs, fo, reps):
-        g = dev(p.guess)
-        rs = B.cp_als_run(handle, p.A, p.B, dev(p.f0), g, 2, opts)
-        assert [r["sweeps"] for r in rs] == [r["sweeps"] for r in rb]
-        assert all(np.array_equal(a, b) for a, b in zip(host(f), host(g)))
+    handle.set_cluster(1)          # single calls on one workgroup, like the batched launch
+    try:
+        for p, f, rb in zip(probs, fo, reps):
+            g = dev(p.guess)
+            rs = B.cp_als_run(handle, p.A, p.B, dev(p.f0), g, 2, opts)
+            assert [r["sweeps"] for r in rs] == [r["sweeps"] for r in rb]
+            assert all(np.array_equal(a, b) for a, b in zip(host(f), host(g)))
+    finally:
+        handle.set_cluster(16)
+
+
+@pytest.mark.parametrize("cluster", [2, 4, 8])
+def test_cluster_matches_single_workgroup(handle, cluster):
+    """A problem shared by a cluster of workgroups (grid rows split, partial sums added in a
+    fixed order) agrees with one workgroup to rounding, and is itself deterministic."""
+    log("cluster", cluster)
+    p = W.advection_ie_variable(seed=5, d=4, n=128, ic_rank=3, cap=6)
+    handle.set_cluster(1)
+    try:
+        ref, rr = run_gpu_step(handle, p.A, p.B, p.f0, p.guess, tol=0.0, max_sweeps=4)
+        handle.set_cluster(cluster)
+        a, ra = run_gpu_step(handle, p.A, p.B, p.f0, p.guess, tol=0.0, max_sweeps=4)
+        b, _ = run_gpu_step(handle, p.A, p.B, p.f0, p.guess, tol=0.0, max_sweeps=4)
+    finally:
+        handle.set_cluster(16)
+    assert all(np.array_equal(x, y) for x, y in zip(a, b))
+    assert not (ra["flags"] & B.FLAG_SYNC_TIMEOUT)
+    dist = tensor_distance(a, ref)
+    log("cluster %d: distance to one workgroup %.3e, pcg iterations %d vs %d" % (cluster, dist, ra["pcg_iters"], rr["pcg_iters"]))
+    assert dist <= 1e-12
+
+
+def test_set_cluster_rejects_out_of_range(handle):
+    with pytest.raises(B.CpalsError):
+        handle.set_cluster(0)
+    with pytest.raises(B.CpalsError):
+        handle.set_cluster(257)
 
 
 def test_deterministic(handle):
