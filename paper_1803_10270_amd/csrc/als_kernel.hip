@@ -126,6 +126,7 @@ __device__ __forceinline__ double cluster_sum(double v) {
     if (tid_here() == 0) stg(base + part * 8, v);
     cluster_sync();
     double tot = 0.0;
+#pragma unroll 8
     for (int w = 0; w < W; ++w) tot += ldg(base + w * 8);
     __syncthreads();
     if (tid_here() == 0) s.dcount += 1u;
@@ -257,6 +258,7 @@ __device__ __forceinline__ void refresh_dim(int k, int r0, bool lowp) {
         double* Xk = pb.X + pb.offX[k];
         for (int e = e0 + tid_here(); e < e1; e += WG) {
             double acc = 0.0;
+#pragma unroll 8
             for (int w = 0; w < W; ++w) acc += ldg(pb.gpart + (int64_t)w * pb.psz + e);
             if (e < M1 * M1) stg(Gk + e, acc);
             else stg(Xk + (e - M1 * M1), acc);
@@ -676,9 +678,13 @@ __device__ __forceinline__ double cgemm(int n, int r, const OpDev* comps, int nb
     // rows come from the transformed panel and halo rows are formed from the transform's
     // inputs (never rewritten in place when there is a halo: p is double-buffered)
     const bool single = nown == n && npass == 1;
+    // When every operator block's Kt rows and stencil coefficients fit in LDS beside the
+    // staged rows (short passes: a cluster's share of the grid), they are staged once per
+    // pass; otherwise block b + 1 is prefetched while block b is consumed.
+    const bool allk = ufirst((int)(ldx * rc + nblk * (ktsz + CG_TAPS * RP) <= SCRATCH)) != 0;
     double* Xs = s.scratch;
-    double* KtS = s.scratch + ldx * rc;
-    double* CfS = KtS + 2 * ktsz;           // [2][CG_TAPS][RP] stencil coefficients of the pass rows
+    double* KtS = s.scratch + ldx * rc;                  // [nkb][rc4][LDB]
+    double* CfS = KtS + (allk ? nblk : 2) * ktsz;        // [nkb][CG_TAPS][RP] stencil coefficients
     const bool xw = xf.wv != nullptr || xf.x2 != nullptr;
     const double* own_src = xw ? xf.wv : xf.a;
     __syncthreads();
@@ -707,6 +713,12 @@ __device__ __forceinline__ double cgemm(int n, int r, const OpDev* comps, int nb
         const int kq = lane >> 4, cc = lane & 15;
         const int nrow = min(RP, rhi - i0);
         const int nsp = (nrow + 15) >> 4;
+        // fewer strips than waves with every block staged: the waves split the operator
+        // blocks (G groups per strip) and their partial tiles are added afterwards
+        const int G = (allk && nsp < NWAVES && NWAVES % nsp == 0 &&
+                       (NWAVES - nsp) * TN * 256 <= SCRATCH - ldx * rc) ? NWAVES / nsp : 1;
+        const int kg = G > 1 ? wave / nsp : 0;
+        const int wstrip = G > 1 ? wave - kg * nsp : wave;
         // stage X rows i0 - H .. i0 + RP + H (periodic); in a single pass the halo is copied
         // from the staged rows afterwards (they may be rewritten by the transform)
         if (single) {
@@ -750,15 +762,22 @@ __device__ __forceinline__ double cgemm(int n, int r, const OpDev* comps, int nb
                 }
             }
         }
-        // Kt block 0
-        batched_loop<4>(
-            rc4 * TN * 16,
-            [&](int t) {
-                const int k = t / (TN * 16), j = t - k * (TN * 16);
-                return (k < rc && j < r) ? ldg(Kt + j + (int64_t)k * r) : 0.0;
-            },
-            [&](int t, double v) { KtS[(t / (TN * 16)) * LDB + t % (TN * 16)] = v; });
-        __syncthreads();
+        // Kt block 0 (or every block)
+        {
+            const int per = rc4 * TN * 16;
+            const int nkb = allk ? nblk : 1;
+            batched_loop<8>(
+                nkb * per,
+                [&](int t) {
+                    const int b = t / per, e = t - b * per;
+                    const int k = e / (TN * 16), j = e - k * (TN * 16);
+                    return (k < rc && j < r) ? ldg(Kt + j + (int64_t)(b * rc + k) * r) : 0.0;
+                },
+                [&](int t, double v) {
+                    const int b = t / per, e = t - b * per;
+                    KtS[b * ktsz + (e / (TN * 16)) * LDB + e % (TN * 16)] = v;
+                });
+        }
         Tile<F32> acc[SPW][TN];
 #pragma unroll
         for (int u = 0; u < SPW; ++u)
@@ -789,23 +808,40 @@ __device__ __forceinline__ double cgemm(int n, int r, const OpDev* comps, int nb
                 if (t < CG_TAPS * RP) CfS[buf * CG_TAPS * RP + t] = cv[u];
             }
         };
-        {
+        if (allk) {
+            const int per = CG_TAPS * RP;
+            const float invper = __frcp_rn((float)per);
+            batched_loop<8>(
+                nblk * per,
+                [&](int t) {
+                    const int b = fdiv(t, invper), e = t - b * per;
+                    const int j = fdiv(e, invRP), i = i0 + (e - j * RP);
+                    const int kind = comps[b].kind, h = comps[b].hbw;
+                    const bool band = kind == CP_OP_BAND;
+                    const int nt = (band && h <= 2) ? 2 * h + 1 : 1;
+                    if (!(j < nt && i < n && !(band && h > 2))) return 0.0;
+                    return (kind == CP_OP_IDENTITY) ? 1.0 : ldg(comps[b].data + (int64_t)j * n + i);
+                },
+                [&](int t, double v) { CfS[t] = v; });
+        } else {
             double cv[PFC];
             load_cf(0, cv);
             store_cf(0, cv);
         }
         __syncthreads();
-        for (int blk = 0; blk < nblk; ++blk) {
-            const int cur = blk & 1;
-            const bool more = blk + 1 < nblk;
+        for (int blk = kg; blk < nblk; blk += G) {
+            const int cur = allk ? blk : (blk & 1);
+            const bool more = !allk && blk + 1 < nblk;
             double pf[PF], pc[PFC];
+            if (more) {
 #pragma unroll
-            for (int u = 0; u < PF; ++u) {
-                const int t = tid + u * WG;
-                const int k = t / (TN * 16), j = t - k * (TN * 16);
-                pf[u] = (more && k < rc && j < r) ? ldg(Kt + j + (int64_t)((blk + 1) * rc + k) * r) : 0.0;
+                for (int u = 0; u < PF; ++u) {
+                    const int t = tid + u * WG;
+                    const int k = t / (TN * 16), j = t - k * (TN * 16);
+                    pf[u] = (k < rc && j < r) ? ldg(Kt + j + (int64_t)((blk + 1) * rc + k) * r) : 0.0;
+                }
+                load_cf(blk + 1, pc);
             }
-            if (more) load_cf(blk + 1, pc);
             const int kind = ufirst(comps[blk].kind);
             const int h = ufirst(comps[blk].hbw);
             const double* data = comps[blk].data;
@@ -820,7 +856,7 @@ __device__ __forceinline__ double cgemm(int n, int r, const OpDev* comps, int nb
             for (int u = 0; u < SPW; ++u)
 #pragma unroll
                 for (int j = 0; j < CG_TAPS; ++j)
-                    cf[u][j] = (j < nt && wave + NWAVES * u < nsp) ? CfS[(cur * CG_TAPS + j) * RP + (wave + NWAVES * u) * 16 + cc] : 0.0;
+                    cf[u][j] = (j < nt && wstrip + NWAVES * u < nsp) ? CfS[(cur * CG_TAPS + j) * RP + (wstrip + NWAVES * u) * 16 + cc] : 0.0;
             // one k-step: every lane forms the A elements of its strips (all LDS reads of the
             // step in flight together), then the matrix-core steps.  The tap count is fixed per
             // operator block, so the loop is instantiated per stencil width.
@@ -837,11 +873,11 @@ __device__ __forceinline__ double cgemm(int n, int r, const OpDev* comps, int nb
                         if (NTAP == 0) {
                             xv[u][0] = s.dots[blk * rc + l];   // rank-1 block: m_i (w^T X[:, l])
                         } else if (NTAP > 0) {
-                            const double* xr = Xs + l * ldx + (wave + NWAVES * u) * 16 + cc + off0;
+                            const double* xr = Xs + l * ldx + (wstrip + NWAVES * u) * 16 + cc + off0;
 #pragma unroll
                             for (int j = 0; j < NV; ++j) xv[u][j] = xr[j];
                         } else {
-                            const int strip = wave + NWAVES * u;
+                            const int strip = wstrip + NWAVES * u;
                             const int i = i0 + strip * 16 + cc;
                             double v = 0.0;
                             if (i < n && strip < nsp) {
@@ -871,7 +907,7 @@ __device__ __forceinline__ double cgemm(int n, int r, const OpDev* comps, int nb
                             a = xc[u][0];
                         }
                         a = lv ? a : 0.0;
-                        if (wave + NWAVES * u < nsp) {
+                        if (wstrip + NWAVES * u < nsp) {
                             // operands swapped: the tile holds out^T, so a lane's four results
                             // are four columns of sixteen consecutive rows (coalesced stores)
 #pragma unroll
@@ -902,13 +938,34 @@ __device__ __forceinline__ double cgemm(int n, int r, const OpDev* comps, int nb
                 }
                 store_cf(cur ^ 1, pc);
             }
+            if (!allk) __syncthreads();
+        }
+        if (G > 1) {
+            // partial tiles of groups 1 .. G-1 through LDS (the staged Kt area), added by
+            // group 0 in a fixed order
+            double* red = KtS;
             __syncthreads();
+            if (kg > 0 && wstrip < nsp) {
+#pragma unroll
+                for (int t = 0; t < TN; ++t)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v)
+                        red[(((kg - 1) * nsp + wstrip) * TN + t) * 256 + v * 64 + lane] = acc[0][t].get(v);
+            }
+            __syncthreads();
+            if (kg == 0 && wstrip < nsp) {
+                for (int g = 1; g < G; ++g)
+#pragma unroll
+                    for (int t = 0; t < TN; ++t)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) acc[0][t].add(v, red[(((g - 1) * nsp + wstrip) * TN + t) * 256 + v * 64 + lane]);
+            }
         }
         // epilogue
 #pragma unroll
         for (int u = 0; u < SPW; ++u) {
-            const int strip = wave + NWAVES * u;
-            if (strip < nsp) {
+            const int strip = wstrip + NWAVES * u;
+            if (strip < nsp && kg == 0) {
 #pragma unroll
                 for (int t = 0; t < TN; ++t) {
                     const int lr = strip * 16 + cc;
@@ -1269,8 +1326,10 @@ __global__ void __launch_bounds__(WG) als_persistent(const Problem* __restrict__
             double part = 0.0;
             for (int t = tid_here(); t < r * r; t += WG) {
                 double sv = 0.0;
-                if (W > 1)
+                if (W > 1) {
+#pragma unroll 8
                     for (int w = 0; w < W; ++w) sv += ldg(pb.spart + (int64_t)w * r * r + t);
+                }
                 else
                     sv = ldg(pb.S + t);
                 part = fma(sv, ldg(pb.H0 + t), part);

@@ -32,6 +32,7 @@ struct Tile<false> {
     __device__ __forceinline__ void zero() { v = d4{0.0, 0.0, 0.0, 0.0}; }
     __device__ __forceinline__ void step(double a, double b) { v = mfma_f64(a, b, v); }
     __device__ __forceinline__ double get(int i) const { return v[i]; }
+    __device__ __forceinline__ void add(int i, double x) { v[i] += x; }
     __device__ __forceinline__ static int row(int lane, int i) { return (lane >> 4) + 4 * i; }
 };
 
@@ -43,6 +44,7 @@ struct Tile<true> {
         v = __builtin_amdgcn_mfma_f32_16x16x4f32((float)a, (float)b, v, 0, 0, 0);
     }
     __device__ __forceinline__ double get(int i) const { return (double)v[i]; }
+    __device__ __forceinline__ void add(int i, double x) { v[i] += (float)x; }
     __device__ __forceinline__ static int row(int lane, int i) { return 4 * (lane >> 4) + i; }
 };
 
