@@ -113,6 +113,22 @@ __device__ __forceinline__ void cluster_sync() {
     __syncthreads();
 }
 
+// sum_{w < W} base[w stride] in the order w = 0, 1, ...: the loads of up to 16 partials
+// are in flight together (one round trip to memory for clusters of up to 16 workgroups)
+__device__ __forceinline__ double sum_partials(const double* base, int64_t stride, int W) {
+    constexpr int B = 16;
+    double acc = 0.0;
+    for (int w0 = 0; w0 < W; w0 += B) {
+        double v[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) v[u] = (w0 + u < W) ? ldg(base + (int64_t)(w0 + u) * stride) : 0.0;
+#pragma unroll
+        for (int u = 0; u < B; ++u)
+            if (w0 + u < W) acc += v[u];
+    }
+    return acc;
+}
+
 // Sum over the cluster of one workgroup-uniform value, in a fixed order (partials in
 // device memory, two alternating buffers so that a fast workgroup never overwrites a
 // partial that a slow one has not read).
@@ -125,9 +141,7 @@ __device__ __forceinline__ double cluster_sum(double v) {
     double* base = s.pb.dpart + (int64_t)buf * W * 8;
     if (tid_here() == 0) stg(base + part * 8, v);
     cluster_sync();
-    double tot = 0.0;
-#pragma unroll 8
-    for (int w = 0; w < W; ++w) tot += ldg(base + w * 8);
+    const double tot = sum_partials(base, 8, W);
     __syncthreads();
     if (tid_here() == 0) s.dcount += 1u;
     __syncthreads();
@@ -256,12 +270,17 @@ __device__ __forceinline__ void refresh_dim(int k, int r0, bool lowp) {
         const int e0 = ufirst(s.part) * per, e1 = min(tot, e0 + per);
         double* Gk = pb.G + pb.offG[k];
         double* Xk = pb.X + pb.offX[k];
-        for (int e = e0 + tid_here(); e < e1; e += WG) {
-            double acc = 0.0;
-#pragma unroll 8
-            for (int w = 0; w < W; ++w) acc += ldg(pb.gpart + (int64_t)w * pb.psz + e);
-            if (e < M1 * M1) stg(Gk + e, acc);
-            else stg(Xk + (e - M1 * M1), acc);
+        auto put = [&](int e, double v) {
+            if (e < M1 * M1) stg(Gk + e, v);
+            else stg(Xk + (e - M1 * M1), v);
+        };
+        // two entries per thread and pass, all their loads before the stores
+        for (int e = e0 + tid_here(); e < e1; e += 2 * WG) {
+            const bool two = e + WG < e1;
+            const double a0 = sum_partials(pb.gpart + e, pb.psz, W);
+            const double a1 = two ? sum_partials(pb.gpart + e + WG, pb.psz, W) : 0.0;
+            put(e, a0);
+            if (two) put(e + WG, a1);
         }
         cluster_sync();
     }
@@ -501,14 +520,16 @@ __device__ __forceinline__ double assemble(int q, int r0) {
 // column publish them to a double-buffered LDS copy, so each pivot costs one barrier.
 // Returns flags.
 // ------------------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t factor_precond(double lam) {
+template <int PER>
+__device__ __forceinline__ uint32_t factor_precond_t(double lam) {
     Smem& s = SMEM;
     const Problem& pb = s.pb;
     const int r = pb.r, rr = r * r;
-    constexpr int PER = (CP_MAX_RANK * CP_MAX_RANK + WG - 1) / WG;
     double* rowb = s.scratch;             // [2][CP_MAX_RANK]
     double* colb = s.scratch + 2 * CP_MAX_RANK;
     const float invr = __frcp_rn((float)r);
+    // entry u of this thread is t = tid + u WG = i + j r (column-major); entries past r r
+    // take i = j = -1, read row and column 0 and are never written
     double hv[PER];
     int hi[PER], hj[PER];
     double dmax = 0.0;
@@ -516,16 +537,21 @@ __device__ __forceinline__ uint32_t factor_precond(double lam) {
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
         const int t = tid_here() + u * WG;
-        hj[u] = fdiv(t, invr);
-        hi[u] = t - hj[u] * r;
-        hv[u] = 0.0;
-        if (t < rr) {
-            hv[u] = ldg(pb.H0 + t) + ((hi[u] == hj[u]) ? lam : 0.0);
-            if (hi[u] == hj[u]) dmax = fmax(dmax, hv[u]);
-            if (hi[u] == 0) rowb[hj[u]] = hv[u];
-            if (hj[u] == 0) colb[hi[u]] = hv[u];
-        } else {
-            hi[u] = hj[u] = -1;
+        hv[u] = (t < rr) ? ldg(pb.H0 + t) : 0.0;
+        const int j = fdiv(t, invr);
+        hi[u] = (t < rr) ? t - j * r : -1;
+        hj[u] = (t < rr) ? j : -1;
+    }
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int i = hi[u], j = hj[u];
+        if (i >= 0) {
+            if (i == j) {
+                hv[u] += lam;
+                dmax = fmax(dmax, hv[u]);
+            }
+            if (i == 0) rowb[j] = hv[u];
+            if (j == 0) colb[i] = hv[u];
         }
     }
     dmax = wave_max(dmax);
@@ -534,8 +560,13 @@ __device__ __forceinline__ uint32_t factor_precond(double lam) {
     dmax = 0.0;
     for (int w = 0; w < NWAVES; ++w) dmax = fmax(dmax, s.red[w]);
     uint32_t fl = 0;
-    for (int p = 0; p < r; ++p) {
-        const int cur = (p & 1) * CP_MAX_RANK, nxt = CP_MAX_RANK - cur;
+    // In-place Gauss-Jordan step on pivot p, with selects in place of branches:
+    //   row p: h[p][j] / piv (1 / piv on the diagonal); column p: -h[i][p] / piv;
+    //   elsewhere h[i][j] - h[i][p] h[p][j] / piv.
+    // Every read of the pivot row and column comes before the writes of the next ones.
+    // `cur` (which half of the double buffer holds pivot p) is a constant after inlining.
+    auto pivot = [&](int p, int cur) __attribute__((always_inline)) {
+        const int nxt = CP_MAX_RANK - cur;
         double piv = colb[cur + p];
         if (!(piv > 1e-12 * dmax)) fl |= CP_FLAG_REGULARIZED;
         if (!(piv > 0.0)) piv = (lam > 0.0) ? lam : 1e-300;
@@ -543,18 +574,21 @@ __device__ __forceinline__ uint32_t factor_precond(double lam) {
 #pragma unroll
         for (int u = 0; u < PER; ++u) {
             const int i = hi[u], j = hj[u];
-            if (i >= 0) {
-                const double hip = colb[cur + i], hpj = rowb[cur + j];
-                double nv;
-                if (i == p) nv = (j == p) ? ip : hpj * ip;
-                else if (j == p) nv = -hip * ip;
-                else nv = fma(-hip * ip, hpj, hv[u]);
-                hv[u] = nv;
-                if (i == p + 1) rowb[nxt + j] = nv;
-                if (j == p + 1) colb[nxt + i] = nv;
-            }
+            const double cv = colb[cur + max(i, 0)], rv = rowb[cur + max(j, 0)];
+            const double e = (j == p) ? 1.0 : rv;
+            const double base = (j == p) ? 0.0 : hv[u];
+            hv[u] = (i == p) ? e * ip : fma(-cv * ip, e, base);
+        }
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            if (hi[u] == p + 1) rowb[nxt + hj[u]] = hv[u];
+            if (hj[u] == p + 1) colb[nxt + hi[u]] = hv[u];
         }
         __syncthreads();
+    };
+    for (int p = 0; p < r; p += 2) {
+        pivot(p, 0);
+        if (p + 1 < r) pivot(p + 1, CP_MAX_RANK);
     }
     // symmetrise (the preconditioner of CG must be symmetric): through LDS
     double* Hm = s.scratch + 4 * CP_MAX_RANK;
@@ -562,11 +596,18 @@ __device__ __forceinline__ uint32_t factor_precond(double lam) {
     for (int u = 0; u < PER; ++u)
         if (hi[u] >= 0) Hm[hi[u] + hj[u] * r] = hv[u];
     __syncthreads();
+    double* Hout = pb.Hinv + (int64_t)ufirst(s.part) * rr;
 #pragma unroll
     for (int u = 0; u < PER; ++u)
-        if (hi[u] >= 0) stg(pb.Hinv + (int64_t)ufirst(s.part) * rr + hi[u] + hj[u] * r, 0.5 * (hv[u] + Hm[hj[u] + hi[u] * r]));
+        if (hi[u] >= 0) stg(Hout + hi[u] + hj[u] * r, 0.5 * (hv[u] + Hm[hj[u] + hi[u] * r]));
     __syncthreads();
     return fl;
+}
+
+__device__ __forceinline__ uint32_t factor_precond(double lam) {
+    constexpr int PER_SMALL = (32 * 32 + WG - 1) / WG;
+    constexpr int PER_FULL = (CP_MAX_RANK * CP_MAX_RANK + WG - 1) / WG;
+    return (SMEM.pb.r <= 32) ? factor_precond_t<PER_SMALL>(lam) : factor_precond_t<PER_FULL>(lam);
 }
 
 // ------------------------------------------------------------------------------------
@@ -648,6 +689,58 @@ __device__ __forceinline__ void xform_dispatch(const Xform& xf, int n, int rlo, 
 }
 
 
+// Staging of one pass with the transform fused: rows i0 - H .. i0 + nrow + H (periodic) of
+// v (MODE as in xform_rows) go to Xs[l ldx + j]; the pass rows (H <= j < H + nrow) also
+// write wv (and, MODE 3, x2 += alpha2 p2).  Halo rows are formed from the transform's
+// inputs, which the caller guarantees are not rewritten by this transform.
+template <int MODE>
+__device__ __forceinline__ void xform_stage(const Xform& xf, int n, int i0, int nrow, int H, int rc, double* Xs,
+                                            int ldx) {
+    constexpr int U = 8;
+    const int R = nrow + 2 * H;
+    const int total = R * rc;
+    const float invR = __frcp_rn((float)R);
+    for (int t0 = tid_here(); t0 < total; t0 += U * WG) {
+        double va[U], vb[U], vx[U], vp[U];
+        int64_t idx[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int t = t0 + u * WG;
+            const bool ok = t < total;
+            const int l = fdiv(t, invR), j = t - l * R;
+            const bool own = ok && j >= H && j < H + nrow;
+            idx[u] = (int64_t)wrap_idx(i0 - H + j, n) + (int64_t)l * n;
+            va[u] = ok ? ldg(xf.a + idx[u]) : 0.0;
+            vb[u] = (MODE >= 2 && ok) ? ldg(xf.b + idx[u]) : 0.0;
+            vx[u] = (MODE == 3 && own) ? ldg(xf.x2 + idx[u]) : 0.0;
+            vp[u] = (MODE == 3 && own) ? ldg(xf.p2 + idx[u]) : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int t = t0 + u * WG;
+            if (t < total) {
+                const int l = fdiv(t, invR), j = t - l * R;
+                const bool own = j >= H && j < H + nrow;
+                const double v = (MODE >= 2) ? fma(xf.beta, vb[u], va[u]) : va[u];
+                Xs[l * ldx + j] = v;
+                if (MODE >= 1 && own) stg(xf.wv + idx[u], v);
+                if (MODE == 3 && own) stg(xf.x2 + idx[u], fma(xf.alpha2, vp[u], vx[u]));
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ void xform_stage_dispatch(const Xform& xf, int n, int i0, int nrow, int H, int rc, double* Xs,
+                                                     int ldx) {
+    const int mode = xf.x2 ? 3 : (xf.b ? 2 : (xf.wv ? 1 : 0));
+    switch (ufirst(mode)) {
+        case 0: xform_stage<0>(xf, n, i0, nrow, H, rc, Xs, ldx); break;
+        case 1: xform_stage<1>(xf, n, i0, nrow, H, rc, Xs, ldx); break;
+        case 2: xform_stage<2>(xf, n, i0, nrow, H, rc, Xs, ldx); break;
+        default: xform_stage<3>(xf, n, i0, nrow, H, rc, Xs, ldx); break;
+    }
+}
+
 template <bool F32, int TN>
 __device__ __forceinline__ double cgemm(int n, int r, const OpDev* comps, int nblk, int rc, Xform xf,
                                         const double* Kt, double* out, double lam, bool shift, bool dot, int rlo, int rhi) {
@@ -687,8 +780,12 @@ __device__ __forceinline__ double cgemm(int n, int r, const OpDev* comps, int nb
     double* CfS = KtS + (allk ? nblk : 2) * ktsz;        // [nkb][CG_TAPS][RP] stencil coefficients
     const bool xw = xf.wv != nullptr || xf.x2 != nullptr;
     const double* own_src = xw ? xf.wv : xf.a;
+    // the transform rides along with the staging of each pass unless the rank-1 blocks need
+    // the whole transformed panel first, or a halo row could be read after being rewritten
+    const bool fused = !single && !any_r1 &&
+                       (H == 0 || (xf.wv != xf.a && xf.wv != xf.b && xf.x2 != xf.a && xf.x2 != xf.b));
     __syncthreads();
-    if (xw && !single) {
+    if (xw && !single && !fused) {
         // apply the transform to the own rows first
         xform_dispatch(xf, n, rlo, nown, rc, false, nullptr, 0, 0);
         __syncthreads();
@@ -723,6 +820,8 @@ __device__ __forceinline__ double cgemm(int n, int r, const OpDev* comps, int nb
         // from the staged rows afterwards (they may be rewritten by the transform)
         if (single) {
             xform_dispatch(xf, n, 0, n, rc, true, Xs, ldx, H);
+        } else if (fused) {
+            xform_stage_dispatch(xf, n, i0, nrow, H, rc, Xs, ldx);
         } else {
             const float invR = __frcp_rn((float)R);
             batched_loop<8>(
@@ -1304,8 +1403,7 @@ __global__ void __launch_bounds__(WG) als_persistent(const Problem* __restrict__
                 op = OP_DELTA;
             }
         } else if (op == OP_DELTA) {
-            // ||Delta f_q||^2 = sum((dU^T dU) o H0), dU = x - U_q; then U_q <- x (own rows; the
-            // increment Gram partials of the cluster are added in a fixed order)
+            // ||Delta f_q||^2 = sum((dU^T dU) o H0), dU = x - U_q; then U_q <- x (own rows)
             const int n = pb.n[q];
             double* Uq = pb.U + pb.offU[q];
             int rlo, rhi;
@@ -1322,19 +1420,14 @@ __global__ void __launch_bounds__(WG) als_persistent(const Problem* __restrict__
                 };
                 batched_loop<8>(nown * r, [&](int t) { return ldg(pb.vx + idx(t)); }, [&](int t, double v) { stg(Uq + idx(t), v); });
             }
-            cluster_sync();   // (a workgroup barrier when alone) publishes U_q and the partials
+            __syncthreads();
+            // this workgroup's share sum(S_w o H0) of ||Delta f_q||^2 (H0 is the same for every
+            // workgroup), then the shares in a fixed order; the cluster sum's barrier also
+            // publishes U_q
             double part = 0.0;
-            for (int t = tid_here(); t < r * r; t += WG) {
-                double sv = 0.0;
-                if (W > 1) {
-#pragma unroll 8
-                    for (int w = 0; w < W; ++w) sv += ldg(pb.spart + (int64_t)w * r * r + t);
-                }
-                else
-                    sv = ldg(pb.S + t);
-                part = fma(sv, ldg(pb.H0 + t), part);
-            }
-            const double delta2 = ufirst(wg_sum(part, s.red));
+#pragma unroll 4
+            for (int t = tid_here(); t < r * r; t += WG) part = fma(ldg(S + t), ldg(pb.H0 + t), part);
+            const double delta2 = ufirst(cluster_sum(wg_sum(part, s.red)));
             dmax2 = fmax(dmax2, delta2);
             k = q;
             k_end = q + 1;
