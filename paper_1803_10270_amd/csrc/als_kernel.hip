@@ -41,6 +41,8 @@ extern __shared__ __attribute__((aligned(16))) unsigned char cpals_smem[];
 struct Smem {
     Problem pb;
     OpDev ident;                 // the identity operator (preconditioner products)
+    int32_t bnt[CP_MAX_OPS * CP_MAX_OPS];    // per operator block of the current product: taps
+    int32_t boff[CP_MAX_OPS * CP_MAX_OPS];   // and first staged row of the stencil
     double red[2 * NWAVES];
     double dots[CP_MAX_OPS * CP_MAX_OPS * CP_MAX_RANK];
     double colnorm[CP_MAX_DIMS * CP_MAX_RANK];
@@ -758,6 +760,22 @@ __device__ __forceinline__ double cgemm(int n, int r, const OpDev* comps, int nb
         any_r1 |= comps[b].kind == CP_OP_RANK1;
     }
     H = ufirst(H);
+    // every block an identity, diagonal or band of at most 5 taps (the flat k-step split)
+    bool flat_ok = !any_r1;
+    int flat_taps = 1;
+    for (int b = 0; b < nblk; ++b) {
+        const bool band = comps[b].kind == CP_OP_BAND;
+        flat_ok &= !(band && comps[b].hbw > 2);
+        if (band) flat_taps = max(flat_taps, 2 * comps[b].hbw + 1);
+    }
+    flat_ok = ufirst((int)flat_ok) != 0;
+    flat_taps = ufirst(flat_taps);
+    if (tid_here() < nblk) {
+        const bool band = comps[tid_here()].kind == CP_OP_BAND;
+        const int h = comps[tid_here()].hbw;
+        s.bnt[tid_here()] = band ? 2 * h + 1 : 1;
+        s.boff[tid_here()] = band ? H - h : H;
+    }
     // rows per pass: as many strips as the waves hold, limited by the LDS staging area
     const int nown = rhi - rlo;
     int RP = min((nown + 15) >> 4, NWAVES * SPW) * 16;
@@ -862,19 +880,32 @@ __device__ __forceinline__ double cgemm(int n, int r, const OpDev* comps, int nb
             }
         }
         // Kt block 0 (or every block)
-        {
-            const int per = rc4 * TN * 16;
-            const int nkb = allk ? nblk : 1;
+        const int nkb = allk ? nblk : 1;
+        if (rc == rc4) {
+            // Kt rows (blk rc + k) are contiguous in memory and land at row (blk rc4 + k) of
+            // the staged layout; columns j >= r of a tile only reach outputs that are dropped
+            const float invr = __frcp_rn((float)r);
+            auto ld = [&](int t) { return ldg(Kt + t); };
+            auto st = [&](int t, double v) {
+                const int row = fdiv(t, invr);
+                KtS[row * LDB + (t - row * r)] = v;
+            };
+            if (allk) batched_loop<24>(nkb * rc * r, ld, st);
+            else batched_loop<8>(nkb * rc * r, ld, st);
+        } else {
+            constexpr int TW = TN * 16;
+            const int per = rc4 * TW;
+            const float invper = __frcp_rn((float)per);
             batched_loop<8>(
                 nkb * per,
                 [&](int t) {
-                    const int b = t / per, e = t - b * per;
-                    const int k = e / (TN * 16), j = e - k * (TN * 16);
+                    const int b = fdiv(t, invper), e = t - b * per;
+                    const int k = e / TW, j = e - k * TW;
                     return (k < rc && j < r) ? ldg(Kt + j + (int64_t)(b * rc + k) * r) : 0.0;
                 },
                 [&](int t, double v) {
-                    const int b = t / per, e = t - b * per;
-                    KtS[b * ktsz + (e / (TN * 16)) * LDB + e % (TN * 16)] = v;
+                    const int b = fdiv(t, invper), e = t - b * per;
+                    KtS[b * ktsz + (e / TW) * LDB + e % TW] = v;
                 });
         }
         Tile<F32> acc[SPW][TN];
@@ -928,7 +959,63 @@ __device__ __forceinline__ double cgemm(int n, int r, const OpDev* comps, int nb
             store_cf(0, cv);
         }
         __syncthreads();
-        for (int blk = kg; blk < nblk; blk += G) {
+        // One strip and every block staged with taps of at most 5: the k-steps of all blocks
+        // (blk, ks) are dealt to the waves in equal contiguous shares.  A wave gathers the
+        // operands of KC steps at once (B fragments, taps, coefficients), then issues their
+        // matrix-core steps back to back; the partial tiles meet below as in the block split.
+        const bool flat = G == NWAVES && nsp == 1 && flat_ok;
+        if (flat) {
+            const int spb = rc4 >> 2;                 // k-steps per block
+            const int T = nblk * spb;
+            const int s0 = (wave * T) / NWAVES, s1 = ((wave + 1) * T) / NWAVES;
+            const float invspb = __frcp_rn((float)spb);
+            // KC steps from c0 (those at or past s1 are skipped), stencils of up to TAPS taps;
+            // the staged coefficients of taps past a block's own are zero
+            auto chunk = [&](int c0, auto kc_c, auto taps_c) {
+                constexpr int KC = decltype(kc_c)::value;
+                constexpr int TAPS = decltype(taps_c)::value;
+                double bv[KC][TN], xv[KC][TAPS], cv[KC][TAPS];
+                bool lv[KC];
+#pragma unroll
+                for (int u = 0; u < KC; ++u) {
+                    const int st = min(c0 + u, s1 - 1);
+                    const int blk = fdiv(st, invspb), ks = (st - blk * spb) * 4;
+                    const int nt = s.bnt[blk], off0 = s.boff[blk];
+                    const int l = min(ks + kq, rc - 1);
+                    lv[u] = c0 + u < s1 && ks + kq < rc;
+#pragma unroll
+                    for (int t = 0; t < TN; ++t) bv[u][t] = KtS[blk * ktsz + (ks + kq) * LDB + t * 16 + cc];
+                    const double* xr = Xs + l * ldx + cc + off0;
+                    const double* cr = CfS + blk * CG_TAPS * RP + cc;
+#pragma unroll
+                    for (int j = 0; j < TAPS; ++j) {
+                        xv[u][j] = xr[min(j, nt - 1)];
+                        cv[u][j] = cr[j * RP];
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < KC; ++u) {
+                    if (c0 + u < s1) {
+                        double a = 0.0;
+#pragma unroll
+                        for (int j = 0; j < TAPS; ++j) a = fma(cv[u][j], xv[u][j], a);
+                        a = lv[u] ? a : 0.0;
+#pragma unroll
+                        for (int t = 0; t < TN; ++t) acc[0][t].step(bv[u][t], a);
+                    }
+                }
+            };
+            auto run = [&](auto taps_c) {
+                constexpr int KC = TN == 4 ? 4 : 8;
+                int c0 = s0;
+                for (; c0 + KC <= s1; c0 += KC) chunk(c0, std::integral_constant<int, KC>{}, taps_c);
+                for (; c0 < s1; c0 += 2) chunk(c0, std::integral_constant<int, 2>{}, taps_c);
+            };
+            if (flat_taps == 1) run(std::integral_constant<int, 1>{});
+            else if (flat_taps == 3) run(std::integral_constant<int, 3>{});
+            else run(std::integral_constant<int, 5>{});
+        }
+        for (int blk = flat ? nblk : kg; blk < nblk; blk += G) {
             const int cur = allk ? blk : (blk & 1);
             const bool more = !allk && blk + 1 < nblk;
             double pf[PF], pc[PFC];
