@@ -54,6 +54,10 @@ struct Smem {
     uint32_t bar_target;         // arrivals the next cluster barrier waits for (thread 0)
     uint32_t sync_ok;            // 0 once a cluster barrier timed out
     uint32_t dcount;             // calls of cluster_sum (selects the partial buffer)
+    // operator blocks and coefficients kept in LDS across the products of one solve:
+    // slot 0 the matvec, slot 1 the preconditioner (key: the Kt array; cleared per solve)
+    const double* kc_key[2];
+    int32_t kc_base[2], kc_size[2], kc_rlo[2];
 };
 static_assert(sizeof(Smem) <= 160 * 1024, "LDS budget of one workgroup");
 
@@ -745,7 +749,8 @@ __device__ __forceinline__ void xform_stage_dispatch(const Xform& xf, int n, int
 
 template <bool F32, int TN>
 __device__ __forceinline__ double cgemm(int n, int r, const OpDev* comps, int nblk, int rc, Xform xf,
-                                        const double* Kt, double* out, double lam, bool shift, bool dot, int rlo, int rhi) {
+                                        const double* Kt, double* out, double lam, bool shift, bool dot, int rlo, int rhi,
+                                        int slot) {
     constexpr int SPW = (TN == 4) ? 2 : 4;   // 16-row strips per wave and pass
     constexpr int LDB = TN * 16 + 1;
     constexpr int PF = (64 * TN * 16 + WG - 1) / WG;
@@ -793,8 +798,19 @@ __device__ __forceinline__ double cgemm(int n, int r, const OpDev* comps, int nb
     // staged rows (short passes: a cluster's share of the grid), they are staged once per
     // pass; otherwise block b + 1 is prefetched while block b is consumed.
     const bool allk = ufirst((int)(ldx * rc + nblk * (ktsz + CG_TAPS * RP) <= SCRATCH)) != 0;
+    // Kept blocks (one pass, every block staged): the slot of this product sits at the top of
+    // the scratch area (slot 1 highest, slot 0 below the space slot 1 takes), the staged rows
+    // and the reduction area of the block split at the bottom.  A slot is reused when its key,
+    // place and rows match.
+    const int REDSZ = (NWAVES - 1) * TN * 256;
+    const int SA = nblk * (ktsz + CG_TAPS * RP);
+    const int top1 = ufirst(s.kc_key[1] ? max(s.kc_size[1], ktsz + CG_TAPS * RP) : ktsz + CG_TAPS * RP);
+    const int kbase = slot == 1 ? SCRATCH - SA : SCRATCH - top1 - SA;
+    const bool keep = ufirst((int)(slot >= 0 && allk && npass == 1 && ldx * rc + REDSZ <= kbase)) != 0;
+    const bool hit = keep && ufirst((int)(s.kc_key[slot] == Kt && s.kc_base[slot] == kbase && s.kc_size[slot] == SA &&
+                                          s.kc_rlo[slot] == rlo)) != 0;
     double* Xs = s.scratch;
-    double* KtS = s.scratch + ldx * rc;                  // [nkb][rc4][LDB]
+    double* KtS = keep ? s.scratch + kbase : s.scratch + ldx * rc;   // [nkb][rc4][LDB]
     double* CfS = KtS + (allk ? nblk : 2) * ktsz;        // [nkb][CG_TAPS][RP] stencil coefficients
     const bool xw = xf.wv != nullptr || xf.x2 != nullptr;
     const double* own_src = xw ? xf.wv : xf.a;
@@ -831,7 +847,7 @@ __device__ __forceinline__ double cgemm(int n, int r, const OpDev* comps, int nb
         // fewer strips than waves with every block staged: the waves split the operator
         // blocks (G groups per strip) and their partial tiles are added afterwards
         const int G = (allk && nsp < NWAVES && NWAVES % nsp == 0 &&
-                       (NWAVES - nsp) * TN * 256 <= SCRATCH - ldx * rc) ? NWAVES / nsp : 1;
+                       (NWAVES - nsp) * TN * 256 <= (keep ? REDSZ : SCRATCH - ldx * rc)) ? NWAVES / nsp : 1;
         const int kg = G > 1 ? wave / nsp : 0;
         const int wstrip = G > 1 ? wave - kg * nsp : wave;
         // stage X rows i0 - H .. i0 + RP + H (periodic); in a single pass the halo is copied
@@ -881,7 +897,9 @@ __device__ __forceinline__ double cgemm(int n, int r, const OpDev* comps, int nb
         }
         // Kt block 0 (or every block)
         const int nkb = allk ? nblk : 1;
-        if (rc == rc4) {
+        if (hit) {
+            // kept from an earlier product of this solve
+        } else if (rc == rc4) {
             // Kt rows (blk rc + k) are contiguous in memory and land at row (blk rc4 + k) of
             // the staged layout; columns j >= r of a tile only reach outputs that are dropped
             const float invr = __frcp_rn((float)r);
@@ -938,7 +956,8 @@ __device__ __forceinline__ double cgemm(int n, int r, const OpDev* comps, int nb
                 if (t < CG_TAPS * RP) CfS[buf * CG_TAPS * RP + t] = cv[u];
             }
         };
-        if (allk) {
+        if (hit) {
+        } else if (allk) {
             const int per = CG_TAPS * RP;
             const float invper = __frcp_rn((float)per);
             batched_loop<8>(
@@ -1129,7 +1148,7 @@ __device__ __forceinline__ double cgemm(int n, int r, const OpDev* comps, int nb
         if (G > 1) {
             // partial tiles of groups 1 .. G-1 through LDS (the staged Kt area), added by
             // group 0 in a fixed order
-            double* red = KtS;
+            double* red = keep ? s.scratch + ldx * rc : KtS;
             __syncthreads();
             if (kg > 0 && wstrip < nsp) {
 #pragma unroll
@@ -1172,6 +1191,22 @@ __device__ __forceinline__ double cgemm(int n, int r, const OpDev* comps, int nb
             }
         }
         __syncthreads();
+    }
+    // slot bookkeeping: record this product's slot; forget a slot whose space this product
+    // used (any product that does not keep its blocks forgets both)
+    __syncthreads();
+    if (tid_here() == 0) {
+        if (keep) {
+            s.kc_key[slot] = Kt;
+            s.kc_base[slot] = kbase;
+            s.kc_size[slot] = SA;
+            s.kc_rlo[slot] = rlo;
+            const int o = 1 - slot;
+            if (s.kc_key[o] && !(s.kc_base[o] >= kbase + SA || s.kc_base[o] + s.kc_size[o] <= kbase) ) s.kc_key[o] = nullptr;
+            if (s.kc_key[o] && s.kc_base[o] < ldx * rc + REDSZ) s.kc_key[o] = nullptr;
+        } else {
+            s.kc_key[0] = s.kc_key[1] = nullptr;
+        }
     }
     return part;
 }
@@ -1316,6 +1351,7 @@ __global__ void __launch_bounds__(WG) als_persistent(const Problem* __restrict__
             s.bar_target = 0;
             s.sync_ok = 1;
             s.dcount = 0;
+            s.kc_key[0] = s.kc_key[1] = nullptr;
         }
     }
     __syncthreads();
@@ -1419,17 +1455,18 @@ __global__ void __launch_bounds__(WG) als_persistent(const Problem* __restrict__
                 default: xf.a = pb.vz; xf.b = pcur; xf.beta = beta; xf.wv = pnxt; break;  // p' = z + beta p
             }
             const bool dot = ph != PH_RHS && ph != PH_MV_X;
+            const int slot = pre ? 1 : (mv ? 0 : -1);
             const bool f32 = lowp && !pre;
             const int tn = (r + 15) >> 4;
             double part;
             if (f32) {
-                if (tn == 1) part = cgemm<true, 1>(n, r, comps, nblk, rc, xf, Kt, outp, lam, mv, dot, rlo, rhi);
-                else if (tn == 2) part = cgemm<true, 2>(n, r, comps, nblk, rc, xf, Kt, outp, lam, mv, dot, rlo, rhi);
-                else part = cgemm<true, 4>(n, r, comps, nblk, rc, xf, Kt, outp, lam, mv, dot, rlo, rhi);
+                if (tn == 1) part = cgemm<true, 1>(n, r, comps, nblk, rc, xf, Kt, outp, lam, mv, dot, rlo, rhi, slot);
+                else if (tn == 2) part = cgemm<true, 2>(n, r, comps, nblk, rc, xf, Kt, outp, lam, mv, dot, rlo, rhi, slot);
+                else part = cgemm<true, 4>(n, r, comps, nblk, rc, xf, Kt, outp, lam, mv, dot, rlo, rhi, slot);
             } else {
-                if (tn == 1) part = cgemm<false, 1>(n, r, comps, nblk, rc, xf, Kt, outp, lam, mv, dot, rlo, rhi);
-                else if (tn == 2) part = cgemm<false, 2>(n, r, comps, nblk, rc, xf, Kt, outp, lam, mv, dot, rlo, rhi);
-                else part = cgemm<false, 4>(n, r, comps, nblk, rc, xf, Kt, outp, lam, mv, dot, rlo, rhi);
+                if (tn == 1) part = cgemm<false, 1>(n, r, comps, nblk, rc, xf, Kt, outp, lam, mv, dot, rlo, rhi, slot);
+                else if (tn == 2) part = cgemm<false, 2>(n, r, comps, nblk, rc, xf, Kt, outp, lam, mv, dot, rlo, rhi, slot);
+                else part = cgemm<false, 4>(n, r, comps, nblk, rc, xf, Kt, outp, lam, mv, dot, rlo, rhi, slot);
             }
             // dot products are summed over the cluster (fixed order)
             const double val = ufirst(dot ? cluster_sum(wg_sum(part, s.red)) : wg_sum(part, s.red));
@@ -1437,6 +1474,8 @@ __global__ void __launch_bounds__(WG) als_persistent(const Problem* __restrict__
             bool finish = false;
             switch (ph) {
                 case PH_RHS:
+                    // the new update's blocks and preconditioner: nothing kept is valid
+                    if (tid_here() == 0) s.kc_key[0] = s.kc_key[1] = nullptr;
                     flags |= factor_precond(lam);
                     psel = 0;
                     ph = PH_PRE_B;

@@ -218,6 +218,29 @@ def test_cluster_matches_single_workgroup(handle, cluster):
     assert dist <= 1e-12
 
 
+def test_cluster_time_loop_matches_single_workgroup(handle):
+    """Three device-resident steps of four sweeps on a cluster of 4 workgroups (rank 16, so
+    the operator blocks of the matvec and the preconditioner are kept in LDS across the PCG
+    iterations of every update) against one workgroup: the same iterates to rounding.  (The
+    mixed form on a cluster is covered by the mixed-precision tests, whose n = 32 grids run
+    on two workgroups.)"""
+    log("cluster time loop")
+    p = W.advection_ie_variable(seed=7, d=4, n=64, dt=1e-2, ic_rank=3, cap=16, n_steps=3)
+    out = {}
+    try:
+        for cl in (1, 4):
+            handle.set_cluster(cl)
+            Vd, Gd = dev(p.f0), dev(p.guess)
+            reps = B.cp_als_run(handle, p.A, p.B, Vd, Gd, 3, B.default_opts(tol=0.0, max_sweeps=4))
+            out[cl] = (host(Gd), reps)
+    finally:
+        handle.set_cluster(16)
+    assert all(not (r["flags"] & B.FLAG_SYNC_TIMEOUT) for r in out[4][1])
+    dist = tensor_distance(out[4][0], out[1][0])
+    log("cluster 4 vs 1 after 3 steps: %.3e" % dist)
+    assert dist <= 1e-12
+
+
 def test_set_cluster_rejects_out_of_range(handle):
     with pytest.raises(B.CpalsError):
         handle.set_cluster(0)
