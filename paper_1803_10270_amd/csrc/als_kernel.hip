@@ -154,6 +154,31 @@ __device__ __forceinline__ double cluster_sum(double v) {
     return tot;
 }
 
+// Two workgroup-uniform values summed over the cluster behind one barrier (the second one
+// carried from an earlier phase whose sum was not needed there); same order as cluster_sum.
+__device__ __forceinline__ void cluster_sum2(double v, double u, double& sv, double& su) {
+    Smem& s = SMEM;
+    const int W = ufirst(s.W);
+    if (W == 1) {
+        sv = v;
+        su = u;
+        return;
+    }
+    const int part = ufirst(s.part);
+    const int buf = ufirst((int)(s.dcount & 1u));
+    double* base = s.pb.dpart + (int64_t)buf * W * 8;
+    if (tid_here() == 0) {
+        stg(base + part * 8, v);
+        stg(base + part * 8 + 1, u);
+    }
+    cluster_sync();
+    sv = sum_partials(base, 8, W);
+    su = sum_partials(base + 1, 8, W);
+    __syncthreads();
+    if (tid_here() == 0) s.dcount += 1u;
+    __syncthreads();
+}
+
 // Plain column-major panel element (i, c).
 struct ColF {
     typedef double raw_t;
@@ -521,43 +546,45 @@ __device__ __forceinline__ double assemble(int q, int r0) {
 
 // ------------------------------------------------------------------------------------
 // Preconditioner: Hinv = (H0 + lam I)^{-1} by Gauss-Jordan elimination on the diagonal
-// pivots (H0 + lam I is symmetric positive definite).  The r x r entries live in registers
-// spread over the workgroup (at most 8 per thread); the owners of the next pivot row and
-// column publish them to a double-buffered LDS copy, so each pivot costs one barrier.
-// Returns flags.
+// pivots (H0 + lam I is symmetric positive definite).  The matrix lives in LDS in two
+// buffers; for pivot p every thread reads its entries, the pivot row and column from one
+// buffer and writes its updated entries to the other, so each pivot costs one barrier and
+// no thread branches on its position.  1 / pivot is the hardware reciprocal refined by two
+// Newton steps (within an ulp of the quotient).  Returns flags.
 // ------------------------------------------------------------------------------------
+__device__ __forceinline__ double recip_nr(double a) {
+    double x = __builtin_amdgcn_rcp(a);
+    x = fma(x, fma(-a, x, 1.0), x);
+    x = fma(x, fma(-a, x, 1.0), x);
+    return x;
+}
+
 template <int PER>
 __device__ __forceinline__ uint32_t factor_precond_t(double lam) {
     Smem& s = SMEM;
     const Problem& pb = s.pb;
     const int r = pb.r, rr = r * r;
-    double* rowb = s.scratch;             // [2][CP_MAX_RANK]
-    double* colb = s.scratch + 2 * CP_MAX_RANK;
+    double* M0 = s.scratch;               // [2][r r], column-major: entry (i, j) at i + j r
+    double* M1 = s.scratch + rr;
     const float invr = __frcp_rn((float)r);
-    // entry u of this thread is t = tid + u WG = i + j r (column-major); entries past r r
-    // take i = j = -1, read row and column 0 and are never written
-    double hv[PER];
+    // entry u of this thread: t = tid + u WG = i + j r; entries past r r read entry 0 and are
+    // never written
     int hi[PER], hj[PER];
     double dmax = 0.0;
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
         const int t = tid_here() + u * WG;
-        hv[u] = (t < rr) ? ldg(pb.H0 + t) : 0.0;
         const int j = fdiv(t, invr);
-        hi[u] = (t < rr) ? t - j * r : -1;
-        hj[u] = (t < rr) ? j : -1;
-    }
-#pragma unroll
-    for (int u = 0; u < PER; ++u) {
-        const int i = hi[u], j = hj[u];
-        if (i >= 0) {
-            if (i == j) {
-                hv[u] += lam;
-                dmax = fmax(dmax, hv[u]);
+        hi[u] = (t < rr) ? t - j * r : 0;
+        hj[u] = (t < rr) ? j : 0;
+        if (t < rr) {
+            double v = ldg(pb.H0 + t);
+            if (hi[u] == hj[u]) {
+                v += lam;
+                dmax = fmax(dmax, v);
             }
-            if (i == 0) rowb[j] = hv[u];
-            if (j == 0) colb[i] = hv[u];
+            M0[t] = v;
         }
     }
     dmax = wave_max(dmax);
@@ -569,43 +596,41 @@ __device__ __forceinline__ uint32_t factor_precond_t(double lam) {
     // In-place Gauss-Jordan step on pivot p, with selects in place of branches:
     //   row p: h[p][j] / piv (1 / piv on the diagonal); column p: -h[i][p] / piv;
     //   elsewhere h[i][j] - h[i][p] h[p][j] / piv.
-    // Every read of the pivot row and column comes before the writes of the next ones.
-    // `cur` (which half of the double buffer holds pivot p) is a constant after inlining.
-    auto pivot = [&](int p, int cur) __attribute__((always_inline)) {
-        const int nxt = CP_MAX_RANK - cur;
-        double piv = colb[cur + p];
+    auto pivot = [&](int p, const double* Mc, double* Mn) __attribute__((always_inline)) {
+        double piv = Mc[p + p * r];
         if (!(piv > 1e-12 * dmax)) fl |= CP_FLAG_REGULARIZED;
         if (!(piv > 0.0)) piv = (lam > 0.0) ? lam : 1e-300;
-        const double ip = 1.0 / piv;
+        double hv[PER], cv[PER], rv[PER];
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            hv[u] = Mc[hi[u] + hj[u] * r];
+            cv[u] = Mc[hi[u] + p * r];
+            rv[u] = Mc[p + hj[u] * r];
+        }
+        const double ip = recip_nr(piv);
 #pragma unroll
         for (int u = 0; u < PER; ++u) {
             const int i = hi[u], j = hj[u];
-            const double cv = colb[cur + max(i, 0)], rv = rowb[cur + max(j, 0)];
-            const double e = (j == p) ? 1.0 : rv;
+            const double e = (j == p) ? 1.0 : rv[u];
             const double base = (j == p) ? 0.0 : hv[u];
-            hv[u] = (i == p) ? e * ip : fma(-cv * ip, e, base);
-        }
-#pragma unroll
-        for (int u = 0; u < PER; ++u) {
-            if (hi[u] == p + 1) rowb[nxt + hj[u]] = hv[u];
-            if (hj[u] == p + 1) colb[nxt + hi[u]] = hv[u];
+            const double nv = (i == p) ? e * ip : fma(-cv[u] * ip, e, base);
+            if (tid_here() + u * WG < rr) Mn[i + j * r] = nv;
         }
         __syncthreads();
     };
     for (int p = 0; p < r; p += 2) {
-        pivot(p, 0);
-        if (p + 1 < r) pivot(p + 1, CP_MAX_RANK);
+        pivot(p, M0, M1);
+        if (p + 1 < r) pivot(p + 1, M1, M0);
     }
-    // symmetrise (the preconditioner of CG must be symmetric): through LDS
-    double* Hm = s.scratch + 4 * CP_MAX_RANK;
-#pragma unroll
-    for (int u = 0; u < PER; ++u)
-        if (hi[u] >= 0) Hm[hi[u] + hj[u] * r] = hv[u];
-    __syncthreads();
+    // the result is in M0 when r is even, else in M1; symmetrised (the preconditioner of CG
+    // must be symmetric)
+    const double* Mr = (r & 1) ? M1 : M0;
     double* Hout = pb.Hinv + (int64_t)ufirst(s.part) * rr;
 #pragma unroll
-    for (int u = 0; u < PER; ++u)
-        if (hi[u] >= 0) stg(Hout + hi[u] + hj[u] * r, 0.5 * (hv[u] + Hm[hj[u] + hi[u] * r]));
+    for (int u = 0; u < PER; ++u) {
+        const int t = tid_here() + u * WG;
+        if (t < rr) stg(Hout + t, 0.5 * (Mr[t] + Mr[hj[u] + hi[u] * r]));
+    }
     __syncthreads();
     return fl;
 }
@@ -1468,8 +1493,19 @@ __global__ void __launch_bounds__(WG) als_persistent(const Problem* __restrict__
                 else if (tn == 2) part = cgemm<false, 2>(n, r, comps, nblk, rc, xf, Kt, outp, lam, mv, dot, rlo, rhi, slot);
                 else part = cgemm<false, 4>(n, r, comps, nblk, rc, xf, Kt, outp, lam, mv, dot, rlo, rhi, slot);
             }
-            // dot products are summed over the cluster (fixed order)
-            const double val = ufirst(dot ? cluster_sum(wg_sum(part, s.red)) : wg_sum(part, s.red));
+            // dot products are summed over the cluster (fixed order); b^T P^{-1} b is only needed
+            // by the stopping test two phases later, so its sum rides with that of r^T P^{-1} r
+            double val;
+            if (ph == PH_PRE_B) {
+                val = ufirst(wg_sum(part, s.red));
+            } else if (ph == PH_PRE_R0) {
+                double sv, su;
+                cluster_sum2(wg_sum(part, s.red), bz, sv, su);
+                val = ufirst(sv);
+                bz = ufirst(su);
+            } else {
+                val = ufirst(dot ? cluster_sum(wg_sum(part, s.red)) : wg_sum(part, s.red));
+            }
             if (ph == PH_MV_P) psel ^= 1;   // the new direction is now the current one
             bool finish = false;
             switch (ph) {
@@ -1481,7 +1517,7 @@ __global__ void __launch_bounds__(WG) als_persistent(const Problem* __restrict__
                     ph = PH_PRE_B;
                     break;
                 case PH_PRE_B:
-                    bz = val;
+                    bz = val;   // this workgroup's share until the next cluster sum
                     ph = PH_MV_X;
                     break;
                 case PH_MV_X:
