@@ -232,7 +232,13 @@ def bench_batched(args):
     scale = sum(cost(p) for p in probs) / sum(cost(probs[i]) for i in sample)
     t_plain = t_plain_sample * scale
     sweeps = [r["sweeps"] for rr in reps for r in rr]
+    # whole-chip matrix-core use of the batched launch: the instances' algorithmic flops
+    # (same model as the headline roofline) over the launch's wall time
+    flops = sum(flop_model(p, rr) for p, rr in zip(probs, reps))
     out = {"form": "batched", "instances": args.batch_count, "steps_each": args.batch_steps,
+           "roofline": {"bound": "mfma", "achieved": flops / t_batched / 1e12, "peak": FP64_PEAK_TFLOPS,
+                        "unit": "TFLOP/s", "frac": flops / t_batched / 1e12 / FP64_PEAK_TFLOPS,
+                        "flops": flops, "seconds": t_batched},
            "batched_s": t_batched, "batched_steps_per_s": steps_total / t_batched,
            "plain_sample": len(sample), "plain_s_sample": t_plain_sample, "plain_s_estimated": t_plain,
            "plain_steps_per_s": steps_total / t_plain, "speedup": t_plain / t_batched,

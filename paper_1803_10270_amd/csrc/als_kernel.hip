@@ -827,7 +827,7 @@ __device__ __forceinline__ double cgemm(int n, int r, const OpDev* comps, int nb
     // the scratch area (slot 1 highest, slot 0 below the space slot 1 takes), the staged rows
     // and the reduction area of the block split at the bottom.  A slot is reused when its key,
     // place and rows match.
-    const int REDSZ = (NWAVES - 1) * TN * 256;
+    const int REDSZ = NWAVES * TN * 256;
     const int SA = nblk * (ktsz + CG_TAPS * RP);
     const int top1 = ufirst(s.kc_key[1] ? max(s.kc_size[1], ktsz + CG_TAPS * RP) : ktsz + CG_TAPS * RP);
     const int kbase = slot == 1 ? SCRATCH - SA : SCRATCH - top1 - SA;
@@ -872,7 +872,7 @@ __device__ __forceinline__ double cgemm(int n, int r, const OpDev* comps, int nb
         // fewer strips than waves with every block staged: the waves split the operator
         // blocks (G groups per strip) and their partial tiles are added afterwards
         const int G = (allk && nsp < NWAVES && NWAVES % nsp == 0 &&
-                       (NWAVES - nsp) * TN * 256 <= (keep ? REDSZ : SCRATCH - ldx * rc)) ? NWAVES / nsp : 1;
+                       NWAVES * TN * 256 <= (keep ? REDSZ : SCRATCH - ldx * rc)) ? NWAVES / nsp : 1;
         const int kg = G > 1 ? wave / nsp : 0;
         const int wstrip = G > 1 ? wave - kg * nsp : wave;
         // stage X rows i0 - H .. i0 + RP + H (periodic); in a single pass the halo is copied
@@ -1170,7 +1170,44 @@ __device__ __forceinline__ double cgemm(int n, int r, const OpDev* comps, int nb
             }
             if (!allk) __syncthreads();
         }
-        if (G > 1) {
+        bool done = false;
+        if (flat) {
+            // every wave's partial tiles through LDS; wave w adds value w of every lane and tile
+            // over the waves in the order 0..3 (the order of the block split below) and
+            // finishes those outputs, so the epilogue is spread over the four waves
+            double* red = keep ? s.scratch + ldx * rc : KtS;
+            __syncthreads();
+#pragma unroll
+            for (int t = 0; t < TN; ++t)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) red[((wave * TN + t) * 4 + v) * 64 + lane] = acc[0][t].get(v);
+            __syncthreads();
+#pragma unroll
+            for (int t = 0; t < TN; ++t) {
+                double val;
+                if (F32) {
+                    float a = (float)red[((0 * TN + t) * 4 + wave) * 64 + lane];
+#pragma unroll
+                    for (int g = 1; g < NWAVES; ++g) a += (float)red[((g * TN + t) * 4 + wave) * 64 + lane];
+                    val = (double)a;
+                } else {
+                    val = red[((0 * TN + t) * 4 + wave) * 64 + lane];
+#pragma unroll
+                    for (int g = 1; g < NWAVES; ++g) val += red[((g * TN + t) * 4 + wave) * 64 + lane];
+                }
+                const int lr = cc;
+                const int col = t * 16 + Tile<F32>::row(lane, wave);
+                if (lr < nrow && col < r) {
+                    if (shift || dot) {
+                        const double xv = Xs[col * ldx + H + lr];
+                        if (shift) val = fma(lam, xv, val);
+                        if (dot) part = fma(xv, val, part);
+                    }
+                    stg(out + (i0 + lr) + (int64_t)col * n, val);
+                }
+            }
+            done = true;
+        } else if (G > 1) {
             // partial tiles of groups 1 .. G-1 through LDS (the staged Kt area), added by
             // group 0 in a fixed order
             double* red = keep ? s.scratch + ldx * rc : KtS;
@@ -1195,7 +1232,7 @@ __device__ __forceinline__ double cgemm(int n, int r, const OpDev* comps, int nb
 #pragma unroll
         for (int u = 0; u < SPW; ++u) {
             const int strip = wstrip + NWAVES * u;
-            if (strip < nsp && kg == 0) {
+            if (strip < nsp && kg == 0 && !done) {
 #pragma unroll
                 for (int t = 0; t < TN; ++t) {
                     const int lr = strip * 16 + cc;
