@@ -10,8 +10,10 @@ device-resident in one persistent kernel launch per batch of steps.
 
 Beside the plain method (the headline value) the same run measures the two other forms at
 the same 1e-8 tolerance:
-  learned  the per-column CNN warm start, trained on solver trajectories of new seeds,
-           against the plain warm start on a held-out instance of the same workload;
+  learned  the linear extrapolation 2 f_n - f_{n-1} corrected by the per-column CNN, trained
+           on solver trajectories of new seeds, against the plain warm start f_n on a
+           held-out instance of the same workload (the untrained network, i.e. the
+           extrapolation alone, is reported beside it);
   batched  256 uneven advection instances in one persistent launch against the same
            instances advanced one launch at a time (a seeded sample, scaled by cost).
 
@@ -120,7 +122,8 @@ def committed_traffic():
 
 
 def bench_learned(args, log):
-    """Learned warm start vs plain warm start on held-out steps (same tolerance)."""
+    """Learned warm start vs plain warm start on held-out steps (same tolerance); the untrained
+    network (the linear extrapolation alone) is timed beside them."""
     import torch
     from paper_1803_10270_amd import binding as B
     from paper_1803_10270_amd import warmstart as WS
@@ -140,9 +143,14 @@ def bench_learned(args, log):
 
     t0 = time.perf_counter()
     trajs = []
-    for sd in range(args.seed + 301, args.seed + 301 + args.learned_train_seeds):
-        tr, _ = trajectory(mk(sd), args.learned_train_steps)
-        trajs.append(tr.contiguous())
+    # training data: the trajectories of new seeds whose every step converged (an unconverged
+    # step is an ALS iterate, not a solution of the step)
+    for sd in range(args.seed + 301, args.seed + 301 + 4 * args.learned_train_seeds):
+        tr, reps = trajectory(mk(sd), args.learned_train_steps)
+        if all(not (q["flags"] & B.FLAG_NOT_CONVERGED) for q in reps):
+            trajs.append(tr.contiguous())
+        if len(trajs) == args.learned_train_seeds:
+            break
     t_data = time.perf_counter() - t0
     net = B.WarmStartNet(h, WS.init_params(seed=9), n, max_batch=512)
     t0 = time.perf_counter()
@@ -172,19 +180,26 @@ def bench_learned(args, log):
         cur = nxt
     torch.cuda.synchronize()
     t_plain = time.perf_counter() - t0
-    # learned: the same K steps from the same levels
-    prev, cur = [u.clone() for u in lvl1], [u.clone() for u in lvl2]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    learned_sweeps, used, errs = [], 0, []
-    for _ in range(K):
-        out, rep = WS.learned_step(h, net, p0.A, p0.B, prev, cur, coef, opts)
-        learned_sweeps.append(rep["sweeps"])
-        used += rep["used_prediction"]
-        errs.append(rep["pred_rel_dist"])
-        prev, cur = cur, out
-    torch.cuda.synchronize()
-    t_learned = time.perf_counter() - t0
+    # learned: the same K steps from the same levels; then the untrained network (zero output
+    # layer: the linear extrapolation alone) to show what the training adds
+    def predicted_run(model):
+        prev, cur = [u.clone() for u in lvl1], [u.clone() for u in lvl2]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sw, used, errs = [], 0, []
+        for _ in range(K):
+            out, rep = WS.learned_step(h, model, p0.A, p0.B, prev, cur, coef, opts)
+            sw.append(rep["sweeps"])
+            used += rep["used_prediction"]
+            errs.append(rep["pred_rel_dist"])
+            prev, cur = cur, out
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, sw, used, errs
+
+    t_learned, learned_sweeps, used, errs = predicted_run(net)
+    net0 = B.WarmStartNet(h, WS.init_params(seed=9), n, max_batch=512)
+    t_extrap, extrap_sweeps, _, extrap_errs = predicted_run(net0)
+    net0.close()
     net.close()
     h.close()
     return {"form": "learned", "workload": "advection_ie_variable d=6 n=256 r=32, held-out seed %d, %d steps" % (
@@ -194,7 +209,9 @@ def bench_learned(args, log):
             "plain_steps_per_s": K / t_plain, "learned_steps_per_s": K / t_learned,
             "speedup": t_plain / t_learned, "plain_mean_sweeps": float(np.mean(plain_sweeps)),
             "learned_mean_sweeps": float(np.mean(learned_sweeps)), "prediction_used": used,
-            "prediction_rel_error_mean": float(np.nanmean(errs))}
+            "prediction_rel_error_mean": float(np.nanmean(errs)),
+            "untrained_extrapolation": {"steps_per_s": K / t_extrap, "mean_sweeps": float(np.mean(extrap_sweeps)),
+                                        "prediction_rel_error_mean": float(np.nanmean(extrap_errs))}}
 
 
 def bench_batched(args):

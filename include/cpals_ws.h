@@ -2,9 +2,10 @@
  *
  * The implicit step of Section 3.1 minimises ||A f_{n+1} - B f_n|| by alternating least
  * squares started from a guess of f_{n+1}; the plain method starts from f_n.  This part of
- * the library predicts a better guess, factor column by factor column, with a small 1-D
- * convolutional network, and the caller then runs cp_als_step from it (ALS refines the
- * guess to the same tolerance and stays the arbiter of the result).
+ * the library predicts a better guess, factor column by factor column: the linear
+ * extrapolation of the column in time plus a correction from a small 1-D convolutional
+ * network.  The caller then runs cp_als_step from it (ALS refines the guess to the same
+ * tolerance and stays the arbiter of the result).
  *
  * Network (one sample = column l of the factor of dimension k, n = n_k grid points):
  *   input   x[3][n] = (U_k(t_{n-1})[:, l] / s, U_k(t_n)[:, l] / s, c_k),  s = rms(U_k(t_n)[:, l])
@@ -12,7 +13,10 @@
  *   layers  four circular convolutions of width 5 over the periodic grid,
  *           z[o][i] = b[o] + sum_{c,t} W[o][c][t] x[c][(i + t - 2) mod n],
  *           channels 3 -> 32 -> 32 -> 32 -> 1, ReLU after the first three;
- *   output  y[n]; the guess is U_k(t_n)[:, l] + s y, the training target (U_k(t_{n+1}) - U_k(t_n))[:, l] / s;
+ *   output  y[n]; the guess is 2 U_k(t_n)[:, l] - U_k(t_{n-1})[:, l] + 2^-12 s y (a zero network
+ *           gives the linear extrapolation), the training target
+ *           (U_k(t_{n+1}) - 2 U_k(t_n) + U_k(t_{n-1}))[:, l] / (2^-12 s); the fixed power-of-two
+ *           output scale lets the network produce the small correction as outputs of order one;
  *   loss    mean squared error over samples and grid points; Adam (0.9, 0.999, 1e-8).
  * Parameters in natural order: for each layer W[o][c][t] (row-major) then b[o]; 10977 in all.
  * Precision: BF16 weights, activations and gradients, FP32 accumulation on the matrix
@@ -65,9 +69,11 @@ cp_status cp_ws_gradients(cp_handle h, cp_ws_net net, const float* x_dev, const 
 cp_status cp_ws_train_step(cp_handle h, cp_ws_net net, const double* traj_dev, int32_t T, int32_t C,
                            const int32_t* samples_host, const double* coef_host, int32_t B, float lr, float* loss_host);
 
-/* Predicted next factors: f_guess column (k, l) = f_cur column + s y for the inputs built from
- * f_prev and f_cur; coef_host[k] per dimension.  All three tensors have the same d, n_k and
- * rank; every n_k must equal the network's n; d * r <= max_batch. */
+/* Predicted next factors: f_guess column (k, l) = 2 f_cur column - f_prev column + 2^-12 s y
+ * for the inputs built from f_prev and f_cur; coef_host[k] per dimension; f_guess may be
+ * f_cur.
+ * All three tensors have the same d, n_k and rank; every n_k must equal the network's n;
+ * d * r <= max_batch. */
 cp_status cp_ws_predict(cp_handle h, cp_ws_net net, const cp_tensor* f_prev, const cp_tensor* f_cur,
                         const double* coef_host, cp_tensor* f_guess);
 

@@ -7,13 +7,19 @@ The paper advances the CP solution of an implicit step by ALS started from the p
 step's factors (Section 3.1, warm start of the sequential minimisation).  The learned form
 replaces that starting point by a prediction of the next factors, column by column, and
 ALS refines it to the same tolerance.  The network is not in the paper; it is specified
-as follows and this module is its definition written out:
+as follows and this module is its definition written out.  The network corrects the
+linear extrapolation of the factor columns in time (an untrained, zero output layer
+predicts exactly that extrapolation):
 
 * one sample is one factor column l of one dimension k at step n:
     input  x[3, n_k] = (U_k(t_{n-1})[:, l] / s, U_k(t_n)[:, l] / s, c_k),
     s = rms(U_k(t_n)[:, l]) (1 if that is 0), c_k a per-dimension scalar channel;
-    output y[n_k], prediction U_k(t_{n+1})[:, l] = U_k(t_n)[:, l] + s y,
-    training target (U_k(t_{n+1})[:, l] - U_k(t_n)[:, l]) / s;
+    output y[n_k], prediction
+      U_k(t_{n+1})[:, l] = 2 U_k(t_n)[:, l] - U_k(t_{n-1})[:, l] + OUT s y,
+    training target (U_k(t_{n+1})[:, l] - 2 U_k(t_n)[:, l] + U_k(t_{n-1})[:, l]) / (OUT s),
+    with the fixed output scale OUT = 2^-12: the correction is far smaller than the column,
+    and the scale lets the network work with outputs of order one (a power of two, so
+    exact in every precision);
 * four circular convolutions of width 5 over the periodic grid,
     z[co, i] = b[co] + sum_{ci, t} W[co, ci, t] x[ci, (i + t - 2) mod n],
   with channel widths 3 -> 32 -> 32 -> 32 -> 1 and ReLU after the first three;
@@ -28,6 +34,7 @@ from __future__ import annotations
 import numpy as np
 
 WIDTHS = (3, 32, 32, 32, 1)
+OUT = 2.0 ** -12   # output scale of the correction
 KW = 5          # stencil width
 HALF = KW // 2
 
@@ -53,7 +60,7 @@ def n_params():
 
 
 def init_params(seed=0):
-    """He-uniform weights, zero biases, last layer zero (prediction = plain warm start)."""
+    """He-uniform weights, zero biases, last layer zero (prediction = linear extrapolation)."""
     rng = np.random.default_rng(seed)
     params = []
     for li in range(len(WIDTHS) - 1):
@@ -162,8 +169,25 @@ def make_inputs(u_prev, u_cur, coef):
     return x, s
 
 
+def extrapolate(u_prev, u_cur):
+    """Linear extrapolation of columns in time: 2 U(t_n) - U(t_{n-1})."""
+    return 2.0 * np.asarray(u_cur, dtype=np.float64) - np.asarray(u_prev, dtype=np.float64)
+
+
+def training_target(u_prev, u_cur, u_next):
+    """Target of a batch of columns: the second difference in time over the column's scale
+    and the output scale, (U(t_{n+1}) - 2 U(t_n) + U(t_{n-1})) / (OUT s)."""
+    _, s = make_inputs(u_prev, u_cur, np.zeros(np.asarray(u_cur).shape[0]))
+    return (np.asarray(u_next, dtype=np.float64) - extrapolate(u_prev, u_cur)) / (OUT * s[:, None])
+
+
+def predict_columns_from_output(u_prev, u_cur, y):
+    """The prediction 2 U(t_n) - U(t_{n-1}) + OUT s y for given network outputs y."""
+    _, s = make_inputs(u_prev, u_cur, np.zeros(np.asarray(u_cur).shape[0]))
+    return extrapolate(u_prev, u_cur) + (OUT * s[:, None]) * np.asarray(y, dtype=np.float64)
+
+
 def predict_columns(params, u_prev, u_cur, coef, bf16=False):
-    """Predicted next columns U(t_{n+1}) = U(t_n) + s y for a batch of columns."""
-    x, s = make_inputs(u_prev, u_cur, coef)
-    y = forward(params, x, bf16=bf16)[-1][:, 0, :]
-    return np.asarray(u_cur, dtype=np.float64) + s[:, None] * y
+    """Predicted next columns U(t_{n+1}) = 2 U(t_n) - U(t_{n-1}) + OUT s y for a batch of columns."""
+    x, _ = make_inputs(u_prev, u_cur, coef)
+    return predict_columns_from_output(u_prev, u_cur, forward(params, x, bf16=bf16)[-1][:, 0, :])

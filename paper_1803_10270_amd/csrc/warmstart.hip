@@ -233,9 +233,16 @@ __global__ void pack_input(const float* __restrict__ x, int B, int n, u16* __res
     act0[t] = (c < 3) ? f2bf(x[((int64_t)b * 3 + c) * n + i]) : (u16)0;
 }
 
+// Output scale of the network's correction (a power of two: exact in BF16, FP32 and FP64).
+// The correction of the linear extrapolation is a small fraction of the column; the scale
+// lets the network produce it as outputs of order one.
+constexpr double OUT_SCALE = 1.0 / 4096.0;
+
 // Samples from columns of factor panels: sample s = (u_prev, u_cur[, u_next]) rows of n
 // values.  One workgroup per sample: the RMS scale, the BF16 input channels and (training)
-// the FP32 target (u_next - u_cur) / s.  Column sources come through a table of pointers.
+// the FP32 target (u_next - 2 u_cur + u_prev) / (OUT_SCALE s), the second difference in
+// time that corrects the linear extrapolation.  Column sources come through a table of
+// pointers.
 __global__ void __launch_bounds__(TPB) make_samples(const double* const* __restrict__ prev, const double* const* __restrict__ cur,
                                                     const double* const* __restrict__ next, const double* __restrict__ coef,
                                                     int n, u16* __restrict__ act0, float* __restrict__ target,
@@ -262,7 +269,7 @@ __global__ void __launch_bounds__(TPB) make_samples(const double* const* __restr
         a[2] = f2bf(cf);
 #pragma unroll
         for (int c = 3; c < 8; ++c) a[c] = 0;
-        if (target) target[(int64_t)b * n + i] = (float)((next[b][i] - uc[i]) * inv);
+        if (target) target[(int64_t)b * n + i] = (float)((next[b][i] - (2.0 * uc[i] - up[i])) * (inv / OUT_SCALE));
     }
     if (tid == 0 && scale) scale[b] = s;
 }
@@ -292,13 +299,16 @@ __global__ void __launch_bounds__(TPB) mse_grad(const float* __restrict__ y, con
     }
 }
 
-// Next columns u_cur + s y into the output panels (pointer table per sample).
-__global__ void finish_guess(const double* const* __restrict__ cur, double* const* __restrict__ dst,
-                             const double* __restrict__ scale, const float* __restrict__ y, int n, int B) {
+// Next columns 2 u_cur - u_prev + OUT_SCALE s y (the linear extrapolation and the
+// network's correction) into the output panels (pointer tables per sample; dst may be
+// u_cur).
+__global__ void finish_guess(const double* const* __restrict__ prev, const double* const* __restrict__ cur,
+                             double* const* __restrict__ dst, const double* __restrict__ scale,
+                             const float* __restrict__ y, int n, int B) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (int64_t)B * n) return;
     const int b = (int)(t / n), i = (int)(t - (int64_t)b * n);
-    dst[b][i] = cur[b][i] + scale[b] * (double)y[t];
+    dst[b][i] = (2.0 * cur[b][i] - prev[b][i]) + (OUT_SCALE * scale[b]) * (double)y[t];
 }
 
 // Adam on the FP32 master parameters (natural order), then the BF16 matrices of every
@@ -681,8 +691,8 @@ cp_status cp_ws_predict(cp_handle h, cp_ws_net net, const cp_tensor* f_prev, con
     WS_TRY(hipGetLastError(), "make_samples");
     WS_TRY(forward_all(net, B, st), "forward");
     const int64_t tot = (int64_t)B * net->n;
-    hipLaunchKernelGGL(cpws::finish_guess, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, net->tab + B,
-                       (double* const*)net->dst, net->scale, net->y, net->n, B);
+    hipLaunchKernelGGL(cpws::finish_guess, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, net->tab,
+                       net->tab + B, (double* const*)net->dst, net->scale, net->y, net->n, B);
     WS_TRY(hipGetLastError(), "finish_guess");
     // the host tables must outlive the asynchronous copies
     WS_TRY(hipStreamSynchronize(st), "hipStreamSynchronize");

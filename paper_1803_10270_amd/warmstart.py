@@ -1,10 +1,11 @@
 """Learned warm start around the implicit CP-ALS step (Section 3.1 solves each step by ALS
 started from a guess of f_{n+1}; the plain method uses f_n).
 
-Every numerical step runs in libcpals (include/cpals_ws.h, include/cpals.h): the network
-predicts a guess, ALS refines it to the tolerance (and falls back to the plain warm start
-f_n when it does not converge from the prediction), and the prediction's relative distance
-to the converged result is reported.
+Every numerical step runs in libcpals (include/cpals_ws.h, include/cpals.h): the guess is
+the linear extrapolation 2 f_n - f_{n-1} of the factor columns plus the network's
+correction, ALS refines it to the tolerance (and falls back to the plain warm start f_n
+when it does not converge from the prediction), and the prediction's relative distance to
+the converged result is reported.
 """
 from __future__ import annotations
 
@@ -64,8 +65,8 @@ def learned_step(h, net, A, Bop, f_prev, f_cur, coef, opts, f_out=None):
 
 def init_params(seed=0):
     """Seeded initial parameters in the natural order of include/cpals_ws.h: He-uniform
-    weights, zero biases, and a zero output layer (the untrained network predicts the plain
-    warm start exactly)."""
+    weights, zero biases, and a zero output layer (the untrained network predicts the linear
+    extrapolation 2 f_n - f_{n-1} exactly)."""
     widths = (3, 32, 32, 32, 1)
     rng = np.random.default_rng(seed)
     out = []

@@ -102,18 +102,23 @@ def test_gradients_match_oracle(handle):
     net.close()
 
 
-def test_zero_output_layer_predicts_current_factors(handle):
+def test_zero_output_layer_predicts_linear_extrapolation(handle):
     import torch
     n, d, r = 32, 3, 4
-    p = flat(WO.init_params(seed=2))          # last layer zero: guess = f_cur
+    p = flat(WO.init_params(seed=2))          # last layer zero: guess = 2 f_cur - f_prev
     net = B.WarmStartNet(handle, p, n, max_batch=d * r)
     rng = np.random.default_rng(0)
-    fp = dev([rng.normal(size=(n, r)) for _ in range(d)])
-    fc = dev([rng.normal(size=(n, r)) for _ in range(d)])
-    fg = [torch.empty_like(u) for u in fc]
-    net.predict(fp, fc, np.ones(d), fg)
-    for a, b in zip(host(fg), host(fc)):
-        assert np.array_equal(a, b)
+    up = [rng.normal(size=(n, r)) for _ in range(d)]
+    uc = [rng.normal(size=(n, r)) for _ in range(d)]
+    fg = [torch.empty((r, n), dtype=torch.float64, device="cuda") for _ in range(d)]
+    net.predict(dev(up), dev(uc), np.ones(d), fg)
+    for a, b, c in zip(host(fg), uc, up):
+        assert np.array_equal(a, 2.0 * b - c)
+    # in place: the guess may overwrite f_cur
+    fc = dev(uc)
+    net.predict(dev(up), fc, np.ones(d), fc)
+    for a, b, c in zip(host(fc), uc, up):
+        assert np.array_equal(a, 2.0 * b - c)
     net.close()
 
 
@@ -132,9 +137,9 @@ def test_predict_matches_oracle(handle):
     for k in range(d):
         ref = WO.predict_columns(params, up[k].T, uc[k].T, np.full(r, coef[k]), bf16=True).T
         got = host(fg)[k]
-        step = np.linalg.norm(ref - uc[k])
+        step = np.linalg.norm(ref - WO.extrapolate(up[k].T, uc[k].T).T)   # the network's part
         err = np.linalg.norm(got - ref) / max(step, 1e-30)
-        log("predict dim %d: error %.3e of the predicted step" % (k, err))
+        log("predict dim %d: error %.3e of the network's correction" % (k, err))
         assert err <= 1e-2
 
 
@@ -158,9 +163,12 @@ def test_training_reduces_loss(handle):
     rng = np.random.default_rng(7)
     tr = torch.from_numpy(translating_trajectory(rng, T, C, n, 0.05)).cuda()
     net = B.WarmStartNet(handle, flat(WO.init_params(seed=5)), n, max_batch=256)
-    losses = WS.train(net, [tr], [np.full(C, 0.5)], steps=150, batch=256, lr=3e-3, seed=1, log=log)
-    log("loss first %.4e last %.4e" % (losses[0], losses[-1]))
-    assert np.isfinite(losses[-1]) and losses[-1] < 0.2 * losses[0]
+    # the target is the second difference in time (the correction of the linear
+    # extrapolation); the loss of the untrained network is that of the extrapolation alone
+    losses = WS.train(net, [tr], [np.full(C, 0.5)], steps=400, batch=256, lr=3e-3, seed=1, log=log)
+    last = float(np.mean(losses[-10:]))
+    log("loss first %.4e last (mean of 10) %.4e" % (losses[0], last))
+    assert np.isfinite(last) and last < 0.2 * losses[0]
     net.close()
 
 
@@ -179,9 +187,10 @@ def _solver_trajectory(h, p, n_steps):
 
 def test_learned_warm_start_saves_sweeps(handle):
     """The variable-coefficient advection step at full size (d=6, n=256, rank 32): trained on
-    solver trajectories of three seeds, evaluated on a fourth.  Steps started from the
-    prediction need fewer sweeps to the same 1e-8 tolerance than steps started from f_n and
-    reach the same solution."""
+    the converged solver trajectories of three seeds, evaluated on another.  Steps started
+    from the prediction (linear extrapolation plus the network's correction) need fewer
+    sweeps to the same 1e-8 tolerance than steps started from f_n and reach the same
+    solution; the untrained network (the extrapolation alone) is run beside it."""
     import torch
     mk = lambda s: W.advection_ie_variable(seed=s, n_steps=20)
     p0 = mk(200)
@@ -189,10 +198,15 @@ def test_learned_warm_start_saves_sweeps(handle):
     dt = 1e-3
     coef = np.full(d, dt * n / (2 * np.pi))               # CFL number dt |a| / h with mean |a| = 1
     trajs = []
-    for s in (201, 202, 203):
+    for s in range(201, 211):
         tr, reps = _solver_trajectory(handle, mk(s), 16)
-        trajs.append(tr[1:].contiguous())                 # levels from the first solved step on
-        log("seed %d: mean sweeps %.1f" % (s, np.mean([q['sweeps'] for q in reps])))
+        ok = all(not (q["flags"] & B.FLAG_NOT_CONVERGED) for q in reps)
+        log("seed %d: mean sweeps %.1f, converged %s" % (s, np.mean([q['sweeps'] for q in reps]), ok))
+        if ok:                                            # only solutions are learned from
+            trajs.append(tr[1:].contiguous())             # levels from the first solved step on
+        if len(trajs) == 3:
+            break
+    assert len(trajs) == 3
     net = B.WarmStartNet(handle, flat(WO.init_params(seed=9)), n, max_batch=512)
     for lr, steps in ((2e-3, 200), (5e-4, 200), (1e-4, 100)):
         WS.train(net, trajs, [WS.column_coef(coef, r)] * len(trajs), steps=steps, batch=512, lr=lr, seed=3, log=log)
@@ -200,7 +214,8 @@ def test_learned_warm_start_saves_sweeps(handle):
     nt = 8
     tr, reps = _solver_trajectory(handle, p0, nt)
     opts = B.default_opts(tol=p0.tol, max_sweeps=200)
-    plain, learned, used = [], [], 0
+    plain, learned, extrap, used = [], [], [], 0
+    net0 = B.WarmStartNet(handle, flat(WO.init_params(seed=9)), n, max_batch=512)   # extrapolation only
     from gpu_util import tensor_distance
     for t in range(2, nt):
         prev = [tr[t - 1, k * r:(k + 1) * r].clone() for k in range(d)]
@@ -208,6 +223,7 @@ def test_learned_warm_start_saves_sweeps(handle):
         ref = [tr[t + 1, k * r:(k + 1) * r].clone() for k in range(d)]
         out, rep = WS.learned_step(handle, net, p0.A, p0.B, prev, cur, coef, opts)
         learned.append(rep['sweeps'])
+        extrap.append(WS.learned_step(handle, net0, p0.A, p0.B, prev, cur, coef, opts)[1]['sweeps'])
         plain.append(reps[t]['sweeps'])
         used += rep['used_prediction']
         dist = tensor_distance(host(out), host(ref))
@@ -215,7 +231,10 @@ def test_learned_warm_start_saves_sweeps(handle):
             "distance of the two solutions %.2e" % (t, reps[t]['sweeps'], rep['sweeps'], rep['used_prediction'],
                                                     rep['pred_rel_dist'], tensor_distance(host(cur), host(ref)), dist))
         assert dist <= 1e-5, dist
-    log("mean sweeps plain %.2f learned %.2f" % (np.mean(plain), np.mean(learned)))
+    log("mean sweeps plain %.2f learned %.2f (untrained: extrapolation alone %.2f)" % (
+        np.mean(plain), np.mean(learned), np.mean(extrap)))
+    net0.close()
     assert used >= len(learned) // 2
-    assert np.mean(learned) <= 0.9 * np.mean(plain)
+    assert np.mean(learned) <= 0.5 * np.mean(plain)
+    assert np.mean(learned) <= np.mean(extrap)           # the training adds to the extrapolation
     net.close()

@@ -89,11 +89,24 @@ def test_gradients_match_finite_differences(layer):
     assert abs(fd - grads[layer][1][0]) <= 1e-6 * max(1.0, abs(fd))
 
 
-def test_zero_last_layer_predicts_plain_warm_start():
+def test_zero_last_layer_predicts_linear_extrapolation():
     params = WO.init_params(seed=3)
     rng = np.random.default_rng(4)
     up, uc = rng.normal(size=(5, 16)), rng.normal(size=(5, 16))
-    assert np.array_equal(WO.predict_columns(params, up, uc, np.ones(5)), uc)
+    assert np.array_equal(WO.predict_columns(params, up, uc, np.ones(5)), 2.0 * uc - up)
+
+
+def test_target_is_exact_for_quadratic_trajectories():
+    # a column moving on a quadratic path u(t) = a + b t + c t^2 has the constant second
+    # difference 2c: the target is 2c / (OUT s), and the perfect output recovers u(t+1)
+    rng = np.random.default_rng(6)
+    a, b, c = rng.normal(size=(3, 4, 24))
+    u = [a + b * t + c * t * t for t in (0.0, 1.0, 2.0)]
+    _, s = WO.make_inputs(u[0], u[1], np.zeros(4))
+    tgt = WO.training_target(u[0], u[1], u[2])
+    assert WO.OUT == 2.0 ** -12
+    assert np.allclose(tgt * WO.OUT, 2.0 * c / s[:, None], rtol=1e-11, atol=1e-12)
+    assert np.allclose(WO.predict_columns_from_output(u[0], u[1], tgt), u[2], rtol=1e-12, atol=1e-12)
 
 
 def test_adam_first_step_closed_form():
