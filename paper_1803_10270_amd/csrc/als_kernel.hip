@@ -1,5 +1,6 @@
-// Persistent implicit CP-ALS kernel for gfx950: one workgroup advances one problem
-// through n_steps implicit time steps, entirely on the device.
+// Persistent implicit CP-ALS kernel for gfx950: one workgroup, or a cluster of W workgroups
+// that split the grid rows, advances one problem through n_steps implicit time steps,
+// entirely on the device.
 //
 // Per time step (Section 3.1):  minimise ||A f_{n+1} - B f_n|| by Gauss-Seidel ALS over
 // the dimensions q = 1..d (eq. sequential_min).  The normal equations of dimension q
@@ -1208,7 +1209,7 @@ __device__ __forceinline__ double cgemm(int n, int r, const OpDev* comps, int nb
             }
             done = true;
         } else if (G > 1) {
-            // partial tiles of groups 1 .. G-1 through LDS (the staged Kt area), added by
+            // partial tiles of groups 1 .. G-1 through LDS (the reduction area), added by
             // group 0 in a fixed order
             double* red = keep ? s.scratch + ldx * rc : KtS;
             __syncthreads();
