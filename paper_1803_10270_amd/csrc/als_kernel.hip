@@ -784,28 +784,22 @@ __device__ __forceinline__ double cgemm(int n, int r, const OpDev* comps, int nb
     const int lane = tid_here() & 63, wave = tid_here() >> 6;
     const int rc4 = (rc + 3) & ~3;
     const int ktsz = rc4 * LDB;
-    int H = 0;
-    bool any_r1 = false;
-    for (int b = 0; b < nblk; ++b) {
-        if (comps[b].kind == CP_OP_BAND) H = max(H, comps[b].hbw);
-        any_r1 |= comps[b].kind == CP_OP_RANK1;
+    // the operator blocks' shapes, one block per lane (nblk <= 16), reduced over the wave:
+    // H the widest half-bandwidth, rank-1 blocks, and whether every block is an identity,
+    // diagonal or band of at most 5 taps (the flat k-step split) with its widest tap count
+    int bk = CP_OP_IDENTITY, bh = 0;
+    if (lane < nblk) {
+        bk = comps[lane].kind;
+        bh = comps[lane].hbw;
     }
-    H = ufirst(H);
-    // every block an identity, diagonal or band of at most 5 taps (the flat k-step split)
-    bool flat_ok = !any_r1;
-    int flat_taps = 1;
-    for (int b = 0; b < nblk; ++b) {
-        const bool band = comps[b].kind == CP_OP_BAND;
-        flat_ok &= !(band && comps[b].hbw > 2);
-        if (band) flat_taps = max(flat_taps, 2 * comps[b].hbw + 1);
-    }
-    flat_ok = ufirst((int)flat_ok) != 0;
-    flat_taps = ufirst(flat_taps);
+    const bool bband = bk == CP_OP_BAND;
+    const int H = ufirst((int)wave_max((double)(bband ? bh : 0)));
+    const bool any_r1 = __ballot(bk == CP_OP_RANK1) != 0;
+    const bool flat_ok = !any_r1 && __ballot(bband && bh > 2) == 0;
+    const int flat_taps = ufirst((int)wave_max((double)(bband ? 2 * bh + 1 : 1)));
     if (tid_here() < nblk) {
-        const bool band = comps[tid_here()].kind == CP_OP_BAND;
-        const int h = comps[tid_here()].hbw;
-        s.bnt[tid_here()] = band ? 2 * h + 1 : 1;
-        s.boff[tid_here()] = band ? H - h : H;
+        s.bnt[tid_here()] = bband ? 2 * bh + 1 : 1;
+        s.boff[tid_here()] = bband ? H - bh : H;
     }
     // rows per pass: as many strips as the waves hold, limited by the LDS staging area
     const int nown = rhi - rlo;
