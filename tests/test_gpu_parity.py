@@ -197,12 +197,13 @@ def test_batched_matches_single(handle):
         handle.set_cluster(16)
 
 
-@pytest.mark.parametrize("cluster", [2, 4, 8])
-def test_cluster_matches_single_workgroup(handle, cluster):
+@pytest.mark.parametrize("cluster,cap", [(2, 6), (4, 6), (8, 6), (8, 40)])
+def test_cluster_matches_single_workgroup(handle, cluster, cap):
     """A problem shared by a cluster of workgroups (grid rows split, partial sums added in a
-    fixed order) agrees with one workgroup to rounding, and is itself deterministic."""
-    log("cluster", cluster)
-    p = W.advection_ie_variable(seed=5, d=4, n=128, ic_rank=3, cap=6)
+    fixed order) agrees with one workgroup to rounding, and is itself deterministic.  Rank
+    6 takes the one-tile product with padded operator blocks, rank 40 the four-tile one."""
+    log("cluster", cluster, "rank", cap)
+    p = W.advection_ie_variable(seed=5, d=4, n=128, ic_rank=3, cap=cap)
     handle.set_cluster(1)
     try:
         ref, rr = run_gpu_step(handle, p.A, p.B, p.f0, p.guess, tol=0.0, max_sweeps=4)
