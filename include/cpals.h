@@ -192,6 +192,29 @@ cp_status cp_als_run_batched(cp_handle h, int32_t count, const cp_operator* A, c
                              const cp_tensor* f_init, cp_tensor* f_io, int32_t n_steps,
                              const cp_als_opts* opts, cp_als_report* reports);
 
+/* The batched run captured once and replayed (the many-instance form of Section 3.1's time
+ * stepping, launched as a HIP graph).
+ *
+ * cp_batch_plan_create validates and packs the count problems exactly as cp_als_run_batched
+ * (same arguments), uploads their operator data once into device memory owned by the plan,
+ * and captures one run into a graph on a stream of the plan's own: copies of the f_init[i]
+ * and f_io[i] panels into the plan, the persistent kernel, the results back into f_io[i],
+ * the reports into pinned host memory of the plan.  The graph keeps the device pointers of
+ * f_init[i] and f_io[i]: those buffers must stay allocated, with the same shapes, until the
+ * plan is destroyed; their contents may change between runs.
+ *
+ * cp_batch_plan_run replays the graph after the work already queued on the handle's stream
+ * and waits for it; reports: count * n_steps entries, problem-major, as cp_als_run_batched
+ * (and the same CP_ERR_NOT_CONVERGED rule).  A plan is used by one thread at a time.
+ * cp_batch_plan_destroy waits for the plan's stream and frees everything the plan owns.
+ * Errors: those of cp_als_run_batched; CP_ERR_HIP when the capture or instantiation fails. */
+typedef struct cp_batch_plan_s* cp_batch_plan;
+cp_status cp_batch_plan_create(cp_handle h, int32_t count, const cp_operator* A, const cp_operator* B,
+                               const cp_tensor* f_init, cp_tensor* f_io, int32_t n_steps,
+                               const cp_als_opts* opts, cp_batch_plan* plan);
+cp_status cp_batch_plan_run(cp_handle h, cp_batch_plan plan, cp_als_report* reports);
+cp_status cp_batch_plan_destroy(cp_batch_plan plan);
+
 #ifdef __cplusplus
 }
 #endif

@@ -86,6 +86,10 @@ def lib() -> C.CDLL:
             "cp_als_run_batched": [H, C.c_int32, P(cp_operator), P(cp_operator), P(cp_tensor), P(cp_tensor),
                                    C.c_int32, P(cp_als_opts), P(cp_als_report)],
             "cp_als_default_opts": [P(cp_als_opts)],
+            "cp_batch_plan_create": [H, C.c_int32, P(cp_operator), P(cp_operator), P(cp_tensor), P(cp_tensor),
+                                     C.c_int32, P(cp_als_opts), P(H)],
+            "cp_batch_plan_run": [H, H, P(cp_als_report)],
+            "cp_batch_plan_destroy": [H],
             # learned warm start (include/cpals_ws.h)
             "cp_ws_create": [H, C.c_void_p, C.c_int32, C.c_int32, P(H)],
             "cp_ws_destroy": [H],
@@ -287,6 +291,36 @@ def cp_als_run_batched(h: Handle, As, Bs, f_inits, f_ios, n_steps: int,
     h.check(lib().cp_als_run_batched(h.h, count, A_arr, B_arr, fi, fo, n_steps, C.byref(opts), reps),
             allow_not_converged=True)
     return [[reps[i * n_steps + s].as_dict() for s in range(n_steps)] for i in range(count)]
+
+
+class BatchPlan:
+    """A batched run captured once in a HIP graph (cp_batch_plan_*): the tensors given here
+    must stay allocated while the plan lives; run() replays the captured run on their current
+    contents (results into f_ios) and returns the reports."""
+
+    def __init__(self, h: Handle, As, Bs, f_inits, f_ios, n_steps: int, opts: Optional[cp_als_opts] = None):
+        opts = default_opts() if opts is None else opts
+        self.h, self.count, self.n_steps = h, len(As), n_steps
+        self._keep = (list(f_inits), list(f_ios))
+        Ads = [OperatorDesc(a) for a in As]
+        Bds = [OperatorDesc(b) for b in Bs]
+        A_arr = (cp_operator * self.count)(*[a.desc for a in Ads])
+        B_arr = (cp_operator * self.count)(*[b.desc for b in Bds])
+        fi = (cp_tensor * self.count)(*[tensor_desc(f) for f in f_inits])
+        fo = (cp_tensor * self.count)(*[tensor_desc(f) for f in f_ios])
+        self.plan = C.c_void_p()
+        h.check(lib().cp_batch_plan_create(h.h, self.count, A_arr, B_arr, fi, fo, n_steps, C.byref(opts),
+                                           C.byref(self.plan)))
+
+    def run(self) -> List[List[dict]]:
+        reps = (cp_als_report * (self.count * self.n_steps))()
+        self.h.check(lib().cp_batch_plan_run(self.h.h, self.plan, reps), allow_not_converged=True)
+        return [[reps[i * self.n_steps + s].as_dict() for s in range(self.n_steps)] for i in range(self.count)]
+
+    def close(self):
+        if self.plan:
+            lib().cp_batch_plan_destroy(self.plan)
+            self.plan = C.c_void_p()
 
 
 # ----------------------------------------------------------------------------------------

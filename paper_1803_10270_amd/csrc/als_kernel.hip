@@ -1715,13 +1715,21 @@ __global__ void __launch_bounds__(WG) als_persistent(const Problem* __restrict__
 
 size_t als_smem_bytes() { return sizeof(Smem); }
 
-hipError_t launch_als(const Problem* d_problems, int count, int W, hipStream_t stream) {
-    const size_t smem = sizeof(Smem);
-    hipError_t e = hipFuncSetAttribute((const void*)als_persistent, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)smem);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(als_persistent, dim3(count * W), dim3(WG), smem, stream, d_problems, count, W);
+hipError_t prepare_als() {
+    return hipFuncSetAttribute((const void*)als_persistent, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)sizeof(Smem));
+}
+
+// The kernel's LDS size must have been allowed by prepare_als (launch_als does both).
+hipError_t launch_als_prepared(const Problem* d_problems, int count, int W, hipStream_t stream) {
+    hipLaunchKernelGGL(als_persistent, dim3(count * W), dim3(WG), sizeof(Smem), stream, d_problems, count, W);
     return hipGetLastError();
+}
+
+hipError_t launch_als(const Problem* d_problems, int count, int W, hipStream_t stream) {
+    hipError_t e = prepare_als();
+    if (e != hipSuccess) return e;
+    return launch_als_prepared(d_problems, count, W, stream);
 }
 
 }  // namespace cpals

@@ -19,10 +19,14 @@ hipError_t launch_inner(const GramJob& job, double* partial, double* out, bool s
 hipError_t launch_apply(const ApplyJob& job, int max_n, hipStream_t st);
 // defined in als_kernel.hip
 hipError_t launch_als(const Problem* d_problems, int count, int W, hipStream_t stream);
+hipError_t prepare_als();
+hipError_t launch_als_prepared(const Problem* d_problems, int count, int W, hipStream_t stream);
 size_t als_smem_bytes();
 }  // namespace cpals
 
 using namespace cpals;
+
+struct cp_batch_plan_s;
 
 struct cp_handle_s {
     hipStream_t stream = nullptr;
@@ -610,106 +614,167 @@ cp_status check_opts(cp_handle h, const cp_als_opts* o) {
     return CP_OK;
 }
 
-cp_status copy_panels_in(cp_handle h, const cp_tensor* t, double* dst, const int64_t* off) {
+cp_status copy_panels_in(cp_handle h, hipStream_t st, const cp_tensor* t, double* dst, const int64_t* off) {
     for (int k = 0; k < t->d; ++k)
         HIP_TRY(hipMemcpy2DAsync(dst + off[k], (size_t)t->n[k] * 8, t->U[k], (size_t)t->ld[k] * 8, (size_t)t->n[k] * 8,
-                                 t->r, hipMemcpyDeviceToDevice, h->stream),
+                                 t->r, hipMemcpyDeviceToDevice, st),
                 "hipMemcpy2DAsync(in)");
     return CP_OK;
 }
 
-cp_status copy_panels_out(cp_handle h, const double* src, const int64_t* off, cp_tensor* t) {
+cp_status copy_panels_out(cp_handle h, hipStream_t st, const double* src, const int64_t* off, cp_tensor* t) {
     for (int k = 0; k < t->d; ++k)
         HIP_TRY(hipMemcpy2DAsync(t->U[k], (size_t)t->ld[k] * 8, src + off[k], (size_t)t->n[k] * 8, (size_t)t->n[k] * 8,
-                                 t->r, hipMemcpyDeviceToDevice, h->stream),
+                                 t->r, hipMemcpyDeviceToDevice, st),
                 "hipMemcpy2DAsync(out)");
     return CP_OK;
 }
 
-cp_status run_problems(cp_handle h, int count, const HostOp* A, const HostOp* B, const cp_tensor* f_init,
-                       cp_tensor* f_io, int n_steps, const cp_als_opts* o, cp_als_report* reports, double* traj) {
-    std::vector<Packed> pk(count);
-    std::vector<size_t> base(count);
-    size_t total = 0;
-    // a single problem is shared by a cluster of workgroups (grid rows split between them)
-    // when every n_k splits into 16-row strips and no rank-1 operator is present
+// Zeroes the arrival counters of the cluster barriers (a kernel rather than a memset so that
+// the sequence can be captured in a graph).
+__global__ void zero_words(uint32_t* p, int n) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) p[t] = 0u;
+}
+
+// Problems packed for one launch: the static part (operator data, pair records, problem
+// descriptors) is uploaded once; every run copies the panels in, launches, copies them out.
+struct Staged {
+    int count = 0, n_steps = 0, W = 1;
+    std::vector<Packed> pk;
+    std::vector<size_t> base;
+    size_t total = 0;      // packed regions; the descriptor array follows
+    size_t bytes = 0;      // total device bytes
+    Problem* d_desc = nullptr;
+    std::vector<Problem> descs;   // host copy of the descriptor array (source of its upload)
+};
+
+// Cluster size for a single problem: the largest power of two <= max_cluster with every
+// n_k a multiple of 16 W (16-row strips per workgroup) and no rank-1 operator.
+int cluster_size(cp_handle h, const HostOp& A, const HostOp& B, const cp_tensor& f) {
+    bool ok = f.d > 1;
+    for (int k = 0; k < f.d; ++k) {
+        for (int a = 0; a < A.m[k]; ++a) ok = ok && A.ops[k][a].kind != CP_OP_RANK1;
+        for (int b = 0; b < B.m[k]; ++b) ok = ok && B.ops[k][b].kind != CP_OP_RANK1;
+    }
+    if (!ok) return 1;
     int W = 1;
-    if (count == 1) {
-        bool ok = f_io[0].d > 1;
-        for (int k = 0; k < f_io[0].d; ++k) {
-            for (int a = 0; a < A[0].m[k]; ++a) ok = ok && A[0].ops[k][a].kind != CP_OP_RANK1;
-            for (int b = 0; b < B[0].m[k]; ++b) ok = ok && B[0].ops[k][b].kind != CP_OP_RANK1;
-        }
-        W = ok ? std::max(1, std::min(h->max_cluster, 256)) : 1;
-        // largest power of two <= max_cluster with n_k divisible by 16 W for every k
-        int w = 1;
-        while (2 * w <= W) w *= 2;
-        W = w;
-        for (; W > 1; W /= 2) {
-            bool div = true;
-            for (int k = 0; k < f_io[0].d; ++k) div = div && (f_io[0].n[k] % (16 * W) == 0);
-            if (div) break;
-        }
+    while (2 * W <= std::min(h->max_cluster, 256)) W *= 2;
+    for (; W > 1; W /= 2) {
+        bool div = true;
+        for (int k = 0; k < f.d; ++k) div = div && (f.n[k] % (16 * W) == 0);
+        if (div) break;
     }
+    return W;
+}
+
+cp_status stage_problems(cp_handle h, int count, const HostOp* A, const HostOp* B, const cp_tensor* f_init,
+                         const cp_tensor* f_io, int n_steps, const cp_als_opts* o, int W, Staged& S) {
+    S.count = count;
+    S.n_steps = n_steps;
+    S.W = W;
+    S.pk.resize(count);
+    S.base.resize(count);
+    S.total = 0;
     for (int i = 0; i < count; ++i) {
-        cp_status st = pack_problem(h, A[i], B[i], &f_init[i], &f_io[i], n_steps, *o, W, pk[i]);
+        cp_status st = pack_problem(h, A[i], B[i], &f_init[i], &f_io[i], n_steps, *o, W, S.pk[i]);
         if (st != CP_OK) return st;
-        base[i] = total;
-        total += align_up(pk[i].lay.total);
+        S.base[i] = S.total;
+        S.total += align_up(S.pk[i].lay.total);
     }
-    // problem descriptors are gathered in one array, ordered by estimated cost (largest
-    // first) so that the longest problems start first when workgroups outnumber CUs
-    const size_t desc_bytes = align_up((size_t)count * sizeof(Problem));
-    cp_status st = ensure_ws(h, total + desc_bytes);
-    if (st != CP_OK) return st;
-    char* ws = static_cast<char*>(h->ws);
+    S.bytes = S.total + align_up((size_t)count * sizeof(Problem));
+    return CP_OK;
+}
+
+// Rebases the packed problems onto device memory `ws` and uploads their static data and the
+// descriptor array (ordered by estimated cost, largest first, so that the longest problems
+// start first when workgroups outnumber CUs).
+cp_status upload_static(cp_handle h, Staged& S, char* ws, double* traj, const cp_tensor* f_io, hipStream_t st,
+                        bool wait) {
+    const int count = S.count;
     std::vector<int> order(count);
     std::vector<double> cost(count);
     for (int i = 0; i < count; ++i) {
         order[i] = i;
         double c = 0.0;
-        for (int k = 0; k < f_io[i].d; ++k) c += (double)f_io[i].n[k] * A[i].m[k] * A[i].m[k] * f_io[i].r * f_io[i].r;
+        for (int k = 0; k < f_io[i].d; ++k) c += (double)f_io[i].n[k] * S.pk[i].pb.mA[k] * S.pk[i].pb.mA[k] * f_io[i].r * f_io[i].r;
         cost[i] = c;
     }
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
-    std::vector<Problem> descs(count);
     for (int i = 0; i < count; ++i) {
-        Packed& p = pk[i];
-        char* b = ws + base[i];
+        Packed& p = S.pk[i];
+        char* b = ws + S.base[i];
         rebase(p, b, traj);
-        HIP_TRY(hipMemcpyAsync(b + p.lay.opdata, p.opdata.data(), p.opdata.size() * 8, hipMemcpyHostToDevice, h->stream),
+        HIP_TRY(hipMemcpyAsync(b + p.lay.opdata, p.opdata.data(), p.opdata.size() * 8, hipMemcpyHostToDevice, st),
                 "hipMemcpyAsync(opdata)");
         if (!p.pairsC.empty())
             HIP_TRY(hipMemcpyAsync(b + p.lay.pairsC, p.pairsC.data(), p.pairsC.size() * sizeof(PairRec),
-                                   hipMemcpyHostToDevice, h->stream),
+                                   hipMemcpyHostToDevice, st),
                     "hipMemcpyAsync(pairsC)");
         if (!p.pairsD.empty())
             HIP_TRY(hipMemcpyAsync(b + p.lay.pairsD, p.pairsD.data(), p.pairsD.size() * sizeof(PairRec),
-                                   hipMemcpyHostToDevice, h->stream),
+                                   hipMemcpyHostToDevice, st),
                     "hipMemcpyAsync(pairsD)");
-        st = copy_panels_in(h, &f_init[i], p.pb.V, p.pb.offV);
-        if (st != CP_OK) return st;
-        st = copy_panels_in(h, &f_io[i], p.pb.U, p.pb.offU);
-        if (st != CP_OK) return st;
-        HIP_TRY(hipMemsetAsync(p.pb.bar, 0, 256, h->stream), "hipMemsetAsync(barrier)");
     }
-    for (int j = 0; j < count; ++j) descs[j] = pk[order[j]].pb;
-    Problem* d_desc = reinterpret_cast<Problem*>(ws + total);
-    HIP_TRY(hipMemcpyAsync(d_desc, descs.data(), (size_t)count * sizeof(Problem), hipMemcpyHostToDevice, h->stream),
+    S.descs.resize(count);
+    for (int j = 0; j < count; ++j) S.descs[j] = S.pk[order[j]].pb;
+    S.d_desc = reinterpret_cast<Problem*>(ws + S.total);
+    HIP_TRY(hipMemcpyAsync(S.d_desc, S.descs.data(), (size_t)count * sizeof(Problem), hipMemcpyHostToDevice, st),
             "hipMemcpyAsync(problems)");
-    HIP_TRY(launch_als(d_desc, count, W, h->stream), "als kernel launch");
-    for (int i = 0; i < count; ++i) {
-        st = copy_panels_out(h, pk[i].pb.U, pk[i].pb.offU, &f_io[i]);
-        if (st != CP_OK) return st;
-        HIP_TRY(hipMemcpyAsync(reports + (size_t)i * n_steps, pk[i].pb.reports, (size_t)n_steps * sizeof(cp_als_report),
-                               hipMemcpyDeviceToHost, h->stream),
+    // with `wait` the host data may be released on return (else it must outlive the copies)
+    if (wait) HIP_TRY(hipStreamSynchronize(st), "hipStreamSynchronize");
+    return CP_OK;
+}
+
+// One run on stream st: panels in, barrier counters zeroed (clusters), the persistent
+// kernel, panels out, reports to the host buffer `rep` (count * n_steps entries).
+cp_status enqueue_run(cp_handle h, const Staged& S, const cp_tensor* f_init, cp_tensor* f_io, cp_als_report* rep,
+                      hipStream_t st, bool prepared = false) {
+    for (int i = 0; i < S.count; ++i) {
+        const Packed& p = S.pk[i];
+        cp_status s2 = copy_panels_in(h, st, &f_init[i], p.pb.V, p.pb.offV);
+        if (s2 != CP_OK) return s2;
+        s2 = copy_panels_in(h, st, &f_io[i], p.pb.U, p.pb.offU);
+        if (s2 != CP_OK) return s2;
+        if (S.W > 1) {
+            hipLaunchKernelGGL(zero_words, dim3(1), dim3(64), 0, st, p.pb.bar, 64);
+            HIP_TRY(hipGetLastError(), "zero_words");
+        }
+    }
+    HIP_TRY(prepared ? launch_als_prepared(S.d_desc, S.count, S.W, st) : launch_als(S.d_desc, S.count, S.W, st),
+            "als kernel launch");
+    for (int i = 0; i < S.count; ++i) {
+        cp_status s2 = copy_panels_out(h, st, S.pk[i].pb.U, S.pk[i].pb.offU, &f_io[i]);
+        if (s2 != CP_OK) return s2;
+        HIP_TRY(hipMemcpyAsync(rep + (size_t)i * S.n_steps, S.pk[i].pb.reports, (size_t)S.n_steps * sizeof(cp_als_report),
+                               hipMemcpyDeviceToHost, st),
                 "hipMemcpyAsync(reports)");
     }
-    HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+    return CP_OK;
+}
+
+cp_status check_reports(cp_handle h, const cp_als_report* reports, int n) {
     bool nc = false;
-    for (int i = 0; i < count * n_steps; ++i) nc |= (reports[i].flags & CP_FLAG_NOT_CONVERGED) != 0;
+    for (int i = 0; i < n; ++i) nc |= (reports[i].flags & CP_FLAG_NOT_CONVERGED) != 0;
     if (nc) return fail(h, CP_ERR_NOT_CONVERGED, "ALS reached max_sweeps before eps_conv <= tol");
     return CP_OK;
+}
+
+cp_status run_problems(cp_handle h, int count, const HostOp* A, const HostOp* B, const cp_tensor* f_init,
+                       cp_tensor* f_io, int n_steps, const cp_als_opts* o, cp_als_report* reports, double* traj) {
+    // a single problem is shared by a cluster of workgroups (grid rows split between them)
+    const int W = (count == 1) ? cluster_size(h, A[0], B[0], f_io[0]) : 1;
+    Staged S;
+    cp_status st = stage_problems(h, count, A, B, f_init, f_io, n_steps, o, W, S);
+    if (st != CP_OK) return st;
+    st = ensure_ws(h, S.bytes);
+    if (st != CP_OK) return st;
+    st = upload_static(h, S, static_cast<char*>(h->ws), traj, f_io, h->stream, false);
+    if (st != CP_OK) return st;
+    st = enqueue_run(h, S, f_init, f_io, reports, h->stream);
+    if (st != CP_OK) return st;
+    HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+    return check_reports(h, reports, count * n_steps);
 }
 
 cp_status prepare_step(cp_handle h, const cp_operator* A, const cp_operator* B, const cp_tensor* f_init,
@@ -938,6 +1003,115 @@ cp_status cp_als_run_batched(cp_handle h, int32_t count, const cp_operator* A, c
         if (st != CP_OK) return fail(h, st, "problem " + std::to_string(i) + ": " + h->err);
     }
     return run_problems(h, count, hA.data(), hB.data(), f_init, f_io, n_steps, opts, reports, nullptr);
+}
+
+}  // extern "C"
+
+// A batched launch captured once in a HIP graph: the packed problems live in the plan's own
+// device memory, the graph holds the per-run sequence (panels in, barrier counters zeroed,
+// the persistent kernel, panels out, reports into pinned host memory) and is replayed on the
+// plan's stream (default priority).
+struct cp_batch_plan_s {
+    Staged S;
+    int count = 0, n_steps = 0;
+    std::vector<cp_tensor> f_init, f_io;
+    hipStream_t stream = nullptr;
+    void* dmem = nullptr;
+    cp_als_report* rep = nullptr;   // pinned host memory, count * n_steps
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t ready = nullptr;
+};
+
+namespace {
+void plan_release(cp_batch_plan p) {
+    if (!p) return;
+    if (p->stream) (void)hipStreamSynchronize(p->stream);
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->ready) (void)hipEventDestroy(p->ready);
+    if (p->rep) (void)hipHostFree(p->rep);
+    if (p->dmem) (void)hipFree(p->dmem);
+    if (p->stream) (void)hipStreamDestroy(p->stream);
+    delete p;
+}
+}  // namespace
+
+extern "C" {
+
+cp_status cp_batch_plan_create(cp_handle h, int32_t count, const cp_operator* A, const cp_operator* B,
+                               const cp_tensor* f_init, cp_tensor* f_io, int32_t n_steps, const cp_als_opts* opts,
+                               cp_batch_plan* plan) {
+    if (!h) return CP_ERR_INVALID_ARG;
+    if (count < 1 || !A || !B || !f_init || !f_io || !plan) return fail(h, CP_ERR_INVALID_ARG, "bad plan arguments");
+    *plan = nullptr;
+    std::vector<HostOp> hA(count), hB(count);
+    for (int i = 0; i < count; ++i) {
+        cp_status st = prepare_step(h, &A[i], &B[i], &f_init[i], &f_io[i], n_steps, opts, hA[i], hB[i]);
+        if (st != CP_OK) return fail(h, st, "problem " + std::to_string(i) + ": " + h->err);
+    }
+    cp_batch_plan p = new (std::nothrow) cp_batch_plan_s();
+    if (!p) return fail(h, CP_ERR_HIP, "out of host memory");
+    p->count = count;
+    p->n_steps = n_steps;
+    p->f_init.assign(f_init, f_init + count);
+    p->f_io.assign(f_io, f_io + count);
+    const int W = (count == 1) ? cluster_size(h, hA[0], hB[0], f_io[0]) : 1;
+    cp_status st = stage_problems(h, count, hA.data(), hB.data(), f_init, f_io, n_steps, opts, W, p->S);
+    hipError_t e = hipSuccess;
+    const char* what = "";
+    if (st == CP_OK) {
+        if ((e = hipStreamCreate(&p->stream)) != hipSuccess) what = "hipStreamCreate";
+        else if ((e = hipMalloc(&p->dmem, p->S.bytes)) != hipSuccess) what = "hipMalloc";
+        else if ((e = hipHostMalloc((void**)&p->rep, (size_t)count * n_steps * sizeof(cp_als_report), hipHostMallocDefault)) != hipSuccess)
+            what = "hipHostMalloc";
+        else if ((e = hipEventCreateWithFlags(&p->ready, hipEventDisableTiming)) != hipSuccess) what = "hipEventCreate";
+        else if ((e = prepare_als()) != hipSuccess) what = "hipFuncSetAttribute";
+    }
+    if (st == CP_OK && e == hipSuccess)
+        st = upload_static(h, p->S, static_cast<char*>(p->dmem), nullptr, f_io, p->stream, true);
+    if (st == CP_OK && e == hipSuccess) {
+        if ((e = hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal)) != hipSuccess) {
+            what = "hipStreamBeginCapture";
+        } else {
+            st = enqueue_run(h, p->S, p->f_init.data(), p->f_io.data(), p->rep, p->stream, true);
+            hipGraph_t g = nullptr;
+            const hipError_t e2 = hipStreamEndCapture(p->stream, &g);
+            p->graph = g;
+            if (st == CP_OK && e2 != hipSuccess) {
+                e = e2;
+                what = "hipStreamEndCapture";
+            }
+            if (st == CP_OK && e == hipSuccess && (e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0)) != hipSuccess)
+                what = "hipGraphInstantiate";
+        }
+    }
+    if (st == CP_OK && e != hipSuccess) st = hip_fail(h, e, what);
+    if (st != CP_OK) {
+        plan_release(p);
+        return st;
+    }
+    *plan = p;
+    return CP_OK;
+}
+
+cp_status cp_batch_plan_run(cp_handle h, cp_batch_plan plan, cp_als_report* reports) {
+    if (!h) return CP_ERR_INVALID_ARG;
+    if (!plan || !reports) return fail(h, CP_ERR_INVALID_ARG, "null plan or reports");
+    // the run starts after the work already queued on the handle's stream
+    HIP_TRY(hipEventRecord(plan->ready, h->stream), "hipEventRecord");
+    HIP_TRY(hipStreamWaitEvent(plan->stream, plan->ready, 0), "hipStreamWaitEvent");
+    HIP_TRY(hipGraphLaunch(plan->exec, plan->stream), "hipGraphLaunch");
+    HIP_TRY(hipStreamSynchronize(plan->stream), "hipStreamSynchronize");
+    const int n = plan->count * plan->n_steps;
+    std::memcpy(reports, plan->rep, (size_t)n * sizeof(cp_als_report));
+    return check_reports(h, reports, n);
+}
+
+cp_status cp_batch_plan_destroy(cp_batch_plan plan) {
+    if (!plan) return CP_ERR_INVALID_ARG;
+    plan_release(plan);
+    return CP_OK;
 }
 
 }  // extern "C"

@@ -197,6 +197,41 @@ def test_batched_matches_single(handle):
         handle.set_cluster(16)
 
 
+@pytest.mark.parametrize("case", ["batch", "cluster"])
+def test_batch_plan_replays_match_eager(handle, case):
+    """The graph-captured run (cp_batch_plan_*), replayed three times with the program's own
+    device work on the handle's stream between the replays, gives bitwise the eager result of
+    cp_als_run_batched on the same inputs every time.  'cluster': one problem on a cluster of
+    workgroups, whose barrier counters are reset inside the graph at every replay."""
+    import torch
+    log("batch plan", case)
+    if case == "batch":
+        probs = [W.advection_ie_constant(seed=s, d=d, n=n, cap=c, ic_rank=2, n_steps=2)
+                 for s, d, n, c in [(1, 4, 64, 5), (2, 6, 32, 3), (3, 3, 128, 8)]]
+    else:
+        probs = [W.advection_ie_variable(seed=6, d=4, n=64, ic_rank=2, cap=6)]
+    opts = B.default_opts(tol=1e-8, max_sweeps=30)
+    As, Bs = [p.A for p in probs], [p.B for p in probs]
+    ref_out = [dev(p.guess) for p in probs]
+    ref = B.cp_als_run_batched(handle, As, Bs, [dev(p.f0) for p in probs], ref_out, 2, opts)
+    fi = [dev(p.f0) for p in probs]
+    fo = [dev(p.guess) for p in probs]
+    start = [[u.clone() for u in f] for f in fo]
+    plan = B.BatchPlan(handle, As, Bs, fi, fo, 2, opts)
+    try:
+        for rep in range(3):
+            for f, s0 in zip(fo, start):          # eager device work between the replays
+                for u, v in zip(f, s0):
+                    u.mul_(0.0).add_(v)
+            reps = plan.run()
+            torch.cuda.synchronize()
+            assert [[r["sweeps"] for r in rr] for rr in reps] == [[r["sweeps"] for r in rr] for rr in ref]
+            for f, g in zip(fo, ref_out):
+                assert all(np.array_equal(a, b) for a, b in zip(host(f), host(g))), "replay %d" % rep
+    finally:
+        plan.close()
+
+
 @pytest.mark.parametrize("cluster,cap", [(2, 6), (4, 6), (8, 6), (8, 40)])
 def test_cluster_matches_single_workgroup(handle, cluster, cap):
     """A problem shared by a cluster of workgroups (grid rows split, partial sums added in a
