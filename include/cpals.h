@@ -185,7 +185,8 @@ cp_status cp_als_run(cp_handle h, const cp_operator* A, const cp_operator* B, co
 cp_status cp_truncate(cp_handle h, const cp_tensor* g, cp_tensor* f, const cp_als_opts* opts,
                       cp_als_report* report);
 
-/* Many independent problems advanced in one persistent launch (one workgroup per problem).
+/* Many independent problems advanced in one persistent launch (one workgroup per problem, or
+ * the tuned cluster sizes: see cp_tune_cluster).
  * Arrays of length count: A[i], B[i] (host descriptions), f_init[i], f_io[i] as in
  * cp_als_run; reports: count * n_steps entries, problem-major. */
 cp_status cp_als_run_batched(cp_handle h, int32_t count, const cp_operator* A, const cp_operator* B,
@@ -214,6 +215,31 @@ cp_status cp_batch_plan_create(cp_handle h, int32_t count, const cp_operator* A,
                                const cp_als_opts* opts, cp_batch_plan* plan);
 cp_status cp_batch_plan_run(cp_handle h, cp_batch_plan plan, cp_als_report* reports);
 cp_status cp_batch_plan_destroy(cp_batch_plan plan);
+
+/* Cluster-size tuning.  A problem can be advanced by a cluster of W workgroups that split its
+ * grid rows (W a power of two <= the cp_set_cluster limit, every n_k a multiple of 16 W, no
+ * rank-1 operator); the handle keeps a table of tuned W per problem shape (d, n_k, r, the
+ * rank of f_n, the operator counts per dimension, the precision).
+ *
+ * cp_tune_cluster times `sweeps` sweeps (tol 0) of the implicit step of Section 3.1 for f_n
+ * from guess with every admissible W (each once to warm up, then timed with HIP events on the
+ * handle's stream), records the fastest in the table and returns it in *best_w and its time
+ * in *best_ms (nullable).  guess is left untouched (trials run on a copy the call allocates
+ * and frees).
+ * Use of the table: a single problem (cp_als_step, cp_als_run, a plan of one problem) runs
+ * with its tuned W when one is recorded, else with the largest admissible W.  A batch
+ * (cp_als_run_batched, cp_batch_plan_create) gives every problem its tuned W (1 where none
+ * is recorded) when all workgroups of the launch fit on the device at once (at most one
+ * workgroup per compute unit), else one workgroup to each problem.
+ * cp_tune_save writes the table as JSON, {"cluster": {"<shape>": W, ...}}; cp_tune_load
+ * merges such a file into the table (CP_ERR_INVALID_ARG for a file that cannot be read or
+ * parsed, or a W that is not a power of two in 1..256); cp_tune_clear empties it. */
+cp_status cp_tune_cluster(cp_handle h, const cp_operator* A, const cp_operator* B, const cp_tensor* f_n,
+                          const cp_tensor* guess, const cp_als_opts* opts, int32_t sweeps, int32_t* best_w,
+                          float* best_ms);
+cp_status cp_tune_save(cp_handle h, const char* path);
+cp_status cp_tune_load(cp_handle h, const char* path);
+cp_status cp_tune_clear(cp_handle h);
 
 #ifdef __cplusplus
 }

@@ -90,6 +90,9 @@ def lib() -> C.CDLL:
                                      C.c_int32, P(cp_als_opts), P(H)],
             "cp_batch_plan_run": [H, H, P(cp_als_report)],
             "cp_batch_plan_destroy": [H],
+            "cp_tune_cluster": [H, P(cp_operator), P(cp_operator), P(cp_tensor), P(cp_tensor), P(cp_als_opts),
+                                C.c_int32, P(C.c_int32), P(C.c_float)],
+            "cp_tune_save": [H, C.c_char_p], "cp_tune_load": [H, C.c_char_p], "cp_tune_clear": [H],
             # learned warm start (include/cpals_ws.h)
             "cp_ws_create": [H, C.c_void_p, C.c_int32, C.c_int32, P(H)],
             "cp_ws_destroy": [H],
@@ -291,6 +294,30 @@ def cp_als_run_batched(h: Handle, As, Bs, f_inits, f_ios, n_steps: int,
     h.check(lib().cp_als_run_batched(h.h, count, A_arr, B_arr, fi, fo, n_steps, C.byref(opts), reps),
             allow_not_converged=True)
     return [[reps[i * n_steps + s].as_dict() for s in range(n_steps)] for i in range(count)]
+
+
+def cp_tune_cluster(h: Handle, A, B, f_n, guess, opts: Optional[cp_als_opts] = None, sweeps: int = 3):
+    """Times every admissible cluster size on this problem, records the fastest in the
+    handle's table and returns (W, milliseconds for `sweeps` sweeps)."""
+    opts = default_opts() if opts is None else opts
+    Ad, Bd = OperatorDesc(A), OperatorDesc(B)
+    fd, gd = tensor_desc(f_n), tensor_desc(guess)
+    w, ms = C.c_int32(0), C.c_float(0.0)
+    h.check(lib().cp_tune_cluster(h.h, C.byref(Ad.desc), C.byref(Bd.desc), C.byref(fd), C.byref(gd), C.byref(opts),
+                                  sweeps, C.byref(w), C.byref(ms)))
+    return int(w.value), float(ms.value)
+
+
+def cp_tune_save(h: Handle, path: str):
+    h.check(lib().cp_tune_save(h.h, path.encode()))
+
+
+def cp_tune_load(h: Handle, path: str):
+    h.check(lib().cp_tune_load(h.h, path.encode()))
+
+
+def cp_tune_clear(h: Handle):
+    h.check(lib().cp_tune_clear(h.h))
 
 
 class BatchPlan:

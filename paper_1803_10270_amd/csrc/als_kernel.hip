@@ -1389,12 +1389,29 @@ enum : int { OP_STEP, OP_REFRESH, OP_UPDATE, OP_CG, OP_DELTA, OP_SWEEP, OP_REPOR
 // phases of one dimension update's composite products
 enum : int { PH_RHS, PH_PRE_B, PH_MV_X, PH_PRE_R0, PH_MV_P0, PH_PRE_R, PH_MV_P };
 
-__global__ void __launch_bounds__(WG) als_persistent(const Problem* __restrict__ problems, int count, int W) {
+__global__ void __launch_bounds__(WG) als_persistent(const Problem* __restrict__ problems, int count, int W,
+                                                      const int32_t* __restrict__ wg_first) {
     Smem& s = SMEM;
-    // workgroups pid W .. pid W + W - 1 advance problem pid together
-    const int pid = blockIdx.x / W;
+    // problem pid is advanced by its workgroups wg_first[pid] .. wg_first[pid + 1] - 1 (a
+    // table of count + 1 offsets) or, without the table, by workgroups pid W .. pid W + W - 1
+    int pid, cpart, Wp;
+    if (wg_first) {
+        const int b = blockIdx.x;
+        int lo = 0, hi = count;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (wg_first[mid] <= b) lo = mid;
+            else hi = mid;
+        }
+        pid = lo;
+        cpart = b - wg_first[lo];
+        Wp = wg_first[lo + 1] - wg_first[lo];
+    } else {
+        pid = blockIdx.x / W;
+        cpart = blockIdx.x - pid * W;
+        Wp = W;
+    }
     if (pid >= count) return;
-    const int cpart = blockIdx.x - pid * W;
     {
         const uint32_t* src = reinterpret_cast<const uint32_t*>(problems + pid);
         uint32_t* dst = reinterpret_cast<uint32_t*>(&s.pb);
@@ -1404,7 +1421,7 @@ __global__ void __launch_bounds__(WG) als_persistent(const Problem* __restrict__
             s.ident.hbw = 0;
             s.ident.data = nullptr;
             s.part = cpart;
-            s.W = W;
+            s.W = Wp;
             s.bar_target = 0;
             s.sync_ok = 1;
             s.dcount = 0;
@@ -1721,15 +1738,20 @@ hipError_t prepare_als() {
 }
 
 // The kernel's LDS size must have been allowed by prepare_als (launch_als does both).
-hipError_t launch_als_prepared(const Problem* d_problems, int count, int W, hipStream_t stream) {
-    hipLaunchKernelGGL(als_persistent, dim3(count * W), dim3(WG), sizeof(Smem), stream, d_problems, count, W);
+// Uniform clusters of W workgroups (wg_first null, grid count W), or per-problem clusters
+// given by the device table wg_first (count + 1 offsets, grid = total workgroups).
+hipError_t launch_als_prepared(const Problem* d_problems, int count, int W, const int32_t* wg_first, int total_wg,
+                               hipStream_t stream) {
+    const int grid = wg_first ? total_wg : count * W;
+    hipLaunchKernelGGL(als_persistent, dim3(grid), dim3(WG), sizeof(Smem), stream, d_problems, count, W, wg_first);
     return hipGetLastError();
 }
 
-hipError_t launch_als(const Problem* d_problems, int count, int W, hipStream_t stream) {
+hipError_t launch_als(const Problem* d_problems, int count, int W, const int32_t* wg_first, int total_wg,
+                      hipStream_t stream) {
     hipError_t e = prepare_als();
     if (e != hipSuccess) return e;
-    return launch_als_prepared(d_problems, count, W, stream);
+    return launch_als_prepared(d_problems, count, W, wg_first, total_wg, stream);
 }
 
 }  // namespace cpals

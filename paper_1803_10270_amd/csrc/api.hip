@@ -3,9 +3,11 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <new>
 #include <string>
 #include <vector>
@@ -18,9 +20,11 @@ int gram_chunks(const int32_t* n, int d, int32_t* chunk0);
 hipError_t launch_inner(const GramJob& job, double* partial, double* out, bool sqrt_out, hipStream_t st);
 hipError_t launch_apply(const ApplyJob& job, int max_n, hipStream_t st);
 // defined in als_kernel.hip
-hipError_t launch_als(const Problem* d_problems, int count, int W, hipStream_t stream);
+hipError_t launch_als(const Problem* d_problems, int count, int W, const int32_t* wg_first, int total_wg,
+                      hipStream_t stream);
 hipError_t prepare_als();
-hipError_t launch_als_prepared(const Problem* d_problems, int count, int W, hipStream_t stream);
+hipError_t launch_als_prepared(const Problem* d_problems, int count, int W, const int32_t* wg_first, int total_wg,
+                               hipStream_t stream);
 size_t als_smem_bytes();
 }  // namespace cpals
 
@@ -32,6 +36,8 @@ struct cp_handle_s {
     hipStream_t stream = nullptr;
     int device = 0;
     int max_cluster = 16;     // workgroups that may share one problem (cp_set_cluster)
+    int n_cu = 256;           // compute units of the device (co-residency bound of clusters)
+    std::map<std::string, int> tuned;   // cluster size per problem shape (cp_tune_cluster)
     std::string err;
     void* ws = nullptr;
     size_t ws_bytes = 0;
@@ -640,13 +646,17 @@ __global__ void zero_words(uint32_t* p, int n) {
 // Problems packed for one launch: the static part (operator data, pair records, problem
 // descriptors) is uploaded once; every run copies the panels in, launches, copies them out.
 struct Staged {
-    int count = 0, n_steps = 0, W = 1;
+    int count = 0, n_steps = 0;
+    std::vector<int> W;    // workgroups per problem
     std::vector<Packed> pk;
     std::vector<size_t> base;
-    size_t total = 0;      // packed regions; the descriptor array follows
+    size_t total = 0;      // packed regions; the descriptor array and the workgroup table follow
     size_t bytes = 0;      // total device bytes
     Problem* d_desc = nullptr;
-    std::vector<Problem> descs;   // host copy of the descriptor array (source of its upload)
+    int32_t* d_wg_first = nullptr;   // null: every problem has W[0] workgroups
+    int total_wg = 0;
+    std::vector<Problem> descs;      // host copies (sources of the uploads)
+    std::vector<int32_t> wg_first;
 };
 
 // Cluster size for a single problem: the largest power of two <= max_cluster with every
@@ -668,8 +678,54 @@ int cluster_size(cp_handle h, const HostOp& A, const HostOp& B, const cp_tensor&
     return W;
 }
 
+// Whether W workgroups may share the problem: a power of two <= max_cluster, every n_k a
+// multiple of 16 W, and (W > 1) no rank-1 operator.
+bool cluster_ok(cp_handle h, const HostOp& A, const HostOp& B, const cp_tensor& f, int W) {
+    if (W < 1 || (W & (W - 1)) || W > h->max_cluster) return false;
+    if (W == 1) return true;
+    return cluster_size(h, A, B, f) >= W;
+}
+
+// The problem shape a tuned cluster size is recorded for.
+std::string shape_key(const HostOp& A, const HostOp& B, const cp_tensor& f_init, const cp_tensor& f_io,
+                      const cp_als_opts& o) {
+    std::string k = "d=" + std::to_string(f_io.d) + ";n=";
+    for (int i = 0; i < f_io.d; ++i) k += (i ? "," : "") + std::to_string(f_io.n[i]);
+    k += ";r=" + std::to_string(f_io.r) + ";r0=" + std::to_string(f_init.r) + ";mA=";
+    for (int i = 0; i < f_io.d; ++i) k += (i ? "," : "") + std::to_string(A.m[i]);
+    k += ";mB=";
+    for (int i = 0; i < f_io.d; ++i) k += (i ? "," : "") + std::to_string(B.m[i]);
+    k += ";prec=" + std::to_string((int)o.precision);
+    return k;
+}
+
+// Workgroups per problem.  One problem: its tuned size when one is recorded (and still
+// admissible), else the largest admissible.  Several problems: their tuned sizes (1 where
+// none is recorded), provided every workgroup of the launch fits on the device at once (a
+// cluster's workgroups wait for each other), else one workgroup each.
+std::vector<int> choose_clusters(cp_handle h, int count, const HostOp* A, const HostOp* B, const cp_tensor* f_init,
+                                 const cp_tensor* f_io, const cp_als_opts& o) {
+    std::vector<int> W(count, 1);
+    if (count == 1) {
+        auto it = h->tuned.find(shape_key(A[0], B[0], f_init[0], f_io[0], o));
+        W[0] = (it != h->tuned.end() && cluster_ok(h, A[0], B[0], f_io[0], it->second))
+                   ? it->second : cluster_size(h, A[0], B[0], f_io[0]);
+        return W;
+    }
+    if (h->tuned.empty()) return W;
+    long total = 0;
+    for (int i = 0; i < count; ++i) {
+        auto it = h->tuned.find(shape_key(A[i], B[i], f_init[i], f_io[i], o));
+        if (it != h->tuned.end() && cluster_ok(h, A[i], B[i], f_io[i], it->second)) W[i] = it->second;
+        total += W[i];
+    }
+    if (total > h->n_cu) std::fill(W.begin(), W.end(), 1);
+    return W;
+}
+
 cp_status stage_problems(cp_handle h, int count, const HostOp* A, const HostOp* B, const cp_tensor* f_init,
-                         const cp_tensor* f_io, int n_steps, const cp_als_opts* o, int W, Staged& S) {
+                         const cp_tensor* f_io, int n_steps, const cp_als_opts* o, const std::vector<int>& W,
+                         Staged& S) {
     S.count = count;
     S.n_steps = n_steps;
     S.W = W;
@@ -677,12 +733,12 @@ cp_status stage_problems(cp_handle h, int count, const HostOp* A, const HostOp* 
     S.base.resize(count);
     S.total = 0;
     for (int i = 0; i < count; ++i) {
-        cp_status st = pack_problem(h, A[i], B[i], &f_init[i], &f_io[i], n_steps, *o, W, S.pk[i]);
+        cp_status st = pack_problem(h, A[i], B[i], &f_init[i], &f_io[i], n_steps, *o, W[i], S.pk[i]);
         if (st != CP_OK) return st;
         S.base[i] = S.total;
         S.total += align_up(S.pk[i].lay.total);
     }
-    S.bytes = S.total + align_up((size_t)count * sizeof(Problem));
+    S.bytes = S.total + align_up((size_t)count * sizeof(Problem)) + align_up((size_t)(count + 1) * sizeof(int32_t));
     return CP_OK;
 }
 
@@ -721,6 +777,19 @@ cp_status upload_static(cp_handle h, Staged& S, char* ws, double* traj, const cp
     S.d_desc = reinterpret_cast<Problem*>(ws + S.total);
     HIP_TRY(hipMemcpyAsync(S.d_desc, S.descs.data(), (size_t)count * sizeof(Problem), hipMemcpyHostToDevice, st),
             "hipMemcpyAsync(problems)");
+    // workgroup table (in descriptor order) when the problems' cluster sizes differ
+    bool uniform = true;
+    for (int i = 1; i < count; ++i) uniform = uniform && S.W[i] == S.W[0];
+    S.wg_first.assign(count + 1, 0);
+    for (int j = 0; j < count; ++j) S.wg_first[j + 1] = S.wg_first[j] + S.W[order[j]];
+    S.total_wg = S.wg_first[count];
+    S.d_wg_first = nullptr;
+    if (!uniform) {
+        S.d_wg_first = reinterpret_cast<int32_t*>(ws + S.total + align_up((size_t)count * sizeof(Problem)));
+        HIP_TRY(hipMemcpyAsync(S.d_wg_first, S.wg_first.data(), (size_t)(count + 1) * sizeof(int32_t),
+                               hipMemcpyHostToDevice, st),
+                "hipMemcpyAsync(workgroup table)");
+    }
     // with `wait` the host data may be released on return (else it must outlive the copies)
     if (wait) HIP_TRY(hipStreamSynchronize(st), "hipStreamSynchronize");
     return CP_OK;
@@ -736,12 +805,13 @@ cp_status enqueue_run(cp_handle h, const Staged& S, const cp_tensor* f_init, cp_
         if (s2 != CP_OK) return s2;
         s2 = copy_panels_in(h, st, &f_io[i], p.pb.U, p.pb.offU);
         if (s2 != CP_OK) return s2;
-        if (S.W > 1) {
+        if (S.W[i] > 1) {
             hipLaunchKernelGGL(zero_words, dim3(1), dim3(64), 0, st, p.pb.bar, 64);
             HIP_TRY(hipGetLastError(), "zero_words");
         }
     }
-    HIP_TRY(prepared ? launch_als_prepared(S.d_desc, S.count, S.W, st) : launch_als(S.d_desc, S.count, S.W, st),
+    HIP_TRY(prepared ? launch_als_prepared(S.d_desc, S.count, S.W[0], S.d_wg_first, S.total_wg, st)
+                     : launch_als(S.d_desc, S.count, S.W[0], S.d_wg_first, S.total_wg, st),
             "als kernel launch");
     for (int i = 0; i < S.count; ++i) {
         cp_status s2 = copy_panels_out(h, st, S.pk[i].pb.U, S.pk[i].pb.offU, &f_io[i]);
@@ -762,10 +832,10 @@ cp_status check_reports(cp_handle h, const cp_als_report* reports, int n) {
 
 cp_status run_problems(cp_handle h, int count, const HostOp* A, const HostOp* B, const cp_tensor* f_init,
                        cp_tensor* f_io, int n_steps, const cp_als_opts* o, cp_als_report* reports, double* traj) {
-    // a single problem is shared by a cluster of workgroups (grid rows split between them)
-    const int W = (count == 1) ? cluster_size(h, A[0], B[0], f_io[0]) : 1;
+    // a problem may be shared by a cluster of workgroups (grid rows split between them)
     Staged S;
-    cp_status st = stage_problems(h, count, A, B, f_init, f_io, n_steps, o, W, S);
+    cp_status st = stage_problems(h, count, A, B, f_init, f_io, n_steps, o,
+                                  choose_clusters(h, count, A, B, f_init, f_io, *o), S);
     if (st != CP_OK) return st;
     st = ensure_ws(h, S.bytes);
     if (st != CP_OK) return st;
@@ -818,6 +888,9 @@ cp_status cp_create(cp_handle* handle, void* hip_stream) {
         delete h;
         return CP_ERR_HIP;
     }
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h->device) == hipSuccess && ncu > 0)
+        h->n_cu = ncu;
     *handle = h;
     return CP_OK;
 }
@@ -1056,8 +1129,8 @@ cp_status cp_batch_plan_create(cp_handle h, int32_t count, const cp_operator* A,
     p->n_steps = n_steps;
     p->f_init.assign(f_init, f_init + count);
     p->f_io.assign(f_io, f_io + count);
-    const int W = (count == 1) ? cluster_size(h, hA[0], hB[0], f_io[0]) : 1;
-    cp_status st = stage_problems(h, count, hA.data(), hB.data(), f_init, f_io, n_steps, opts, W, p->S);
+    cp_status st = stage_problems(h, count, hA.data(), hB.data(), f_init, f_io, n_steps, opts,
+                                  choose_clusters(h, count, hA.data(), hB.data(), f_init, f_io, *opts), p->S);
     hipError_t e = hipSuccess;
     const char* what = "";
     if (st == CP_OK) {
@@ -1111,6 +1184,131 @@ cp_status cp_batch_plan_run(cp_handle h, cp_batch_plan plan, cp_als_report* repo
 cp_status cp_batch_plan_destroy(cp_batch_plan plan) {
     if (!plan) return CP_ERR_INVALID_ARG;
     plan_release(plan);
+    return CP_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------------------
+// cluster-size tuning
+// ---------------------------------------------------------------------------------------
+extern "C" {
+
+cp_status cp_tune_cluster(cp_handle h, const cp_operator* A, const cp_operator* B, const cp_tensor* f_n,
+                          const cp_tensor* guess, const cp_als_opts* opts, int32_t sweeps, int32_t* best_w,
+                          float* best_ms) {
+    if (!h) return CP_ERR_INVALID_ARG;
+    if (!best_w || sweeps < 1) return fail(h, CP_ERR_INVALID_ARG, "best_w is null or sweeps < 1");
+    HostOp hA, hB;
+    cp_status st = prepare_step(h, A, B, f_n, guess, 1, opts, hA, hB);
+    if (st != CP_OK) return st;
+    cp_als_opts o = *opts;
+    o.tol = 0.0;              // every candidate runs the same number of sweeps
+    o.max_sweeps = sweeps;
+    // a device copy of the guess, refreshed before every trial (the caller's stays untouched)
+    size_t nel = 0;
+    for (int k = 0; k < guess->d; ++k) nel += (size_t)guess->n[k] * guess->r;
+    double* scratch = nullptr;
+    HIP_TRY(hipMalloc(&scratch, nel * 8), "hipMalloc(tuning)");
+    cp_tensor g = *guess;
+    size_t off = 0;
+    for (int k = 0; k < g.d; ++k) {
+        g.U[k] = scratch + off;
+        g.ld[k] = g.n[k];
+        off += (size_t)g.n[k] * g.r;
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int best = 1;
+    float tbest = -1.0f;
+    hipError_t he = hipEventCreate(&e0);
+    if (he == hipSuccess) he = hipEventCreate(&e1);
+    const int wmax = cluster_size(h, hA, hB, *guess);
+    for (int W = 1; he == hipSuccess && st == CP_OK && W <= wmax; W *= 2) {
+        float ms = 0.0f;
+        for (int rep = 0; rep < 2 && st == CP_OK && he == hipSuccess; ++rep) {   // the first run warms up
+            for (int k = 0; k < g.d && he == hipSuccess; ++k)
+                he = hipMemcpy2DAsync(g.U[k], (size_t)g.n[k] * 8, guess->U[k], (size_t)guess->ld[k] * 8,
+                                      (size_t)g.n[k] * 8, g.r, hipMemcpyDeviceToDevice, h->stream);
+            Staged S;
+            cp_als_report rp;
+            if (he == hipSuccess) st = stage_problems(h, 1, &hA, &hB, f_n, &g, 1, &o, std::vector<int>(1, W), S);
+            if (st == CP_OK) st = ensure_ws(h, S.bytes);
+            if (st == CP_OK) st = upload_static(h, S, static_cast<char*>(h->ws), nullptr, &g, h->stream, false);
+            if (st == CP_OK && he == hipSuccess) he = hipEventRecord(e0, h->stream);
+            if (st == CP_OK && he == hipSuccess) st = enqueue_run(h, S, f_n, &g, &rp, h->stream);
+            if (st == CP_OK && he == hipSuccess) he = hipEventRecord(e1, h->stream);
+            if (st == CP_OK && he == hipSuccess) he = hipStreamSynchronize(h->stream);
+            if (st == CP_OK && he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+        }
+        if (st == CP_OK && he == hipSuccess && (tbest < 0.0f || ms < tbest)) {
+            tbest = ms;
+            best = W;
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(scratch);
+    if (st != CP_OK) return st;
+    if (he != hipSuccess) return hip_fail(h, he, "cluster tuning");
+    h->tuned[shape_key(hA, hB, *f_n, *guess, *opts)] = best;
+    *best_w = best;
+    if (best_ms) *best_ms = tbest;
+    return CP_OK;
+}
+
+cp_status cp_tune_save(cp_handle h, const char* path) {
+    if (!h) return CP_ERR_INVALID_ARG;
+    if (!path) return fail(h, CP_ERR_INVALID_ARG, "path is null");
+    FILE* f = std::fopen(path, "w");
+    if (!f) return fail(h, CP_ERR_INVALID_ARG, std::string("cannot write ") + path);
+    std::fprintf(f, "{\"cluster\": {");
+    bool first = true;
+    for (const auto& kv : h->tuned) {
+        std::fprintf(f, "%s\n  \"%s\": %d", first ? "" : ",", kv.first.c_str(), kv.second);
+        first = false;
+    }
+    std::fprintf(f, "%s}}\n", first ? "" : "\n");
+    const bool ok = std::fclose(f) == 0;
+    return ok ? CP_OK : fail(h, CP_ERR_INVALID_ARG, std::string("cannot write ") + path);
+}
+
+cp_status cp_tune_load(cp_handle h, const char* path) {
+    if (!h) return CP_ERR_INVALID_ARG;
+    if (!path) return fail(h, CP_ERR_INVALID_ARG, "path is null");
+    FILE* f = std::fopen(path, "r");
+    if (!f) return fail(h, CP_ERR_INVALID_ARG, std::string("cannot read ") + path);
+    std::string txt;
+    char buf[4096];
+    size_t got;
+    while ((got = std::fread(buf, 1, sizeof(buf), f)) > 0) txt.append(buf, got);
+    std::fclose(f);
+    // {"cluster": {"<key>": <int>, ...}}: keys hold no quotes or escapes
+    const size_t c = txt.find("\"cluster\"");
+    const size_t o = c == std::string::npos ? c : txt.find('{', c);
+    const size_t e = o == std::string::npos ? o : txt.find('}', o);
+    if (e == std::string::npos) return fail(h, CP_ERR_INVALID_ARG, std::string("no cluster table in ") + path);
+    std::map<std::string, int> add;
+    size_t pos = o + 1;
+    while (true) {
+        const size_t q0 = txt.find('"', pos);
+        if (q0 == std::string::npos || q0 > e) break;
+        const size_t q1 = txt.find('"', q0 + 1);
+        const size_t colon = q1 == std::string::npos ? q1 : txt.find(':', q1);
+        if (colon == std::string::npos || colon > e) return fail(h, CP_ERR_INVALID_ARG, "malformed cluster table");
+        char* end = nullptr;
+        const long v = std::strtol(txt.c_str() + colon + 1, &end, 10);
+        if (end == txt.c_str() + colon + 1 || v < 1 || v > 256 || (v & (v - 1)))
+            return fail(h, CP_ERR_INVALID_ARG, "bad cluster size in table");
+        add[txt.substr(q0 + 1, q1 - q0 - 1)] = (int)v;
+        pos = (size_t)(end - txt.c_str());
+    }
+    for (const auto& kv : add) h->tuned[kv.first] = kv.second;
+    return CP_OK;
+}
+
+cp_status cp_tune_clear(cp_handle h) {
+    if (!h) return CP_ERR_INVALID_ARG;
+    h->tuned.clear();
     return CP_OK;
 }
 
