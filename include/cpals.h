@@ -171,6 +171,17 @@ cp_status cp_apply_operator(cp_handle h, const cp_operator* L, const cp_tensor* 
 cp_status cp_als_step(cp_handle h, const cp_operator* A, const cp_operator* B, const cp_tensor* f_n,
                       cp_tensor* f_next, const cp_als_opts* opts, cp_als_report* report);
 
+/* The implicit step with a source term, A f_{n+1} = B f_n + c (the time step of Section 3.1
+ * with the source of the paper's forced equations, already scaled, e.g. c = dt C).  c is a
+ * CP tensor (device panels owned by the caller, same d and n_k as f_n; null: cp_als_step).
+ * The right-hand side g = B f_n + c is formed on the device as one CP tensor (the applied
+ * terms of B f_n, as cp_apply_operator, followed by c's columns) and the step
+ * A f_{n+1} = g is solved as cp_als_step does (same options, report and errors).  Requires
+ * n_terms(B) * f_n.r + c.r <= CP_MAX_RANK; the call allocates and frees that tensor. */
+cp_status cp_als_step_source(cp_handle h, const cp_operator* A, const cp_operator* B, const cp_tensor* f_n,
+                             const cp_tensor* source, cp_tensor* f_next, const cp_als_opts* opts,
+                             cp_als_report* report);
+
 /* n_steps implicit steps in one device-resident launch: f_0 = f_init, guess for step s is
  * f_{s-1} (the first step uses f_io as guess, which must have rank == cap), result f_{n_steps}
  * written to f_io.  reports: host array of n_steps.  traj (nullable): device buffer of

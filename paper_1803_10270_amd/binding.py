@@ -86,6 +86,8 @@ def lib() -> C.CDLL:
             "cp_als_run_batched": [H, C.c_int32, P(cp_operator), P(cp_operator), P(cp_tensor), P(cp_tensor),
                                    C.c_int32, P(cp_als_opts), P(cp_als_report)],
             "cp_als_default_opts": [P(cp_als_opts)],
+            "cp_als_step_source": [H, P(cp_operator), P(cp_operator), P(cp_tensor), P(cp_tensor), P(cp_tensor),
+                                   P(cp_als_opts), P(cp_als_report)],
             "cp_batch_plan_create": [H, C.c_int32, P(cp_operator), P(cp_operator), P(cp_tensor), P(cp_tensor),
                                      C.c_int32, P(cp_als_opts), P(H)],
             "cp_batch_plan_run": [H, H, P(cp_als_report)],
@@ -294,6 +296,17 @@ def cp_als_run_batched(h: Handle, As, Bs, f_inits, f_ios, n_steps: int,
     h.check(lib().cp_als_run_batched(h.h, count, A_arr, B_arr, fi, fo, n_steps, C.byref(opts), reps),
             allow_not_converged=True)
     return [[reps[i * n_steps + s].as_dict() for s in range(n_steps)] for i in range(count)]
+
+
+def cp_als_step_source(h: Handle, A, B, f_n, source, f_next, opts: Optional[cp_als_opts] = None) -> dict:
+    """One implicit step A f_{n+1} = B f_n + source; f_next is in/out (guess in, solution out)."""
+    opts = default_opts() if opts is None else opts
+    Ad, Bd = OperatorDesc(A), OperatorDesc(B)
+    fd, sd, gd = tensor_desc(f_n), tensor_desc(source), tensor_desc(f_next)
+    rep = cp_als_report()
+    h.check(lib().cp_als_step_source(h.h, C.byref(Ad.desc), C.byref(Bd.desc), C.byref(fd), C.byref(sd), C.byref(gd),
+                                     C.byref(opts), C.byref(rep)), allow_not_converged=True)
+    return rep.as_dict()
 
 
 def cp_tune_cluster(h: Handle, A, B, f_n, guess, opts: Optional[cp_als_opts] = None, sweeps: int = 3):

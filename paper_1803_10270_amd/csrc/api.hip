@@ -1065,6 +1065,71 @@ cp_status cp_truncate(cp_handle h, const cp_tensor* g, cp_tensor* f, const cp_al
     return cp_als_run(h, &I, &I, g, f, 1, opts, report, nullptr);
 }
 
+cp_status cp_als_step_source(cp_handle h, const cp_operator* A, const cp_operator* B, const cp_tensor* f_n,
+                             const cp_tensor* source, cp_tensor* f_next, const cp_als_opts* opts,
+                             cp_als_report* report) {
+    if (!h) return CP_ERR_INVALID_ARG;
+    if (!source) return cp_als_step(h, A, B, f_n, f_next, opts, report);
+    cp_status st = check_tensor(h, f_n, "f_n", CP_MAX_N);
+    if (st != CP_OK) return st;
+    st = check_tensor(h, source, "source", CP_MAX_N);
+    if (st != CP_OK) return st;
+    if (!B) return fail(h, CP_ERR_INVALID_ARG, "B is null");
+    if (source->d != f_n->d) return fail(h, CP_ERR_SHAPE, "source and f_n differ in d");
+    for (int k = 0; k < f_n->d; ++k)
+        if (source->n[k] != f_n->n[k]) return fail(h, CP_ERR_SHAPE, "source and f_n differ in n");
+    const int64_t rb = (int64_t)B->n_terms * f_n->r;
+    const int64_t rr = rb + source->r;
+    if (B->n_terms < 1 || rr > CP_MAX_RANK)
+        return fail(h, CP_ERR_SHAPE, "n_terms(B) * rank(f_n) + rank(source) exceeds CP_MAX_RANK");
+    // right-hand side tensor g = B f_n + source as one CP tensor: the applied terms of B f_n
+    // (coefficients in dimension 0) followed by the source's columns
+    size_t nel = 0;
+    for (int k = 0; k < f_n->d; ++k) nel += (size_t)f_n->n[k] * rr;
+    double* gbuf = nullptr;
+    HIP_TRY(hipMalloc(&gbuf, nel * 8), "hipMalloc(rhs tensor)");
+    cp_tensor g, gb;
+    std::memset(&g, 0, sizeof(g));
+    g.d = f_n->d;
+    g.r = (int32_t)rr;
+    size_t off = 0;
+    for (int k = 0; k < g.d; ++k) {
+        g.n[k] = f_n->n[k];
+        g.ld[k] = f_n->n[k];
+        g.U[k] = gbuf + off;
+        off += (size_t)f_n->n[k] * rr;
+    }
+    gb = g;
+    gb.r = (int32_t)rb;
+    st = cp_apply_operator(h, B, f_n, &gb);
+    hipError_t e = hipSuccess;
+    for (int k = 0; st == CP_OK && e == hipSuccess && k < g.d; ++k)
+        e = hipMemcpy2DAsync(g.U[k] + (size_t)rb * g.ld[k], (size_t)g.ld[k] * 8, source->U[k], (size_t)source->ld[k] * 8,
+                             (size_t)g.n[k] * 8, source->r, hipMemcpyDeviceToDevice, h->stream);
+    if (st == CP_OK && e != hipSuccess) st = hip_fail(h, e, "hipMemcpy2DAsync(source)");
+    if (st == CP_OK || st == CP_ERR_NOT_CONVERGED) {
+        // A f_{n+1} = g with the identity on the right
+        cp_op1d ident[CP_MAX_DIMS];
+        double one = 1.0;
+        int32_t idx[CP_MAX_DIMS] = {0};
+        cp_operator I;
+        std::memset(&I, 0, sizeof(I));
+        I.d = g.d;
+        I.n_terms = 1;
+        I.coef = &one;
+        I.op_index = idx;
+        for (int k = 0; k < g.d; ++k) {
+            ident[k] = cp_op1d{CP_OP_IDENTITY, g.n[k], 0, nullptr};
+            I.n_ops[k] = 1;
+            I.ops[k] = &ident[k];
+        }
+        st = cp_als_run(h, A, &I, &g, f_next, 1, opts, report, nullptr);
+    }
+    (void)hipStreamSynchronize(h->stream);
+    (void)hipFree(gbuf);
+    return st;
+}
+
 cp_status cp_als_run_batched(cp_handle h, int32_t count, const cp_operator* A, const cp_operator* B,
                              const cp_tensor* f_init, cp_tensor* f_io, int32_t n_steps, const cp_als_opts* opts,
                              cp_als_report* reports) {

@@ -153,6 +153,41 @@ def test_full_size_variable_advection(handle, sweeps):
     assert abs(rep["eps_conv"] - ro["eps_conv"]) <= 1e-6 * ro["eps_conv"]
 
 
+def test_step_with_source_matches_oracle(handle):
+    """A f_{n+1} = B f_n + c (Crank-Nicolson advection, a rank-2 source): cp_als_step_source
+    against the oracle's step with the source term, fixed sweeps."""
+    log("step with source")
+    p = W.advection_cn_constant(seed=3, d=4, n=32, cap=6)
+    rng = np.random.default_rng(11)
+    src = [1e-2 * rng.standard_normal((32, 2)) for _ in range(4)]
+    g = dev(p.guess)
+    rep = B.cp_als_step_source(handle, p.A, p.B, dev(p.f0), dev(src), g, B.default_opts(tol=0.0, max_sweeps=4))
+    Uo, ro = O.als_step(p.A, p.B, p.f0, p.guess, tol=0.0, max_sweeps=4, source=src)
+    dist = tensor_distance(host(g), Uo)
+    log("distance to oracle %.3e" % dist, rep)
+    assert rep["sweeps"] == ro["sweeps"] == 4
+    assert dist <= TOL
+
+
+def test_step_with_source_identity_is_sum(handle):
+    """With A = B = I the step with a source is f_n + c exactly (closed form), reached by ALS
+    from a guess of rank rank(f_n) + rank(c).  The regularisation shift biases the result by
+    O(eps_reg), so it is set far below the bar."""
+    log("source identity")
+    rng = np.random.default_rng(12)
+    dims = [24, 16, 20]
+    fn = W.random_factors(rng, dims, 2)
+    c = W.random_factors(rng, dims, 2)
+    I = W.SepOperator(np.array([1.0]), np.zeros((1, 3), dtype=np.int32), [[W.op_identity(n)] for n in dims])
+    guess = [np.concatenate([a, b], axis=1) + 1e-3 * rng.standard_normal((a.shape[0], 4)) for a, b in zip(fn, c)]
+    g = dev(guess)
+    rep = B.cp_als_step_source(handle, I, I, dev(fn), dev(c), g, B.default_opts(tol=1e-12, max_sweeps=200, eps_reg=1e-14))
+    exact = [np.concatenate([a, b], axis=1) for a, b in zip(fn, c)]
+    dist = tensor_distance(host(g), exact)
+    log("distance to f_n + c %.3e" % dist, rep)
+    assert dist <= 1e-10
+
+
 def test_truncate(handle):
     log("truncate")
     rng = np.random.default_rng(12)
