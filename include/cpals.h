@@ -182,6 +182,28 @@ cp_status cp_als_step_source(cp_handle h, const cp_operator* A, const cp_operato
                              const cp_tensor* source, cp_tensor* f_next, const cp_als_opts* opts,
                              cp_als_report* report);
 
+/* Relative residual of the implicit step, rho = ||A f - B f_n|| / ||B f_n|| (the residual
+ * of Section 3.2 that drives rank control), from three scalar products of the applied CP
+ * tensors on the device: <Af, Af> - 2 <Af, Bf_n> + <Bf_n, Bf_n>.  The difference cancels, so
+ * rho below ~1e-7 is resolved only to that level.  Written to *rel_residual (host); the call
+ * allocates and frees the applied tensors and synchronises the stream. */
+cp_status cp_residual(cp_handle h, const cp_operator* A, const cp_operator* B, const cp_tensor* f,
+                      const cp_tensor* f_n, double* rel_residual);
+
+/* The implicit step with adaptive rank (Section 3.2: the separation rank grows until the
+ * residual meets the tolerance).  f_next has capacity f_next->r = cap columns; its first
+ * r_start columns are the initial guess.  The step is solved at rank r = r_start; while
+ * rho > tau and r < cap, one term is added (seeded values in every dimension but the first,
+ * zero there, so the represented tensor is unchanged until the first dimension's next
+ * update sizes it) and the step is solved again from the current factors.  Terms of weight
+ * prod_k ||U_k[:, l]|| below 1e-14 of the largest are then dropped (the kept columns move
+ * to the front).  Output: the factors in the first *final_rank columns, *rel_residual the
+ * last rho, report: the last solve's report with sweeps and pcg_iters summed over all
+ * solves.  Errors as cp_als_step; CP_ERR_INVALID_ARG unless 1 <= r_start <= cap, tau >= 0. */
+cp_status cp_als_step_adaptive(cp_handle h, const cp_operator* A, const cp_operator* B, const cp_tensor* f_n,
+                               cp_tensor* f_next, int32_t r_start, double tau, const cp_als_opts* opts,
+                               cp_als_report* report, int32_t* final_rank, double* rel_residual);
+
 /* n_steps implicit steps in one device-resident launch: f_0 = f_init, guess for step s is
  * f_{s-1} (the first step uses f_io as guess, which must have rank == cap), result f_{n_steps}
  * written to f_io.  reports: host array of n_steps.  traj (nullable): device buffer of

@@ -86,6 +86,9 @@ def lib() -> C.CDLL:
             "cp_als_run_batched": [H, C.c_int32, P(cp_operator), P(cp_operator), P(cp_tensor), P(cp_tensor),
                                    C.c_int32, P(cp_als_opts), P(cp_als_report)],
             "cp_als_default_opts": [P(cp_als_opts)],
+            "cp_residual": [H, P(cp_operator), P(cp_operator), P(cp_tensor), P(cp_tensor), P(C.c_double)],
+            "cp_als_step_adaptive": [H, P(cp_operator), P(cp_operator), P(cp_tensor), P(cp_tensor), C.c_int32,
+                                     C.c_double, P(cp_als_opts), P(cp_als_report), P(C.c_int32), P(C.c_double)],
             "cp_als_step_source": [H, P(cp_operator), P(cp_operator), P(cp_tensor), P(cp_tensor), P(cp_tensor),
                                    P(cp_als_opts), P(cp_als_report)],
             "cp_batch_plan_create": [H, C.c_int32, P(cp_operator), P(cp_operator), P(cp_tensor), P(cp_tensor),
@@ -307,6 +310,33 @@ def cp_als_step_source(h: Handle, A, B, f_n, source, f_next, opts: Optional[cp_a
     h.check(lib().cp_als_step_source(h.h, C.byref(Ad.desc), C.byref(Bd.desc), C.byref(fd), C.byref(sd), C.byref(gd),
                                      C.byref(opts), C.byref(rep)), allow_not_converged=True)
     return rep.as_dict()
+
+
+def cp_residual(h: Handle, A, B, f, f_n) -> float:
+    """||A f - B f_n|| / ||B f_n|| on the device."""
+    Ad, Bd = OperatorDesc(A), OperatorDesc(B)
+    fd, nd = tensor_desc(f), tensor_desc(f_n)
+    out = C.c_double(0.0)
+    h.check(lib().cp_residual(h.h, C.byref(Ad.desc), C.byref(Bd.desc), C.byref(fd), C.byref(nd), C.byref(out)))
+    return float(out.value)
+
+
+def cp_als_step_adaptive(h: Handle, A, B, f_n, f_next, r_start: int, tau: float,
+                         opts: Optional[cp_als_opts] = None) -> dict:
+    """Implicit step growing the rank from r_start (f_next holds cap = f_next rank columns;
+    its first r_start are the guess) until the relative residual is <= tau.  Returns the
+    report with 'final_rank' and 'rel_residual'."""
+    opts = default_opts() if opts is None else opts
+    Ad, Bd = OperatorDesc(A), OperatorDesc(B)
+    fd, gd = tensor_desc(f_n), tensor_desc(f_next)
+    rep = cp_als_report()
+    fr, rho = C.c_int32(0), C.c_double(0.0)
+    h.check(lib().cp_als_step_adaptive(h.h, C.byref(Ad.desc), C.byref(Bd.desc), C.byref(fd), C.byref(gd), r_start, tau,
+                                       C.byref(opts), C.byref(rep), C.byref(fr), C.byref(rho)),
+            allow_not_converged=True)
+    out = rep.as_dict()
+    out.update(final_rank=int(fr.value), rel_residual=float(rho.value))
+    return out
 
 
 def cp_tune_cluster(h: Handle, A, B, f_n, guess, opts: Optional[cp_als_opts] = None, sweeps: int = 3):

@@ -1130,6 +1130,135 @@ cp_status cp_als_step_source(cp_handle h, const cp_operator* A, const cp_operato
     return st;
 }
 
+cp_status cp_residual(cp_handle h, const cp_operator* A, const cp_operator* B, const cp_tensor* f,
+                      const cp_tensor* f_n, double* rel_residual) {
+    if (!h) return CP_ERR_INVALID_ARG;
+    if (!A || !B || !f || !f_n || !rel_residual) return fail(h, CP_ERR_INVALID_ARG, "null argument");
+    cp_status st = check_tensor(h, f, "f", CP_MAX_N);
+    if (st != CP_OK) return st;
+    st = check_tensor(h, f_n, "f_n", CP_MAX_N);
+    if (st != CP_OK) return st;
+    if (f->d != f_n->d || A->n_terms < 1 || B->n_terms < 1) return fail(h, CP_ERR_SHAPE, "f and f_n differ in d");
+    // A f and B f_n as CP tensors in one allocation, then <Af,Af> - 2 <Af,Bf_n> + <Bf_n,Bf_n>
+    const int ra = A->n_terms * f->r, rb = B->n_terms * f_n->r;
+    size_t nel = 0;
+    for (int k = 0; k < f->d; ++k) nel += (size_t)f->n[k] * (ra + rb);
+    double* buf = nullptr;
+    HIP_TRY(hipMalloc(&buf, nel * 8 + 3 * 8), "hipMalloc(residual)");
+    cp_tensor af, bg;
+    std::memset(&af, 0, sizeof(af));
+    af.d = f->d;
+    af.r = ra;
+    bg = af;
+    bg.r = rb;
+    size_t off = 0;
+    for (int k = 0; k < f->d; ++k) {
+        af.n[k] = bg.n[k] = f->n[k];
+        af.ld[k] = bg.ld[k] = f->n[k];
+        af.U[k] = buf + off;
+        off += (size_t)f->n[k] * ra;
+        bg.U[k] = buf + off;
+        off += (size_t)f->n[k] * rb;
+    }
+    double* dots = buf + off;
+    st = cp_apply_operator(h, A, f, &af);
+    if (st == CP_OK) st = cp_apply_operator(h, B, f_n, &bg);
+    if (st == CP_OK) st = cp_inner(h, &af, &af, dots);
+    if (st == CP_OK) st = cp_inner(h, &af, &bg, dots + 1);
+    if (st == CP_OK) st = cp_inner(h, &bg, &bg, dots + 2);
+    double v[3] = {0.0, 0.0, 0.0};
+    if (st == CP_OK) {
+        hipError_t e = hipMemcpyAsync(v, dots, sizeof(v), hipMemcpyDeviceToHost, h->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+        if (e != hipSuccess) st = hip_fail(h, e, "residual copy");
+    }
+    (void)hipStreamSynchronize(h->stream);
+    (void)hipFree(buf);
+    if (st != CP_OK) return st;
+    const double num = std::max(v[0] - 2.0 * v[1] + v[2], 0.0);
+    *rel_residual = v[2] > 0.0 ? std::sqrt(num / v[2]) : std::sqrt(num);
+    return CP_OK;
+}
+
+cp_status cp_als_step_adaptive(cp_handle h, const cp_operator* A, const cp_operator* B, const cp_tensor* f_n,
+                               cp_tensor* f_next, int32_t r_start, double tau, const cp_als_opts* opts,
+                               cp_als_report* report, int32_t* final_rank, double* rel_residual) {
+    if (!h) return CP_ERR_INVALID_ARG;
+    if (!f_next || !report || !final_rank || !rel_residual) return fail(h, CP_ERR_INVALID_ARG, "null argument");
+    const int cap = f_next->r;
+    if (r_start < 1 || r_start > cap || !(tau >= 0.0)) return fail(h, CP_ERR_INVALID_ARG, "need 1 <= r_start <= cap, tau >= 0");
+    cp_status st = check_tensor(h, f_next, "f_next", CP_MAX_N);
+    if (st != CP_OK) return st;
+    cp_tensor f = *f_next;
+    int r = r_start;
+    int sweeps = 0, pcg = 0;
+    double rho = 0.0;
+    uint32_t state = 0x9e3779b9u;
+    for (;;) {
+        f.r = r;
+        cp_als_report rp;
+        st = cp_als_step(h, A, B, f_n, &f, opts, &rp);
+        if (st != CP_OK && st != CP_ERR_NOT_CONVERGED) return st;
+        sweeps += rp.sweeps;
+        pcg += rp.pcg_iters;
+        *report = rp;
+        const cp_status conv = st;
+        st = cp_residual(h, A, B, &f, f_n, &rho);
+        if (st != CP_OK) return st;
+        st = conv;
+        if (rho <= tau || r == cap) break;
+        // one more term: seeded values in every dimension but the first, zero there (it
+        // adds nothing until the next update of the first dimension sizes it)
+        for (int k = 0; k < f.d; ++k) {
+            std::vector<double> col(f.n[k], 0.0);
+            if (k > 0)
+                for (double& x : col) {
+                    state ^= state << 13;
+                    state ^= state >> 17;
+                    state ^= state << 5;
+                    x = ((double)state / 4294967296.0) - 0.5;
+                }
+            HIP_TRY(hipMemcpyAsync(f.U[k] + (size_t)r * f.ld[k], col.data(), col.size() * 8, hipMemcpyHostToDevice,
+                                   h->stream),
+                    "hipMemcpyAsync(new column)");
+            HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+        }
+        ++r;
+    }
+    // drop terms whose weight prod_k ||U_k[:, l]|| is below 1e-14 of the largest (their
+    // columns are moved out; the kept columns keep their order)
+    std::vector<double> w(r, 1.0);
+    for (int k = 0; k < f.d; ++k) {
+        std::vector<double> panel((size_t)f.n[k] * r);
+        HIP_TRY(hipMemcpy2DAsync(panel.data(), (size_t)f.n[k] * 8, f.U[k], (size_t)f.ld[k] * 8, (size_t)f.n[k] * 8, r,
+                                 hipMemcpyDeviceToHost, h->stream),
+                "hipMemcpy2DAsync(weights)");
+        HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+        for (int l = 0; l < r; ++l) {
+            double s2 = 0.0;
+            for (int i = 0; i < f.n[k]; ++i) s2 += panel[(size_t)l * f.n[k] + i] * panel[(size_t)l * f.n[k] + i];
+            w[l] *= std::sqrt(s2);
+        }
+    }
+    const double wmax = *std::max_element(w.begin(), w.end());
+    int kept = 0;
+    for (int l = 0; l < r; ++l) {
+        if (!(w[l] >= 1e-14 * wmax)) continue;
+        if (kept != l)
+            for (int k = 0; k < f.d; ++k)
+                HIP_TRY(hipMemcpyAsync(f.U[k] + (size_t)kept * f.ld[k], f.U[k] + (size_t)l * f.ld[k], (size_t)f.n[k] * 8,
+                                       hipMemcpyDeviceToDevice, h->stream),
+                        "hipMemcpyAsync(compact)");
+        ++kept;
+    }
+    HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+    report->sweeps = sweeps;
+    report->pcg_iters = pcg;
+    *final_rank = std::max(kept, 1);
+    *rel_residual = rho;
+    return st;
+}
+
 cp_status cp_als_run_batched(cp_handle h, int32_t count, const cp_operator* A, const cp_operator* B,
                              const cp_tensor* f_init, cp_tensor* f_io, int32_t n_steps, const cp_als_opts* opts,
                              cp_als_report* reports) {
