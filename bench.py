@@ -265,6 +265,93 @@ def bench_batched(args):
     return out
 
 
+def bench_mixed(args, log):
+    """Mixed-precision form on the linearised kinetic workload (d = 6, n = 128, rank 64,
+    Crank-Nicolson, tol 1e-8): the same steps in FP64 and mixed precision from the same
+    state, their rates and the distance of the two results."""
+    import torch
+    from paper_1803_10270_amd import binding as B
+    from paper_1803_10270_amd import workloads as W
+    h = B.Handle()
+    p = W.kinetic_cn(seed=0, n=128, cap=64)
+    K = 2
+    res = {}
+    for name, prec in (("fp64", B.PREC_FP64), ("mixed", B.PREC_MIXED)):
+        V, U = B.to_device(p.f0), B.to_device(p.guess)
+        opts = B.default_opts(tol=p.tol, max_sweeps=args.max_sweeps, precision=prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps = B.cp_als_run(h, p.A, p.B, V, U, K, opts)
+        torch.cuda.synchronize()
+        res[name] = (time.perf_counter() - t0, reps, U)
+    # ||x - y|| / ||y|| from device scalar products (resolves distances above ~1e-7)
+    dots = torch.zeros(3, dtype=torch.float64, device="cuda")
+    x, y = res["mixed"][2], res["fp64"][2]
+    B.cp_inner(h, x, x, dots[0:1])
+    B.cp_inner(h, x, y, dots[1:2])
+    B.cp_inner(h, y, y, dots[2:3])
+    xx, xy, yy = dots.cpu().tolist()
+    dist = float(np.sqrt(max(xx - 2 * xy + yy, 0.0) / yy))
+    h.close()
+    log("mixed: kinetic d=6 n=128 r=64, %d steps: fp64 %.2f s, mixed %.2f s, distance %.2e" % (
+        K, res["fp64"][0], res["mixed"][0], dist))
+    return {"form": "mixed", "workload": "kinetic_cn d=6 n=128 r=64 (5 Kronecker terms, CN, dt=0.01, tol=1e-8), "
+                                         "%d steps" % K,
+            "fp64_steps_per_s": K / res["fp64"][0], "mixed_steps_per_s": K / res["mixed"][0],
+            "speedup": res["fp64"][0] / res["mixed"][0],
+            "fp64_sweeps": [r["sweeps"] for r in res["fp64"][1]], "mixed_sweeps": [r["sweeps"] for r in res["mixed"][1]],
+            "rel_distance_to_fp64": dist}
+
+
+def bench_streaming(log):
+    """The HBM-bound kernels on gigabyte inputs: cp_inner (d = 2, n = 2^22, ranks 16 and 16)
+    and cp_apply_operator (d = 2, n = 2^21, rank 16, 3 terms), achieved GB/s of their
+    algorithmic bytes against the 8 TB/s HBM peak (HIP events, median of 5 calls)."""
+    import torch
+    from paper_1803_10270_amd import binding as B
+    from paper_1803_10270_amd import workloads as W
+    h = B.Handle()
+    out = {}
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+
+    def timed(fn, reps=5):
+        fn()
+        ts = []
+        for _ in range(reps):
+            a, b = ev(), ev()
+            a.record()
+            fn()
+            b.record()
+            torch.cuda.synchronize()
+            ts.append(a.elapsed_time(b) * 1e-3)
+        return float(np.median(ts))
+
+    n, r = 1 << 22, 16
+    g = torch.Generator(device="cuda").manual_seed(0)
+    x = [torch.randn((r, n), dtype=torch.float64, device="cuda", generator=g) for _ in range(2)]
+    y = [torch.randn((r, n), dtype=torch.float64, device="cuda", generator=g) for _ in range(2)]
+    o = torch.zeros(1, dtype=torch.float64, device="cuda")
+    t = timed(lambda: B.cp_inner(h, x, y, o))
+    nbytes = 2 * 8 * n * (r + r)
+    out["cp_inner"] = {"shape": "d=2 n=2^22 r=16 x 16", "bytes": nbytes, "seconds": t, "GB_per_s": nbytes / t / 1e9,
+                       "frac_of_hbm_peak": nbytes / t / 1e9 / HBM_PEAK_GBS}
+    del x, y
+    n2 = 1 << 21
+    L = W.SepOperator(np.array([1.0, 0.5, 0.25]), np.array([[0, 0], [1, 0], [0, 2]], dtype=np.int32),
+                      [[W.op_identity(n2), W.op_central_diff(n2), W.op_diag(np.linspace(-1, 1, n2))]] * 2)
+    xa = [torch.randn((r, n2), dtype=torch.float64, device="cuda", generator=g) for _ in range(2)]
+    ya = [torch.empty((3 * r, n2), dtype=torch.float64, device="cuda") for _ in range(2)]
+    t = timed(lambda: B.cp_apply_operator(h, L, xa, ya))
+    nbytes = 2 * 8 * n2 * r * (1 + 3)
+    out["cp_apply_operator"] = {"shape": "d=2 n=2^21 r=16, 3 terms", "bytes": nbytes, "seconds": t,
+                                "GB_per_s": nbytes / t / 1e9, "frac_of_hbm_peak": nbytes / t / 1e9 / HBM_PEAK_GBS}
+    del xa, ya
+    h.close()
+    log("streaming: cp_inner %.0f GB/s, cp_apply_operator %.0f GB/s" % (out["cp_inner"]["GB_per_s"],
+                                                                     out["cp_apply_operator"]["GB_per_s"]))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -368,7 +455,15 @@ def main():
             forms["batched"] = bench_batched(args_b)
         except Exception as e:
             forms["batched"] = {"error": repr(e)}
+        try:
+            forms["mixed"] = bench_mixed(args, log)
+        except Exception as e:
+            forms["mixed"] = {"error": repr(e)}
         out["forms"] = forms
+        try:
+            out["streaming"] = bench_streaming(log)
+        except Exception as e:
+            out["streaming"] = {"error": repr(e)}
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(p, float(np.mean(sweeps)))
     print(json.dumps(out), flush=True)

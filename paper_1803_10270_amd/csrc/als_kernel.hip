@@ -1445,6 +1445,8 @@ __global__ void __launch_bounds__(WG) als_persistent(const Problem* __restrict__
     bool lowp = false;
     double lam = 0.0, bz = 0.0, stop = 0.0, rz = 0.0, pw = 0.0, alpha = 0.0, beta = 0.0;
     double dmax2 = 0.0, eps = 0.0, fnorm = 0.0;
+    double eps_low_min = 1e300;   // smallest increment of the FP32 sweeps of this step
+    int low_stall = 0;            // FP32 sweeps since that minimum last improved
     int psel = 0;   // which of the two search-direction buffers holds p
 
     while (op != OP_DONE) {
@@ -1482,6 +1484,8 @@ __global__ void __launch_bounds__(WG) als_persistent(const Problem* __restrict__
             }
             cluster_sync();
             lowp = mixed && max_sweeps > 1;
+            eps_low_min = 1e300;
+            low_stall = 0;
             pcg_iters = 0;
             flags = CP_FLAG_NOT_CONVERGED;
             eps = fnorm = dmax2 = 0.0;
@@ -1673,7 +1677,15 @@ __global__ void __launch_bounds__(WG) als_persistent(const Problem* __restrict__
                 flags |= CP_FLAG_NONFINITE;
                 done = true;
             } else if (was_low) {
-                if (eps <= tol_low || sw + 1 >= max_sweeps) {
+                // the FP32 sweeps stall at their rounding floor: no new minimum (by 10 %) of
+                // the increment for three sweeps ends them as well
+                if (eps < 0.9 * eps_low_min) {
+                    eps_low_min = eps;
+                    low_stall = 0;
+                } else {
+                    ++low_stall;
+                }
+                if (eps <= tol_low || low_stall >= 3 || sw + 1 >= max_sweeps) {
                     // switch to FP64: recompute every Gram in FP64, then the refinement sweep
                     lowp = false;
                     refresh_all = true;
