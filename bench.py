@@ -306,7 +306,10 @@ def bench_mixed(args, log):
 def bench_streaming(log):
     """The HBM-bound kernels on gigabyte inputs: cp_inner (d = 2, n = 2^22, ranks 16 and 16)
     and cp_apply_operator (d = 2, n = 2^21, rank 16, 3 terms), achieved GB/s of their
-    algorithmic bytes against the 8 TB/s HBM peak (HIP events, median of 5 calls)."""
+    algorithmic bytes against the 8 TB/s HBM peak (HIP events, median of 5 calls).  The
+    applied operator's terms are scaled identities: banded and diagonal 1-D operators carry
+    per-row coefficients that every call copies from host memory (the API's contract), and
+    that upload, not the kernel, would be timed."""
     import torch
     from paper_1803_10270_amd import binding as B
     from paper_1803_10270_amd import workloads as W
@@ -337,13 +340,12 @@ def bench_streaming(log):
                        "frac_of_hbm_peak": nbytes / t / 1e9 / HBM_PEAK_GBS}
     del x, y
     n2 = 1 << 21
-    L = W.SepOperator(np.array([1.0, 0.5, 0.25]), np.array([[0, 0], [1, 0], [0, 2]], dtype=np.int32),
-                      [[W.op_identity(n2), W.op_central_diff(n2), W.op_diag(np.linspace(-1, 1, n2))]] * 2)
+    L = W.SepOperator(np.array([1.0, 0.5, 0.25]), np.zeros((3, 2), dtype=np.int32), [[W.op_identity(n2)]] * 2)
     xa = [torch.randn((r, n2), dtype=torch.float64, device="cuda", generator=g) for _ in range(2)]
     ya = [torch.empty((3 * r, n2), dtype=torch.float64, device="cuda") for _ in range(2)]
     t = timed(lambda: B.cp_apply_operator(h, L, xa, ya))
     nbytes = 2 * 8 * n2 * r * (1 + 3)
-    out["cp_apply_operator"] = {"shape": "d=2 n=2^21 r=16, 3 terms", "bytes": nbytes, "seconds": t,
+    out["cp_apply_operator"] = {"shape": "d=2 n=2^21 r=16, 3 scaled-identity terms", "bytes": nbytes, "seconds": t,
                                 "GB_per_s": nbytes / t / 1e9, "frac_of_hbm_peak": nbytes / t / 1e9 / HBM_PEAK_GBS}
     del xa, ya
     h.close()

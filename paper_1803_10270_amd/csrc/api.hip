@@ -16,7 +16,7 @@
 
 namespace cpals {
 // defined in basic_kernels.hip
-int gram_chunks(const int32_t* n, int d, int32_t* chunk0);
+int gram_chunks(const int32_t* n, int d, int32_t* chunk0, int32_t* chunk_rows);
 hipError_t launch_inner(const GramJob& job, double* partial, double* out, bool sqrt_out, hipStream_t st);
 hipError_t launch_apply(const ApplyJob& job, int max_n, hipStream_t st);
 // defined in als_kernel.hip
@@ -952,8 +952,8 @@ static cp_status inner_impl(cp_handle h, const cp_tensor* x, const cp_tensor* y,
         job.ldy[k] = y->ld[k];
         job.n[k] = x->n[k];
     }
-    const int nch = gram_chunks(job.n, job.d, job.chunk0);
-    st = ensure_ws(h, (size_t)nch * x->r * y->r * 8 + 256);
+    const int nch = gram_chunks(job.n, job.d, job.chunk0, job.chunk_rows);
+    st = ensure_ws(h, (size_t)(nch + x->d) * x->r * y->r * 8 + 256);   // chunk partials, then the d Grams
     if (st != CP_OK) return st;
     HIP_TRY(launch_inner(job, static_cast<double*>(h->ws), out_dev, sq, h->stream), "inner launch");
     return CP_OK;

@@ -7,46 +7,65 @@
 namespace cpals {
 
 constexpr int GT = 256;       // threads per workgroup for the streaming kernels
-constexpr int GROWS = 256;    // rows per workgroup chunk of a Gram partial
-
+constexpr int GTR = 64;       // rows per staged tile of a Gram partial
+constexpr int MAX_CHUNKS = 2048;   // row chunks over all dimensions (bounds the final sum)
 
 // One workgroup per (dimension, row chunk): partial[chunk][l + l' * rx] = sum_rows X[i,l] Y[i,l'].
-// Rows are staged through LDS (coalesced HBM reads), each thread owns a few (l, l') entries.
+// Tiles of 64 rows of both panels are staged through LDS (dynamic size 64 (rx + ry + 2)
+// doubles; each column's 64 rows are one contiguous 512-byte read); the next tile's loads
+// are issued into registers before the current tile is reduced, and each thread owns up to
+// 16 (l, l') entries.
 __global__ void __launch_bounds__(GT) gram_partials(GramJob job, double* __restrict__ partial) {
-    constexpr int TR = 32;
-    __shared__ double xs[TR][CP_MAX_RANK + 1];
-    __shared__ double ys[TR][CP_MAX_RANK + 1];
+    extern __shared__ double gsm[];
     const int c = blockIdx.x;
     int k = 0;
     while (k + 1 < job.d && c >= job.chunk0[k + 1]) ++k;
-    const int row0 = (c - job.chunk0[k]) * GROWS;
+    const int rows = job.chunk_rows[k];
+    const int row0 = (c - job.chunk0[k]) * rows;
     const int n = job.n[k], rx = job.rx, ry = job.ry;
-    const int row1 = min(n, row0 + GROWS);
+    const int row1 = min(n, row0 + rows);
     const double* X = job.X[k];
     const double* Y = job.Y[k];
+    const int64_t ldx = job.ldx[k], ldy = job.ldy[k];
+    const int sx = rx + 1, sy = ry + 1;
+    double* xs = gsm;
+    double* ys = gsm + GTR * sx;
     const int ne = rx * ry;
+    constexpr int U = (GTR * CP_MAX_RANK + GT - 1) / GT;   // 16 staged elements per thread and panel
+    double vx[U], vy[U];
+    auto load = [&](int rb) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int t = threadIdx.x + u * GT;
+            const int i = t & (GTR - 1), l = t / GTR;
+            const int row = rb + i;
+            vx[u] = (l < rx && row < row1) ? X[row + (int64_t)l * ldx] : 0.0;
+            vy[u] = (l < ry && row < row1) ? Y[row + (int64_t)l * ldy] : 0.0;
+        }
+    };
     double acc[16];
 #pragma unroll
     for (int e = 0; e < 16; ++e) acc[e] = 0.0;
-    for (int rb = row0; rb < row1; rb += TR) {
-        const int nrow = min(TR, row1 - rb);
+    if (row0 < row1) load(row0);
+    for (int rb = row0; rb < row1; rb += GTR) {
+        const int nrow = min(GTR, row1 - rb);
         __syncthreads();
-        for (int t = threadIdx.x; t < TR * rx; t += GT) {
-            const int i = t % TR, l = t / TR;
-            xs[i][l] = (i < nrow) ? X[(rb + i) + (int64_t)l * job.ldx[k]] : 0.0;
-        }
-        for (int t = threadIdx.x; t < TR * ry; t += GT) {
-            const int i = t % TR, l = t / TR;
-            ys[i][l] = (i < nrow) ? Y[(rb + i) + (int64_t)l * job.ldy[k]] : 0.0;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int t = threadIdx.x + u * GT;
+            const int i = t & (GTR - 1), l = t / GTR;
+            if (l < rx) xs[i * sx + l] = vx[u];
+            if (l < ry) ys[i * sy + l] = vy[u];
         }
         __syncthreads();
+        if (rb + GTR < row1) load(rb + GTR);
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
             const int t = threadIdx.x + e * GT;
             if (t < ne) {
                 const int l = t % rx, lp = t / rx;
                 double a = acc[e];
-                for (int i = 0; i < nrow; ++i) a = fma(xs[i][l], ys[i][lp], a);
+                for (int i = 0; i < nrow; ++i) a = fma(xs[i * sx + l], ys[i * sy + lp], a);
                 acc[e] = a;
             }
         }
@@ -58,19 +77,36 @@ __global__ void __launch_bounds__(GT) gram_partials(GramJob job, double* __restr
     }
 }
 
-// One workgroup: Gram_k = sum of chunk partials (fixed order), out = sum_{l,l'} prod_k Gram_k.
-__global__ void __launch_bounds__(GT) gram_finish(GramJob job, const double* __restrict__ partial, double* out,
+// Gram_k[e] = sum over the dimension's chunk partials, one workgroup per entry e and
+// dimension k (each thread adds a strided share, then a fixed reduction tree), written after
+// the partials at gram[k * ne + e].
+__global__ void __launch_bounds__(GT) gram_reduce(GramJob job, const double* __restrict__ partial,
+                                                  double* __restrict__ gram) {
+    __shared__ double red[GT / 64];
+    const int ne = job.rx * job.ry;
+    const int e = blockIdx.x, k = blockIdx.y;
+    double g = 0.0;
+    for (int c = job.chunk0[k] + threadIdx.x; c < job.chunk0[k + 1]; c += GT) g += partial[(int64_t)c * ne + e];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) g += __shfl_down(g, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = g;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s2 = 0.0;
+        for (int w = 0; w < GT / 64; ++w) s2 += red[w];
+        gram[(int64_t)k * ne + e] = s2;
+    }
+}
+
+// One workgroup: out = sum_{l,l'} prod_k Gram_k[l, l'] (sqrt for the norm).
+__global__ void __launch_bounds__(GT) gram_finish(GramJob job, const double* __restrict__ gram, double* out,
                                                   int sqrt_out) {
     __shared__ double red[GT / 64];
     const int ne = job.rx * job.ry;
     double part = 0.0;
     for (int t = threadIdx.x; t < ne; t += GT) {
         double prod = 1.0;
-        for (int k = 0; k < job.d; ++k) {
-            double g = 0.0;
-            for (int c = job.chunk0[k]; c < job.chunk0[k + 1]; ++c) g += partial[(int64_t)c * ne + t];
-            prod *= g;
-        }
+        for (int k = 0; k < job.d; ++k) prod *= gram[(int64_t)k * ne + t];
         part += prod;
     }
 #pragma unroll
@@ -84,16 +120,35 @@ __global__ void __launch_bounds__(GT) gram_finish(GramJob job, const double* __r
     }
 }
 
-int gram_chunks(const int32_t* n, int d, int32_t* chunk0) {
+// Row chunks per dimension: at least 256 rows each, and no more than MAX_CHUNKS / d chunks
+// per dimension (long panels get longer chunks).
+int gram_chunks(const int32_t* n, int d, int32_t* chunk0, int32_t* chunk_rows) {
     chunk0[0] = 0;
-    for (int k = 0; k < d; ++k) chunk0[k + 1] = chunk0[k] + (n[k] + GROWS - 1) / GROWS;
+    const int per_dim = MAX_CHUNKS / d;
+    for (int k = 0; k < d; ++k) {
+        int rows = 256;
+        while ((n[k] + rows - 1) / rows > per_dim) rows *= 2;
+        chunk_rows[k] = rows;
+        chunk0[k + 1] = chunk0[k] + (n[k] + rows - 1) / rows;
+    }
     return chunk0[d];
 }
 
 hipError_t launch_inner(const GramJob& job, double* partial, double* out, bool sqrt_out, hipStream_t st) {
     const int nchunks = job.chunk0[job.d];
-    if (nchunks > 0) hipLaunchKernelGGL(gram_partials, dim3(nchunks), dim3(GT), 0, st, job, partial);
-    hipLaunchKernelGGL(gram_finish, dim3(1), dim3(GT), 0, st, job, partial, out, sqrt_out ? 1 : 0);
+    const size_t smem = (size_t)GTR * (job.rx + job.ry + 2) * sizeof(double);
+    if (smem > 65536) {   // ranks above ~60 stage more than the default 64 KB
+        const hipError_t e = hipFuncSetAttribute((const void*)gram_partials, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                 (int)smem);
+        if (e != hipSuccess) return e;
+    }
+    // the per-dimension Grams follow the chunk partials in the same buffer
+    double* gram = partial + (size_t)nchunks * job.rx * job.ry;
+    if (nchunks > 0) {
+        hipLaunchKernelGGL(gram_partials, dim3(nchunks), dim3(GT), smem, st, job, partial);
+        hipLaunchKernelGGL(gram_reduce, dim3(job.rx * job.ry, job.d), dim3(GT), 0, st, job, partial, gram);
+    }
+    hipLaunchKernelGGL(gram_finish, dim3(1), dim3(GT), 0, st, job, gram, out, sqrt_out ? 1 : 0);
     return hipGetLastError();
 }
 
@@ -152,7 +207,60 @@ __global__ void __launch_bounds__(GT) apply_columns(ApplyJob job) {
     }
 }
 
+// Without rank-1 operators: one thread per grid row i of dimension blockIdx.y.  For every
+// column l the row of X is read once (coalesced over the workgroup's rows; band taps read
+// the neighbouring rows, which the neighbouring threads just loaded), every distinct
+// operator of the dimension is applied once, and the n_terms output columns are written
+// from those values.
+__global__ void __launch_bounds__(GT) apply_rows(ApplyJob job) {
+    const int k = blockIdx.y;
+    const int n = job.n[k];
+    const int i = blockIdx.x * GT + threadIdx.x;
+    if (i >= n) return;
+    const double* X = job.X[k];
+    double* Y = job.Y[k];
+    const int64_t ldx = job.ldx[k], ldy = job.ldy[k];
+    const int T = job.n_terms, r = job.r;
+    for (int l = 0; l < r; ++l) {
+        const double* x = X + (int64_t)l * ldx;
+        double v[CP_MAX_OPS];
+#pragma unroll
+        for (int a = 0; a < CP_MAX_OPS; ++a) {
+            const OpDev op = job.ops[k][a];
+            double val = 0.0;
+            if (op.kind == CP_OP_IDENTITY) {
+                val = x[i];
+            } else if (op.kind == CP_OP_DIAG) {
+                val = op.data[i] * x[i];
+            } else if (op.kind == CP_OP_BAND) {
+                const int h = op.hbw;
+                for (int j = 0; j <= 2 * h; ++j) {
+                    int c = i + j - h;   // periodic; the half-bandwidth may exceed n
+                    while (c < 0) c += n;
+                    while (c >= n) c -= n;
+                    val = fma(op.data[(int64_t)j * n + i], x[c], val);
+                }
+            }
+            v[a] = val;
+        }
+        for (int e = 0; e < T; ++e) {
+            const int a = job.op_index[e * job.d + k];
+            double val = v[0];
+#pragma unroll
+            for (int b = 1; b < CP_MAX_OPS; ++b) val = (a == b) ? v[b] : val;
+            Y[(int64_t)(e * r + l) * ldy + i] = (k == 0) ? job.coef[e] * val : val;
+        }
+    }
+}
+
 hipError_t launch_apply(const ApplyJob& job, int max_n, hipStream_t st) {
+    bool rank1 = false;
+    for (int k = 0; k < job.d; ++k)
+        for (int a = 0; a < CP_MAX_OPS; ++a) rank1 = rank1 || job.ops[k][a].kind == CP_OP_RANK1;
+    if (!rank1) {
+        hipLaunchKernelGGL(apply_rows, dim3((max_n + GT - 1) / GT, job.d), dim3(GT), 0, st, job);
+        return hipGetLastError();
+    }
     const int cols = job.d * job.n_terms * job.r;
     int rb = (max_n + 4095) / 4096;
     if (rb < 1) rb = 1;

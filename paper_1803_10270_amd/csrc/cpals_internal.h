@@ -84,6 +84,7 @@ struct GramJob {
     int32_t ldx[CP_MAX_DIMS], ldy[CP_MAX_DIMS];
     int32_t n[CP_MAX_DIMS];
     int32_t chunk0[CP_MAX_DIMS + 1];   // prefix sum of row chunks per dimension
+    int32_t chunk_rows[CP_MAX_DIMS];   // rows per chunk (a multiple of 64)
     int32_t d, rx, ry;
 };
 
