@@ -3,6 +3,7 @@
 // panel is read once from HBM.
 #include <hip/hip_runtime.h>
 #include "cpals_internal.h"
+#include "mfma_f64.h"
 
 namespace cpals {
 
@@ -11,12 +12,20 @@ constexpr int GTR = 64;       // rows per staged tile of a Gram partial
 constexpr int MAX_CHUNKS = 2048;   // row chunks over all dimensions (bounds the final sum)
 
 // One workgroup per (dimension, row chunk): partial[chunk][l + l' * rx] = sum_rows X[i,l] Y[i,l'].
-// Tiles of 64 rows of both panels are staged through LDS (dynamic size 64 (rx + ry + 2)
-// doubles; each column's 64 rows are one contiguous 512-byte read); the next tile's loads
-// are issued into registers before the current tile is reduced, and each thread owns up to
-// 16 (l, l') entries.
-__global__ void __launch_bounds__(GT) gram_partials(GramJob job, double* __restrict__ partial) {
+// Tiles of 64 rows of both panels are staged through LDS (dynamic size 2 * 64 (RP + 1)
+// doubles, RP = both ranks rounded up to 16, 32 or 64; each column's 64 rows are one
+// contiguous 512-byte read, columns past the rank are staged as zeros).  The next tile's
+// loads are issued into registers before the current tile is contracted.  The contraction
+// runs on the FP64 matrix cores: wave w takes rows 16w .. 16w + 15 of the tile (four
+// 16x16x4 steps) for every 16 x 16 block of the Gram; the four waves' blocks are added in
+// wave order once per chunk.
+template <int RP>
+__global__ void __launch_bounds__(GT, RP <= 32 ? 2 : 1) gram_partials(GramJob job, double* __restrict__ partial) {
     extern __shared__ double gsm[];
+    constexpr int S = RP + 1;          // LDS row stride (odd: spreads the banks)
+    constexpr int U = GTR * RP / GT;   // staged elements per thread and panel
+    constexpr int NT = RP / 16;        // 16-column blocks per panel at most
+    static_assert(GTR == 16 * (GT / 64), "each wave contracts 16 rows of a tile");
     const int c = blockIdx.x;
     int k = 0;
     while (k + 1 < job.d && c >= job.chunk0[k + 1]) ++k;
@@ -27,11 +36,11 @@ __global__ void __launch_bounds__(GT) gram_partials(GramJob job, double* __restr
     const double* X = job.X[k];
     const double* Y = job.Y[k];
     const int64_t ldx = job.ldx[k], ldy = job.ldy[k];
-    const int sx = rx + 1, sy = ry + 1;
     double* xs = gsm;
-    double* ys = gsm + GTR * sx;
-    const int ne = rx * ry;
-    constexpr int U = (GTR * CP_MAX_RANK + GT - 1) / GT;   // 16 staged elements per thread and panel
+    double* ys = gsm + GTR * S;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int kq = lane >> 4, cc = lane & 15;
+    const int tx = (rx + 15) >> 4, ty = (ry + 15) >> 4;
     double vx[U], vy[U];
     auto load = [&](int rb) {
 #pragma unroll
@@ -43,37 +52,53 @@ __global__ void __launch_bounds__(GT) gram_partials(GramJob job, double* __restr
             vy[u] = (l < ry && row < row1) ? Y[row + (int64_t)l * ldy] : 0.0;
         }
     };
-    double acc[16];
+    d4 acc[NT * NT];
 #pragma unroll
-    for (int e = 0; e < 16; ++e) acc[e] = 0.0;
+    for (int t = 0; t < NT * NT; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
     if (row0 < row1) load(row0);
     for (int rb = row0; rb < row1; rb += GTR) {
-        const int nrow = min(GTR, row1 - rb);
         __syncthreads();
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int t = threadIdx.x + u * GT;
             const int i = t & (GTR - 1), l = t / GTR;
-            if (l < rx) xs[i * sx + l] = vx[u];
-            if (l < ry) ys[i * sy + l] = vy[u];
+            xs[i * S + l] = vx[u];
+            ys[i * S + l] = vy[u];
         }
         __syncthreads();
         if (rb + GTR < row1) load(rb + GTR);
 #pragma unroll
-        for (int e = 0; e < 16; ++e) {
-            const int t = threadIdx.x + e * GT;
-            if (t < ne) {
-                const int l = t % rx, lp = t / rx;
-                double a = acc[e];
-                for (int i = 0; i < nrow; ++i) a = fma(xs[i * sx + l], ys[i * sy + lp], a);
-                acc[e] = a;
+        for (int s = 0; s < 4; ++s) {
+            const int i = 16 * wave + 4 * s + kq;
+            double a[NT], b[NT];
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                a[t] = xs[i * S + 16 * t + cc];
+                b[t] = ys[i * S + 16 * t + cc];
             }
+#pragma unroll
+            for (int ti = 0; ti < NT; ++ti)
+#pragma unroll
+                for (int tj = 0; tj < NT; ++tj)
+                    if (ti < tx && tj < ty) acc[ti * NT + tj] = mfma_f64(a[ti], b[tj], acc[ti * NT + tj]);
         }
     }
+    // block (ti, tj), element v of a lane: Gram[16 ti + kq + 4 v][16 tj + cc]
+    const int ne = rx * ry;
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
-        const int t = threadIdx.x + e * GT;
-        if (t < ne) partial[(int64_t)c * ne + t] = acc[e];
+    for (int t = 0; t < NT * NT; ++t) {
+        const int ti = t / NT, tj = t % NT;
+        if (ti >= tx || tj >= ty) continue;
+        __syncthreads();
+#pragma unroll
+        for (int v = 0; v < 4; ++v) gsm[(wave * 4 + v) * 64 + lane] = acc[t][v];
+        __syncthreads();
+        const int v = threadIdx.x >> 6;
+        double sum = gsm[v * 64 + lane];
+#pragma unroll
+        for (int w = 1; w < GT / 64; ++w) sum += gsm[(w * 4 + v) * 64 + lane];
+        const int l = 16 * ti + kq + 4 * v, lp = 16 * tj + cc;
+        if (l < rx && lp < ry) partial[(int64_t)c * ne + l + lp * rx] = sum;
     }
 }
 
@@ -134,18 +159,29 @@ int gram_chunks(const int32_t* n, int d, int32_t* chunk0, int32_t* chunk_rows) {
     return chunk0[d];
 }
 
-hipError_t launch_inner(const GramJob& job, double* partial, double* out, bool sqrt_out, hipStream_t st) {
-    const int nchunks = job.chunk0[job.d];
-    const size_t smem = (size_t)GTR * (job.rx + job.ry + 2) * sizeof(double);
-    if (smem > 65536) {   // ranks above ~60 stage more than the default 64 KB
-        const hipError_t e = hipFuncSetAttribute((const void*)gram_partials, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                 (int)smem);
+template <int RP>
+static hipError_t launch_partials(const GramJob& job, int nchunks, double* partial, hipStream_t st) {
+    const size_t smem = (size_t)2 * GTR * (RP + 1) * sizeof(double);
+    if (smem > 65536) {   // rank 64 stages more than the default 64 KB
+        const hipError_t e = hipFuncSetAttribute((const void*)gram_partials<RP>,
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
         if (e != hipSuccess) return e;
     }
+    hipLaunchKernelGGL(gram_partials<RP>, dim3(nchunks), dim3(GT), smem, st, job, partial);
+    return hipSuccess;
+}
+
+hipError_t launch_inner(const GramJob& job, double* partial, double* out, bool sqrt_out, hipStream_t st) {
+    const int nchunks = job.chunk0[job.d];
+    const int rmax = job.rx > job.ry ? job.rx : job.ry;
+    if (rmax > CP_MAX_RANK) return hipErrorInvalidValue;
     // the per-dimension Grams follow the chunk partials in the same buffer
     double* gram = partial + (size_t)nchunks * job.rx * job.ry;
     if (nchunks > 0) {
-        hipLaunchKernelGGL(gram_partials, dim3(nchunks), dim3(GT), smem, st, job, partial);
+        const hipError_t e = rmax <= 16   ? launch_partials<16>(job, nchunks, partial, st)
+                             : rmax <= 32 ? launch_partials<32>(job, nchunks, partial, st)
+                                          : launch_partials<64>(job, nchunks, partial, st);
+        if (e != hipSuccess) return e;
         hipLaunchKernelGGL(gram_reduce, dim3(job.rx * job.ry, job.d), dim3(GT), 0, st, job, partial, gram);
     }
     hipLaunchKernelGGL(gram_finish, dim3(1), dim3(GT), 0, st, job, gram, out, sqrt_out ? 1 : 0);
