@@ -160,7 +160,8 @@ cp_status cp_norm(cp_handle h, const cp_tensor* x, double* out_dev);
 
 /* y = L x as a CP tensor of rank n_terms * x.r (operator application, Section 3.2):
  * column e*x.r + l of y.U[k] is E_k^e X_k[:, l], with coef[e] multiplied into dimension 0.
- * y must have y.r == L.n_terms * x.r and the same n; y's panels are overwritten. */
+ * y must have y.r == L.n_terms * x.r and the same n; y's panels are overwritten and must not
+ * overlap x's panels (not checked; overlapping panels give undefined results). */
 cp_status cp_apply_operator(cp_handle h, const cp_operator* L, const cp_tensor* x, cp_tensor* y);
 
 /* One implicit time step: minimise ||A f_{n+1} - B f_n|| over rank-r CP tensors

@@ -249,42 +249,61 @@ __global__ void __launch_bounds__(GT) apply_columns(ApplyJob job) {
 // operator of the dimension is applied once, and the n_terms output columns are written
 // from those values.
 __global__ void __launch_bounds__(GT) apply_rows(ApplyJob job) {
+    __shared__ double coef_s[CP_MAX_TERMS];
+    __shared__ int32_t op_s[CP_MAX_TERMS];
     const int k = blockIdx.y;
     const int n = job.n[k];
+    const int T = job.n_terms, r = job.r;
+    // the term table of this dimension, read once per workgroup
+    for (int e = threadIdx.x; e < T; e += GT) {
+        op_s[e] = job.op_index[e * job.d + k];
+        coef_s[e] = (k == 0) ? job.coef[e] : 1.0;
+    }
+    __syncthreads();
     const int i = blockIdx.x * GT + threadIdx.x;
     if (i >= n) return;
-    const double* X = job.X[k];
-    double* Y = job.Y[k];
+    const double* __restrict__ X = job.X[k];
+    double* __restrict__ Y = job.Y[k];
     const int64_t ldx = job.ldx[k], ldy = job.ldy[k];
-    const int T = job.n_terms, r = job.r;
-    for (int l = 0; l < r; ++l) {
-        const double* x = X + (int64_t)l * ldx;
-        double v[CP_MAX_OPS];
+    // per-row diagonal coefficients, loaded once for all columns
+    double dg[CP_MAX_OPS];
 #pragma unroll
-        for (int a = 0; a < CP_MAX_OPS; ++a) {
-            const OpDev op = job.ops[k][a];
-            double val = 0.0;
-            if (op.kind == CP_OP_IDENTITY) {
-                val = x[i];
-            } else if (op.kind == CP_OP_DIAG) {
-                val = op.data[i] * x[i];
-            } else if (op.kind == CP_OP_BAND) {
-                const int h = op.hbw;
-                for (int j = 0; j <= 2 * h; ++j) {
-                    int c = i + j - h;   // periodic; the half-bandwidth may exceed n
-                    while (c < 0) c += n;
-                    while (c >= n) c -= n;
-                    val = fma(op.data[(int64_t)j * n + i], x[c], val);
+    for (int a = 0; a < CP_MAX_OPS; ++a) dg[a] = job.ops[k][a].kind == CP_OP_DIAG ? job.ops[k][a].data[i] : 1.0;
+    // LB columns' loads are issued together before any output is formed
+    constexpr int LB = 4;
+    for (int l0 = 0; l0 < r; l0 += LB) {
+        double xv[LB];
+#pragma unroll
+        for (int u = 0; u < LB; ++u) xv[u] = (l0 + u < r) ? X[(int64_t)(l0 + u) * ldx + i] : 0.0;
+#pragma unroll
+        for (int u = 0; u < LB; ++u) {
+            const int l = l0 + u;
+            if (l >= r) break;
+            const double* x = X + (int64_t)l * ldx;
+            double v[CP_MAX_OPS];
+#pragma unroll
+            for (int a = 0; a < CP_MAX_OPS; ++a) {
+                const OpDev op = job.ops[k][a];
+                double val = dg[a] * xv[u];   // identity and diagonal
+                if (op.kind == CP_OP_BAND) {
+                    const int h = op.hbw;
+                    val = 0.0;
+                    for (int j = 0; j <= 2 * h; ++j) {
+                        int c = i + j - h;   // periodic; the half-bandwidth may exceed n
+                        while (c < 0) c += n;
+                        while (c >= n) c -= n;
+                        val = fma(op.data[(int64_t)j * n + i], x[c], val);
+                    }
                 }
+                v[a] = val;
             }
-            v[a] = val;
-        }
-        for (int e = 0; e < T; ++e) {
-            const int a = job.op_index[e * job.d + k];
-            double val = v[0];
+            for (int e = 0; e < T; ++e) {
+                const int a = op_s[e];
+                double val = v[0];
 #pragma unroll
-            for (int b = 1; b < CP_MAX_OPS; ++b) val = (a == b) ? v[b] : val;
-            Y[(int64_t)(e * r + l) * ldy + i] = (k == 0) ? job.coef[e] * val : val;
+                for (int b = 1; b < CP_MAX_OPS; ++b) val = (a == b) ? v[b] : val;
+                Y[(int64_t)(e * r + l) * ldy + i] = coef_s[e] * val;
+            }
         }
     }
 }
