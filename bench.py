@@ -362,7 +362,8 @@ def main():
     ap.add_argument("--max-sweeps", type=int, default=200)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--form", default="plain", choices=["plain", "batched"])
+    ap.add_argument("--form", default="plain", choices=["plain", "batched", "streaming"],
+                    help="plain: the headline line; batched / streaming: that leg alone")
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--batch-steps", type=int, default=20)
     ap.add_argument("--plain-sample", type=int, default=8)
@@ -372,8 +373,8 @@ def main():
     ap.add_argument("--learned-eval-steps", type=int, default=6)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build runs on one GPU only (the multi-GPU sharding is a design, not code); "
-              "use --gpus 1", file=sys.stderr)
+        print("bench.py: one GPU only (sharding the step across GPUs is not implemented); use --gpus 1",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -387,6 +388,9 @@ def main():
 
     if args.form == "batched":
         print(json.dumps(bench_batched(args)), flush=True)
+        return
+    if args.form == "streaming":
+        print(json.dumps(bench_streaming(log)), flush=True)
         return
     p = W.advection_ie_variable(seed=args.seed)
     h = B.Handle()

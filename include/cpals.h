@@ -48,7 +48,7 @@ typedef enum {
     CP_OK = 0,
     CP_ERR_INVALID_ARG = 1,  /* null pointer, bad enum, bad option value          */
     CP_ERR_SHAPE = 2,        /* dimensions, ranks or sizes inconsistent / too big */
-    CP_ERR_UNSUPPORTED = 3,  /* valid request that this build does not implement  */
+    CP_ERR_UNSUPPORTED = 3,  /* valid request that the library does not implement */
     CP_ERR_HIP = 4,          /* HIP runtime error (allocation, launch, copy)      */
     CP_ERR_NOT_CONVERGED = 5 /* soft: results written, report.flags says why      */
 } cp_status;
