@@ -15,9 +15,14 @@ the same 1e-8 tolerance:
            held-out instance of the same workload (the untrained network, i.e. the
            extrapolation alone, is reported beside it);
   batched  256 uneven advection instances in one persistent launch against the same
-           instances advanced one launch at a time (a seeded sample, scaled by cost).
+           instances advanced one launch at a time (a seeded sample, scaled by cost);
+  mixed    FP32 matrix-core sweeps finished by an FP64 sweep, against FP64 throughout, on
+           the kinetic Crank-Nicolson workload (d = 6, n = 128, rank 64).
+It also reports the HBM rates of the streaming kernels (cp_inner, cp_apply_operator) on
+gigabyte panels.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-forms]
+    python bench.py --form batched|streaming     (that leg alone)
 
 Prints one JSON line.
 """
