@@ -109,13 +109,16 @@ __device__ __forceinline__ void cluster_sync() {
         uint32_t* ctr = s.pb.bar;
         __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         long spins = 0;
-        while (__hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < tgt) {
+        // spin on relaxed loads; one acquire fence once the count is reached (an acquire load
+        // per spin would invalidate the L2 of the workgroup's XCD on every poll)
+        while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < tgt) {
             __builtin_amdgcn_s_sleep(2);
             if (++spins > (1l << 22)) {
                 s.sync_ok = 0;
                 break;
             }
         }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     __syncthreads();
 }
