@@ -69,6 +69,36 @@ def test_apply_operator(handle, dims, r, T):
         assert np.abs(y - yr).max() <= 1e-13 * max(1.0, np.abs(yr).max())
 
 
+def test_streaming_kernels_at_benchmark_size(handle):
+    """The streaming kernels in the launch configuration the benchmark times: cp_inner on
+    d = 2, n = 2^22, ranks 16 x 16 (against the oracle in full), cp_apply_operator on d = 2,
+    n = 2^21, rank 16, three scaled-identity terms (its outputs on 4096 sampled rows: with
+    pointwise operators a row of the output depends only on the same row of the input)."""
+    import torch
+    log("streaming full size")
+    rng = np.random.default_rng(2024)
+    n, r = 1 << 22, 16
+    X = W.random_factors(rng, [n, n], r)
+    Y = W.random_factors(rng, [n, n], r)
+    out = torch.zeros(1, dtype=torch.float64, device="cuda")
+    B.cp_inner(handle, dev(X), dev(Y), out)
+    ref = O.cp_inner(X, Y)
+    assert abs(out.item() - ref) <= 1e-12 * O.cp_norm(X) * O.cp_norm(Y)
+    del X, Y
+    n2 = 1 << 21
+    coef = np.array([1.0, 0.5, 0.25])
+    L = W.SepOperator(coef, np.zeros((3, 2), dtype=np.int32), [[W.op_identity(n2)]] * 2)
+    Xa = W.random_factors(rng, [n2, n2], r)
+    Yd = [torch.empty((3 * r, n2), dtype=torch.float64, device="cuda") for _ in range(2)]
+    B.cp_apply_operator(handle, L, dev(Xa), Yd)
+    rows = np.unique(np.concatenate([rng.choice(n2, 4094, replace=False), [0, n2 - 1]]))
+    Ls = W.SepOperator(coef, np.zeros((3, 2), dtype=np.int32), [[W.op_identity(len(rows))]] * 2)
+    want = O.cp_apply_operator(Ls, [x[rows] for x in Xa])
+    idx = torch.from_numpy(rows).to("cuda")
+    for y, yr in zip(host([t[:, idx] for t in Yd]), want):
+        assert np.array_equal(y, yr)
+
+
 # ------------------------------------------------------------------------ ALS steps
 
 def run_gpu_step(handle, A, Bop, V, guess, **opts):
