@@ -38,7 +38,8 @@ def mixed_operator(rng, dims, n_terms, with_rank1=True, scale=0.3):
 # ------------------------------------------------------------------ inner / norm / apply
 
 @pytest.mark.parametrize("dims,rx,ry", [([5, 300, 1000], 3, 7), ([256] * 6, 32, 32), ([1], 1, 1),
-                                        ([513, 64], 64, 17), ([2**19 + 37, 5], 20, 9)])
+                                        ([513, 64], 64, 17), ([2**19 + 37, 5], 20, 9), ([100, 37], 17, 64),
+                                        ([4096], 48, 16)])
 def test_inner_and_norm(handle, dims, rx, ry):
     import torch
     log("inner", dims, rx, ry)
