@@ -52,6 +52,8 @@ import numpy as np
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
+from . import ddarith as DD
+
 FLAG_NOT_CONVERGED = 1
 
 DENSE_SOLVE_LIMIT = 3000
@@ -322,39 +324,35 @@ def run(problem, n_steps: Optional[int] = None, max_sweeps: int = 200, eps_reg: 
 
 
 # --------------------------------------------------------------------------------------
-# residual and distances in extended precision
+# residual and distances in double-double (the cancellation floor of the Gram expansion)
 # --------------------------------------------------------------------------------------
 
-def _gram_ld(W: np.ndarray) -> np.ndarray:
-    Wl = W.astype(np.longdouble)
-    return Wl.T @ Wl
-
-
 def stacked_norm2(factors: Sequence[np.ndarray]) -> float:
-    """||sum_l prod_k W_k[:, l]||^2 with every Gram, Hadamard product and the final sum in
-    x87 extended precision (pushes the cancellation floor of the Gram expansion down)."""
-    H = None
-    for W in factors:
-        g = _gram_ld(W)
-        H = g if H is None else H * g
-    return float(H.sum())
+    """||sum_l prod_k W_k[:, l]||^2 with every Gram entry a compensated (Dot2) sum and the
+    Hadamard products and the final sum in double-double; rounded to float64 at the end."""
+    h, l = DD.stacked_norm2_dd(factors)
+    return h + l
+
+
+def _stack_difference(X, Y):
+    """Factors of the CP tensor x - y (y's columns negated in dimension 0)."""
+    return [np.concatenate([x, (-y if k == 0 else y)], axis=1) for k, (x, y) in enumerate(zip(X, Y))]
 
 
 def residual(A, B, U, V, source=None) -> float:
-    """rho = ||A f - g|| / ||g||, g = B f_n (+ c) (eq. (rRr1) / (rRr))."""
+    """rho = ||A f - g|| / ||g||, g = B f_n (+ c) (eqs. (rRr1), (rRr)), from the stacked CP
+    tensor [A f, -g] in double-double: resolved far below float64's sqrt(eps) floor."""
     AU = cp_apply_operator(A, U)
     BV = cp_apply_operator(B, V)
     g = BV if source is None else [np.concatenate([bv, s], axis=1) for bv, s in zip(BV, source)]
-    R = [np.concatenate([au, (-gk if k == 0 else gk)], axis=1) for k, (au, gk) in enumerate(zip(AU, g))]
-    num = stacked_norm2(R)
+    num = stacked_norm2(_stack_difference(AU, g))
     den = stacked_norm2(g)
-    return float(np.sqrt(max(num, 0.0) / den))
+    return float(np.sqrt(max(num, 0.0) / den)) if den > 0 else float(np.sqrt(max(num, 0.0)))
 
 
 def rel_distance(X, Y) -> float:
-    """||x - y|| / ||y|| for two CP tensors, in extended precision."""
-    D = [np.concatenate([x, (-y if k == 0 else y)], axis=1) for k, (x, y) in enumerate(zip(X, Y))]
-    return float(np.sqrt(max(stacked_norm2(D), 0.0) / stacked_norm2(Y)))
+    """||x - y|| / ||y|| for two CP tensors, in double-double."""
+    return float(np.sqrt(max(stacked_norm2(_stack_difference(X, Y)), 0.0) / stacked_norm2(Y)))
 
 
 def sampled_rel_distance(X, Y, n_samples: int = 1 << 16, seed: int = 1234) -> float:
@@ -364,3 +362,133 @@ def sampled_rel_distance(X, Y, n_samples: int = 1 << 16, seed: int = 1234) -> fl
     fx = cp_eval(X, idx)
     fy = cp_eval(Y, idx)
     return float(np.linalg.norm(fx - fy) / np.linalg.norm(fy))
+
+
+# --------------------------------------------------------------------------------------
+# adaptive separation rank (Section 4.1: the rank is chosen at every step up to r_max;
+# Section 3.2: rank reduction)
+# --------------------------------------------------------------------------------------
+
+MASK64 = (1 << 64) - 1
+RANK_SLOTS, DIM_SLOTS = 64, 8     # counter layout of the growth directions
+
+
+def splitmix64(seed: int, counter: int) -> int:
+    """The SplitMix64 generator of Steele, Lea & Flood (OOPSLA 2014) in counter form: the
+    64-bit output for state seed + (counter + 1) * golden gamma."""
+    z = (seed + (counter + 1) * 0x9E3779B97F4A7C15) & MASK64
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & MASK64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & MASK64
+    return z ^ (z >> 31)
+
+
+def growth_column(seed: int, step: int, l: int, k: int, n: int) -> np.ndarray:
+    """Factor of dimension k of the term appended as column l in time step `step`: zero in
+    dimension 0 (the represented tensor is unchanged until that dimension's next update
+    sizes the term, the "small random perturbation" of the initial guess of Section 3.1
+    taken with zero amplitude), elsewhere 2u - 1 with u = the top 53 bits of
+    splitmix64(seed, counter) / 2^53, counter = ((step * 64 + l) * 8 + k) * 2^32 + i."""
+    if k == 0:
+        return np.zeros(n)
+    base = ((step * RANK_SLOTS + l) * DIM_SLOTS + k) << 32
+    u = np.array([(splitmix64(seed, base + i) >> 11) for i in range(n)], dtype=np.float64) * 2.0 ** -53
+    return 2.0 * u - 1.0
+
+
+def term_weights(U: Sequence[np.ndarray]) -> np.ndarray:
+    """Weight of every term, prod_k ||U_k[:, l]||."""
+    w = np.ones(U[0].shape[1])
+    for u in U:
+        w = w * np.sqrt(np.sum(u * u, axis=0))
+    return w
+
+
+def drop_small_terms(U: Sequence[np.ndarray], rel: float = 1e-14) -> List[np.ndarray]:
+    """Rank reduction by dropping terms of weight below rel * (largest weight); the kept
+    columns keep their order and at least one column is kept."""
+    w = term_weights(U)
+    keep = np.nonzero(w >= rel * w.max())[0] if w.max() > 0 else np.arange(w.size)
+    if keep.size == 0:
+        keep = np.arange(1)
+    return [np.array(u[:, keep]) for u in U]
+
+
+def adaptive_step(A, B, V, U_start, cap: int, tau: float, tol: float = 1e-8, max_sweeps: int = 200,
+                  eps_reg: float = 1e-10, seed: int = 0, step: int = 0, replay_rank: Optional[int] = None,
+                  source=None):
+    """One implicit step with adaptive separation rank.
+
+    The step is solved (als_step) from U_start at its rank r; then rho = residual(...) is
+    formed in double-double.  While rho > tau (or, replaying, while r < replay_rank) and
+    r < cap, one term is appended (growth_column) and the step is solved again from the
+    current factors at rank r + 1.  Every decision is logged as (r, rho).  Finally terms of
+    weight < 1e-14 of the largest are dropped.
+
+    Returns (factors, report) with report = dict(sweeps (summed over the solves), eps_conv
+    and flags of the last solve, rel_residual (the last rho), final_rank, log)."""
+    U = [np.array(u, dtype=np.float64, copy=True) for u in U_start]
+    r = U[0].shape[1]
+    log, sweeps = [], 0
+    while True:
+        U, rep = als_step(A, B, V, U, tol, max_sweeps, eps_reg, source)
+        sweeps += rep["sweeps"]
+        rho = residual(A, B, U, V, source)
+        log.append((r, rho))
+        grow = (rho > tau) if replay_rank is None else (r < replay_rank)
+        if not grow or r >= cap:
+            break
+        U = [np.concatenate([u, growth_column(seed, step, r, k, u.shape[0])[:, None]], axis=1)
+             for k, u in enumerate(U)]
+        r += 1
+    U = drop_small_terms(U)
+    return U, {"sweeps": sweeps, "eps_conv": rep["eps_conv"], "flags": rep["flags"], "rel_residual": rho,
+               "final_rank": U[0].shape[1], "log": log}
+
+
+def run_adaptive(A, B, f0, cap: int, tau: float, n_steps: int, tol: float = 1e-8, max_sweeps: int = 200,
+                 eps_reg: float = 1e-10, seed: int = 0, replay_ranks: Optional[Sequence[int]] = None):
+    """Time loop with adaptive rank: step s starts from f_s itself (its own rank)."""
+    V = [np.array(u, dtype=np.float64, copy=True) for u in f0]
+    traj, reports = [], []
+    for s in range(n_steps):
+        rr = None if replay_ranks is None else int(replay_ranks[s])
+        U, rep = adaptive_step(A, B, V, V, cap, tau, tol, max_sweeps, eps_reg, seed, s, rr)
+        traj.append(U)
+        reports.append(rep)
+        V = U
+    return traj, reports
+
+
+# --------------------------------------------------------------------------------------
+# explicit second-order Adams-Bashforth step (Section 3.2, eq. (AB2_))
+# --------------------------------------------------------------------------------------
+
+def cp_axpby(alpha: float, X, beta: float, Y):
+    """alpha x + beta y as one CP tensor: x's columns then y's, the scalars in dimension 0."""
+    return [np.concatenate([alpha * x if k == 0 else x, beta * y if k == 0 else y], axis=1)
+            for k, (x, y) in enumerate(zip(X, Y))]
+
+
+def reduce_rank(G, cap: int, tol: float = 1e-12, max_sweeps: int = 200, eps_reg: float = 1e-10):
+    """Rank reduction of Section 3.2 by ALS (Section 2.1): a tensor of rank <= cap is kept as
+    it is; otherwise it is fitted at rank cap starting from its own leading cap columns."""
+    if G[0].shape[1] <= cap:
+        return [np.array(g) for g in G], {"sweeps": 0, "eps_conv": 0.0, "flags": 0}
+    start = [np.array(g[:, :cap]) for g in G]
+    return truncate(G, start, tol, max_sweeps, eps_reg)
+
+
+def ab2_step(L, dt: float, F_prev, F_cur, cap: int, tol: float = 1e-12, max_sweeps: int = 200,
+             eps_reg: float = 1e-10):
+    """f_{n+2} = f_{n+1} + dt/2 L (3 f_{n+1} - f_n), split as in Section 3.2 into additions,
+    one operator application and rank reductions:
+      i)   w = 3 f_{n+1} - f_n, reduced to rank <= cap;
+      ii)  y = L w (cp_apply_operator), reduced;
+      iii) f_{n+2} = f_{n+1} + (dt/2) y, reduced.
+    (The text of the split names w = f_{n+1} - f_n; the formula it splits has 3 f_{n+1} - f_n,
+    which is what is computed.)  Returns (factors, dict of the three reductions' reports)."""
+    w, r1 = reduce_rank(cp_axpby(3.0, F_cur, -1.0, F_prev), cap, tol, max_sweeps, eps_reg)
+    y, r2 = reduce_rank(cp_apply_operator(L, w), cap, tol, max_sweeps, eps_reg)
+    f, r3 = reduce_rank(cp_axpby(1.0, F_cur, 0.5 * dt, y), cap, tol, max_sweeps, eps_reg)
+    return f, {"reductions": [r1, r2, r3], "sweeps": r1["sweeps"] + r2["sweeps"] + r3["sweeps"],
+               "flags": r1["flags"] | r2["flags"] | r3["flags"]}
