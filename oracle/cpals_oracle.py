@@ -383,16 +383,51 @@ def splitmix64(seed: int, counter: int) -> int:
 
 
 def growth_column(seed: int, step: int, l: int, k: int, n: int) -> np.ndarray:
-    """Factor of dimension k of the term appended as column l in time step `step`: zero in
-    dimension 0 (the represented tensor is unchanged until that dimension's next update
-    sizes the term, the "small random perturbation" of the initial guess of Section 3.1
-    taken with zero amplitude), elsewhere 2u - 1 with u = the top 53 bits of
-    splitmix64(seed, counter) / 2^53, counter = ((step * 64 + l) * 8 + k) * 2^32 + i."""
+    """Seeded start of dimension k of the term appended as column l in time step `step`:
+    2u - 1 with u = the top 53 bits of splitmix64(seed, counter) / 2^53,
+    counter = ((step * 64 + l) * 8 + k) * 2^32 + i.  Dimension 0 is zero: it is the first
+    factor the fit below updates, so its start is never read."""
     if k == 0:
         return np.zeros(n)
     base = ((step * RANK_SLOTS + l) * DIM_SLOTS + k) << 32
     u = np.array([(splitmix64(seed, base + i) >> 11) for i in range(n)], dtype=np.float64) * 2.0 ** -53
     return 2.0 * u - 1.0
+
+
+GROWTH_SWEEPS = 3
+
+
+def residual_tensor(A, B, U, V, source=None) -> List[np.ndarray]:
+    """The step residual g - A f (g = B f_n (+ c)) as one CP tensor: the columns of g, then
+    those of A f with the sign in dimension 0 (Section 3.2: sums of CP tensors stack their
+    terms)."""
+    AU = cp_apply_operator(A, U)
+    g = cp_apply_operator(B, V)
+    if source is not None:
+        g = [np.concatenate([x, c], axis=1) for x, c in zip(g, source)]
+    return [np.concatenate([x, -y if k == 0 else y], axis=1) for k, (x, y) in enumerate(zip(g, AU))]
+
+
+def growth_term(A, B, U, V, seed: int, step: int, source=None) -> List[np.ndarray]:
+    """The term appended when the rank grows: GROWTH_SWEEPS sweeps of rank-1 alternating
+    least squares (Section 2.1 with r = 1) fitting the residual tensor R = g - A f, from
+    the seeded start growth_column(seed, step, r, k).  One update of dimension q sets
+    t_q = R_q y / prod_{k != q} t_k^T t_k with y = o_{k != q} R_k^T t_k (the exact
+    minimiser of ||R - t|| over t_q); a start orthogonal to R gives t = 0."""
+    R = residual_tensor(A, B, U, V, source)
+    r = U[0].shape[1]
+    t = [growth_column(seed, step, r, k, u.shape[0]) for k, u in enumerate(U)]
+    d = len(U)
+    for _ in range(GROWTH_SWEEPS):
+        for q in range(d):
+            y = np.ones(R[0].shape[1])
+            nn = 1.0
+            for k in range(d):
+                if k != q:
+                    y = y * (R[k].T @ t[k])
+                    nn *= float(t[k] @ t[k])
+            t[q] = (R[q] @ y) / nn if nn > 0.0 else np.zeros_like(t[q])
+    return t
 
 
 def term_weights(U: Sequence[np.ndarray]) -> np.ndarray:
@@ -420,12 +455,13 @@ def adaptive_step(A, B, V, U_start, cap: int, tau: float, tol: float = 1e-8, max
 
     The step is solved (als_step) from U_start at its rank r; then rho = residual(...) is
     formed in double-double.  While rho > tau (or, replaying, while r < replay_rank) and
-    r < cap, one term is appended (growth_column) and the step is solved again from the
-    current factors at rank r + 1.  Every decision is logged as (r, rho).  Finally terms of
-    weight < 1e-14 of the largest are dropped.
+    r < cap, one term is appended (growth_term: a rank-1 fit of the residual tensor) and
+    the step is solved again from the current factors at rank r + 1.  Every decision is
+    logged as (r, rho).  Finally terms of weight < 1e-14 of the largest are dropped.
 
     Returns (factors, report) with report = dict(sweeps (summed over the solves), eps_conv
-    and flags of the last solve, rel_residual (the last rho), final_rank, log)."""
+    and flags of the last solve, rel_residual (the last rho), final_rank, grown_rank (the
+    rank before the drop), log)."""
     U = [np.array(u, dtype=np.float64, copy=True) for u in U_start]
     r = U[0].shape[1]
     log, sweeps = [], 0
@@ -437,12 +473,12 @@ def adaptive_step(A, B, V, U_start, cap: int, tau: float, tol: float = 1e-8, max
         grow = (rho > tau) if replay_rank is None else (r < replay_rank)
         if not grow or r >= cap:
             break
-        U = [np.concatenate([u, growth_column(seed, step, r, k, u.shape[0])[:, None]], axis=1)
-             for k, u in enumerate(U)]
+        t = growth_term(A, B, U, V, seed, step, source)
+        U = [np.concatenate([u, x[:, None]], axis=1) for u, x in zip(U, t)]
         r += 1
     U = drop_small_terms(U)
     return U, {"sweeps": sweeps, "eps_conv": rep["eps_conv"], "flags": rep["flags"], "rel_residual": rho,
-               "final_rank": U[0].shape[1], "log": log}
+               "final_rank": U[0].shape[1], "grown_rank": r, "log": log}
 
 
 def run_adaptive(A, B, f0, cap: int, tau: float, n_steps: int, tol: float = 1e-8, max_sweeps: int = 200,

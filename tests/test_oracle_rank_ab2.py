@@ -189,19 +189,52 @@ def test_adaptive_rank_d2_follows_the_svd():
         assert abs(rho - tails[r]) <= 1e-6 * tails[r], (r, rho, tails[r])
 
 
-def test_adaptive_residual_never_increases_with_rank():
-    """Every added term starts with zero weight, so the next solve starts from the previous
-    minimiser and alternating minimisation cannot increase the residual (Section 3.1:
-    every update is the exact minimiser over one factor)."""
-    p = W.advection_ie_variable(seed=3, d=3, n=8, ic_rank=2, cap=6)
-    U, rep = O.adaptive_step(p.A, p.B, p.f0, p.f0, cap=6, tau=1e-14, tol=1e-12, max_sweeps=40, eps_reg=1e-14,
-                             seed=5)
-    # (every solve here stops at its sweep cap: the iterates are still monotone)
+def test_adaptive_residual_never_increases_with_rank_for_truncation():
+    """A = B = I (rank reduction): the appended term is a rank-1 least-squares fit of the
+    residual g - f started from a zero first factor, so ||g - (f + t)|| <= ||g - f||, and
+    every later update is the exact minimiser over one factor (Section 3.1): the logged
+    residual cannot increase with the rank."""
+    rng = np.random.default_rng(8)
+    dims = [7, 6, 8]
+    G = W.random_factors(rng, dims, 6)
+    I = W.identity_operator(dims)
+    start = [g[:, :1] for g in G]
+    U, rep = O.adaptive_step(I, I, G, start, cap=5, tau=1e-14, tol=1e-12, max_sweeps=60, eps_reg=1e-14, seed=5)
     rhos = [rho for _, rho in rep["log"]]
-    assert [r for r, _ in rep["log"]] == [2, 3, 4, 5, 6]
+    assert [r for r, _ in rep["log"]] == [1, 2, 3, 4, 5]
     for a, b in zip(rhos, rhos[1:]):
         assert b <= a * (1 + 1e-9)
-    assert rhos[-1] < rhos[0]
+    assert rhos[-1] < 0.5 * rhos[0]
+
+
+def test_growth_term_recovers_a_rank_one_residual():
+    """When g - f is exactly a rank-1 tensor s (g = f + s, A = B = I), one sweep of the
+    rank-1 fit already reproduces s: checked on the full grid."""
+    rng = np.random.default_rng(12)
+    dims = [5, 6, 4]
+    F = W.random_factors(rng, dims, 3)
+    S = W.random_factors(rng, dims, 1)
+    G = [np.concatenate([f, s], axis=1) for f, s in zip(F, S)]
+    I = W.identity_operator(dims)
+    t = O.growth_term(I, I, F, G, seed=4, step=0)
+    assert rel(cp_full([x[:, None] for x in t]), cp_full(S)) <= 1e-12
+
+
+def test_growth_term_d2_is_power_iteration():
+    """d = 2: a sweep of rank-1 ALS on the residual matrix R is one step of the power
+    method, so after three sweeps t_0 t_1^T = u u^T R / (u^T u) with
+    u = R (R^T R)^2 t_1^(0) (dense matrices, computed without the CP form)."""
+    rng = np.random.default_rng(6)
+    n0, n1 = 9, 7
+    F = W.random_factors(rng, [n0, n1], 2)
+    G = W.random_factors(rng, [n0, n1], 4)
+    I = W.identity_operator([n0, n1])
+    t = O.growth_term(I, I, F, G, seed=17, step=3)
+    Rm = cp_full(G) - cp_full(F)
+    t1 = O.growth_column(17, 3, 2, 1, n1)
+    u = Rm @ (Rm.T @ (Rm @ (Rm.T @ (Rm @ t1))))
+    expect = np.outer(u, u) @ Rm / (u @ u)
+    assert rel(np.outer(t[0], t[1]), expect) <= 1e-12
 
 
 def test_adaptive_replay_reproduces_the_logged_decisions():
