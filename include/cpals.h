@@ -18,8 +18,11 @@
  *   - Operator descriptions (cp_operator, cp_op1d and everything they point to) are HOST
  *     memory; the library copies them to the device during the call.
  *   - Scalar outputs named *_dev are DEVICE pointers; report structs are HOST memory.
- *   - The library owns an internal device workspace per handle (grown on demand, freed by
- *     cp_destroy).
+ *   - Device workspace: by default the library owns one per handle (grown on demand, freed
+ *     by cp_destroy).  After cp_set_workspace the caller's buffer is used instead and no
+ *     call on the handle allocates device memory; a call that needs more than the buffer
+ *     holds returns CP_ERR_WORKSPACE before launching anything.  The cp_workspace_size_*
+ *     queries give the bytes a call needs.
  *
  * Execution: calls are enqueued on the handle's HIP stream.  Calls that return a report
  * synchronise that stream once before returning.  One handle per host thread.
@@ -50,7 +53,8 @@ typedef enum {
     CP_ERR_SHAPE = 2,        /* dimensions, ranks or sizes inconsistent / too big */
     CP_ERR_UNSUPPORTED = 3,  /* valid request that the library does not implement */
     CP_ERR_HIP = 4,          /* HIP runtime error (allocation, launch, copy)      */
-    CP_ERR_NOT_CONVERGED = 5 /* soft: results written, report.flags says why      */
+    CP_ERR_NOT_CONVERGED = 5, /* soft: results written, report.flags says why     */
+    CP_ERR_WORKSPACE = 6     /* the caller's workspace (cp_set_workspace) is too small */
 } cp_status;
 
 /* report.flags bits */
@@ -67,6 +71,12 @@ typedef struct cp_handle_s* cp_handle;
  * NULL = the null stream). */
 cp_status cp_create(cp_handle* handle, void* hip_stream);
 cp_status cp_destroy(cp_handle handle);
+/* Caller-owned device workspace: `dev_ptr` (256-byte aligned, `bytes` long) is used by
+ * every later call on the handle in place of library-allocated memory, until the next
+ * cp_set_workspace; (NULL, 0) returns to the library's own workspace.  The buffer must stay
+ * allocated while calls on the handle may run; calls that overlap on one buffer race.
+ * INVALID_ARG for a misaligned pointer or a null pointer with nonzero bytes. */
+cp_status cp_set_workspace(cp_handle handle, void* dev_ptr, size_t bytes);
 cp_status cp_set_stream(cp_handle handle, void* hip_stream);
 const char* cp_last_error(cp_handle handle);
 /* Largest number of workgroups that may advance one problem together (default 16; 1 keeps
@@ -119,37 +129,67 @@ typedef struct {
 } cp_operator;
 
 typedef enum { CP_PREC_FP64 = 0, CP_PREC_MIXED = 1 } cp_precision;
+typedef enum { CP_RANK_FIXED = 0, CP_RANK_ADAPTIVE = 1 } cp_rank_mode;
 
 /* ALS options.
  *  tol          : stop when eps_conv = max_q ||Delta f_q|| / ||f|| <= tol after a sweep
  *                 (increment test of Section 3.1 / Appendix B, on the represented tensor)
- *  max_sweeps   : cap on Gauss-Seidel sweeps per time step (>= 1)
+ *  max_sweeps   : cap on Gauss-Seidel sweeps per solve (>= 1)
+ *  precision    : CP_PREC_FP64, or CP_PREC_MIXED (FP32 contractions, FP64 solves/checks)
  *  eps_reg      : every per-dimension system is shifted by
  *                 lambda_q = eps_reg * trace(M_q) / (n_q r)  (regularisation, Section 2.1)
  *  pcg_tol      : relative residual target of the per-dimension PCG solve
  *  pcg_max_iter : PCG iteration cap per dimension update
- *  precision    : CP_PREC_FP64, or CP_PREC_MIXED (FP32 contractions, FP64 solves/checks) */
+ *  rank_mode    : CP_RANK_FIXED: the rank of the guess is kept.  CP_RANK_ADAPTIVE: the
+ *                 separation rank is chosen per step (Section 4.1: adaptive rank up to a
+ *                 maximum): after a converged solve at rank r the step residual
+ *                 rho = ||A f - g|| / ||g|| (g = B f_n) is formed in double-double; while
+ *                 rho > tau_rank (or, when replay_rank >= 0, while r < replay_rank) and
+ *                 r < rank_cap, one term is appended -- three sweeps of rank-1 ALS fitting
+ *                 the residual tensor g - A f from a seeded start (SplitMix64 of `seed`,
+ *                 counter ((step*64 + r)*8 + k)*2^32 + i, 2u - 1 in every dimension k > 0)
+ *                 -- and the step is solved again at rank r + 1.  Terms of weight
+ *                 prod_k ||U_k[:, l]|| below 1e-14 of the largest are then dropped (the
+ *                 kept columns move to the front, in order).  Later steps start from f_n
+ *                 at its own rank.  Problems in adaptive mode run on one workgroup.
+ *  tau_rank, rank_cap, replay_rank, seed : see rank_mode (rank_cap <= CP_MAX_RANK; the
+ *                 output panels must hold rank_cap columns)
+ *  report_residual : 1: every step's rho (double-double) into report.rel_residual (the
+ *                 problem then runs on one workgroup); adaptive mode always reports it */
 typedef struct {
     double tol;
     int32_t max_sweeps;
+    int32_t precision;
     double eps_reg;
     double pcg_tol;
     int32_t pcg_max_iter;
-    int32_t precision;
+    int32_t rank_mode;
+    double tau_rank;
+    int32_t rank_cap;
+    int32_t replay_rank;
+    uint64_t seed;
+    int32_t report_residual;
+    int32_t reserved;
 } cp_als_opts;
 
 /* Per-step report (HOST memory, filled after the call's single stream synchronisation). */
 typedef struct {
-    int32_t sweeps;      /* sweeps performed                          */
-    int32_t pcg_iters;   /* PCG iterations summed over all updates     */
-    double eps_conv;     /* eps_conv after the last sweep             */
-    double fnorm;        /* ||f_{n+1}||                               */
-    uint32_t flags;      /* CP_FLAG_* bits                            */
+    int32_t sweeps;        /* sweeps performed (summed over the solves of the step)     */
+    int32_t pcg_iters;     /* PCG iterations summed over all updates                    */
+    double eps_conv;       /* eps_conv after the last sweep                             */
+    double fnorm;          /* ||f_{n+1}||                                               */
+    double rel_residual;   /* rho = ||A f_{n+1} - g|| / ||g|| in double-double, or -1   */
+                           /* when not formed (fixed rank without report_residual)      */
+    uint32_t flags;        /* CP_FLAG_* bits of the last solve                          */
+    int32_t final_rank;    /* rank of f_{n+1}                                           */
+    int32_t grown_rank;    /* rank before small terms were dropped (replay_rank value   */
+                           /* that reproduces this step's growth decisions)             */
     int32_t reserved;
 } cp_als_report;
 
-/* Fill `opts` with the defaults (tol 1e-8, max_sweeps 200, eps_reg 1e-10, pcg_tol 1e-14,
- * pcg_max_iter 100, FP64). */
+/* Fill `opts` with the defaults (tol 1e-8, max_sweeps 200, FP64, eps_reg 1e-10, pcg_tol
+ * 1e-14, pcg_max_iter 100, fixed rank, tau_rank 1e-6, rank_cap CP_MAX_RANK, replay_rank -1,
+ * seed 0, report_residual 0). */
 cp_status cp_als_default_opts(cp_als_opts* opts);
 
 /* <x, y> = sum_{l,l'} prod_k <X_k[:,l], Y_k[:,l']>  (scalar product of CP tensors,
@@ -168,6 +208,8 @@ cp_status cp_apply_operator(cp_handle h, const cp_operator* L, const cp_tensor* 
  * (eqs. rRr1, resnorm) by Gauss-Seidel ALS over q = 1..d (eqs. sequential_min, ALS2).
  * f_next is in/out: on entry the initial guess (rank r = f_next.r), on exit f_{n+1}.
  * The columns of the result are balanced (equal factor norms per column).
+ * With opts.rank_mode = CP_RANK_ADAPTIVE the panels of f_next hold opts.rank_cap columns;
+ * on return f_next->r is the final rank (report.final_rank).
  * Returns CP_ERR_NOT_CONVERGED (results still written) if max_sweeps was reached. */
 cp_status cp_als_step(cp_handle h, const cp_operator* A, const cp_operator* B, const cp_tensor* f_n,
                       cp_tensor* f_next, const cp_als_opts* opts, cp_als_report* report);
@@ -175,41 +217,40 @@ cp_status cp_als_step(cp_handle h, const cp_operator* A, const cp_operator* B, c
 /* The implicit step with a source term, A f_{n+1} = B f_n + c (the time step of Section 3.1
  * with the source of the paper's forced equations, already scaled, e.g. c = dt C).  c is a
  * CP tensor (device panels owned by the caller, same d and n_k as f_n; null: cp_als_step).
- * The right-hand side g = B f_n + c is formed on the device as one CP tensor (the applied
- * terms of B f_n, as cp_apply_operator, followed by c's columns) and the step
+ * The right-hand side g = B f_n + c is formed in the workspace as one CP tensor (the
+ * applied terms of B f_n, as cp_apply_operator, followed by c's columns) and the step
  * A f_{n+1} = g is solved as cp_als_step does (same options, report and errors).  Requires
- * n_terms(B) * f_n.r + c.r <= CP_MAX_RANK; the call allocates and frees that tensor. */
+ * n_terms(B) * f_n.r + c.r <= CP_MAX_RANK. */
 cp_status cp_als_step_source(cp_handle h, const cp_operator* A, const cp_operator* B, const cp_tensor* f_n,
                              const cp_tensor* source, cp_tensor* f_next, const cp_als_opts* opts,
                              cp_als_report* report);
 
 /* Relative residual of the implicit step, rho = ||A f - B f_n|| / ||B f_n|| (the residual
- * of Section 3.2 that drives rank control), from three scalar products of the applied CP
- * tensors on the device: <Af, Af> - 2 <Af, Bf_n> + <Bf_n, Bf_n>.  The difference cancels, so
- * rho below ~1e-7 is resolved only to that level.  Written to *rel_residual (host); the call
- * allocates and frees the applied tensors and synchronises the stream. */
+ * of eqs. rRr1 / resnorm that drives rank control, Section 3.2).  Formed on the device in
+ * double-double: the Grams of the stacked applied panels [O_A^a U_k | O_B^b V_k] by
+ * compensated dot products (Dot2), their Hadamard products over the dimensions and the sum
+ * over all term pairs in double-double, so rho is resolved down to ~1e-15 (a plain FP64
+ * expansion <Af,Af> - 2<Af,Bf_n> + <Bf_n,Bf_n> cancels below ~1e-8).  One workgroup.
+ * Written to *rel_residual (host) after one stream synchronisation. */
 cp_status cp_residual(cp_handle h, const cp_operator* A, const cp_operator* B, const cp_tensor* f,
                       const cp_tensor* f_n, double* rel_residual);
 
-/* The implicit step with adaptive rank (Section 3.2: the separation rank grows until the
- * residual meets the tolerance).  f_next has capacity f_next->r = cap columns; its first
- * r_start columns are the initial guess.  The step is solved at rank r = r_start; while
- * rho > tau and r < cap, one term is added (seeded values in every dimension but the first,
- * zero there, so the represented tensor is unchanged until the first dimension's next
- * update sizes it) and the step is solved again from the current factors.  Terms of weight
- * prod_k ||U_k[:, l]|| below 1e-14 of the largest are then dropped (the kept columns move
- * to the front).  Output: the factors in the first *final_rank columns, *rel_residual the
- * last rho, report: the last solve's report with sweeps and pcg_iters summed over all
- * solves.  Errors as cp_als_step; CP_ERR_INVALID_ARG unless 1 <= r_start <= cap, tau >= 0. */
+/* cp_als_step with opts.rank_mode = CP_RANK_ADAPTIVE, opts.tau_rank = tau and
+ * opts.rank_cap = f_next->r: the panels of f_next hold f_next->r columns, the first r_start
+ * of them are the initial guess.  Output: the factors in the first *final_rank columns,
+ * *rel_residual the last rho (double-double).  Errors as cp_als_step; CP_ERR_INVALID_ARG
+ * unless 1 <= r_start <= f_next->r and tau >= 0. */
 cp_status cp_als_step_adaptive(cp_handle h, const cp_operator* A, const cp_operator* B, const cp_tensor* f_n,
                                cp_tensor* f_next, int32_t r_start, double tau, const cp_als_opts* opts,
                                cp_als_report* report, int32_t* final_rank, double* rel_residual);
 
 /* n_steps implicit steps in one device-resident launch: f_0 = f_init, guess for step s is
- * f_{s-1} (the first step uses f_io as guess, which must have rank == cap), result f_{n_steps}
- * written to f_io.  reports: host array of n_steps.  traj (nullable): device buffer of
- * n_steps * sum_k n_k * r doubles receiving every step's factors, packed dimension after
- * dimension, column-major. */
+ * f_{s-1} (the first step uses f_io as guess), result f_{n_steps} written to f_io.
+ * reports: host array of n_steps.  traj (nullable): device buffer of
+ * n_steps * sum_k n_k * rc doubles (rc = f_io.r, or opts.rank_cap in adaptive mode)
+ * receiving every step's factors, packed dimension after dimension, column-major n_k x rc
+ * (in adaptive mode the first final_rank columns of each step are valid).  Adaptive mode:
+ * f_io's panels hold opts.rank_cap columns; on return f_io->r is the last step's rank. */
 cp_status cp_als_run(cp_handle h, const cp_operator* A, const cp_operator* B, const cp_tensor* f_init,
                      cp_tensor* f_io, int32_t n_steps, const cp_als_opts* opts, cp_als_report* reports,
                      double* traj);
@@ -221,8 +262,10 @@ cp_status cp_truncate(cp_handle h, const cp_tensor* g, cp_tensor* f, const cp_al
 
 /* Many independent problems advanced in one persistent launch (one workgroup per problem, or
  * the tuned cluster sizes: see cp_tune_cluster).
- * Arrays of length count: A[i], B[i] (host descriptions), f_init[i], f_io[i] as in
- * cp_als_run; reports: count * n_steps entries, problem-major. */
+ * Arrays of length count: A[i], B[i] (host descriptions), f_init[i], f_io[i] and opts[i]
+ * (each problem has its own options: tolerance, rank mode and cap) as in cp_als_run;
+ * reports: count * n_steps entries, problem-major.  In adaptive mode f_io[i].r is updated to
+ * problem i's final rank. */
 cp_status cp_als_run_batched(cp_handle h, int32_t count, const cp_operator* A, const cp_operator* B,
                              const cp_tensor* f_init, cp_tensor* f_io, int32_t n_steps,
                              const cp_als_opts* opts, cp_als_report* reports);
@@ -231,7 +274,7 @@ cp_status cp_als_run_batched(cp_handle h, int32_t count, const cp_operator* A, c
  * stepping, launched as a HIP graph).
  *
  * cp_batch_plan_create validates and packs the count problems exactly as cp_als_run_batched
- * (same arguments), uploads their operator data once into device memory owned by the plan,
+ * (same arguments, opts[count]), uploads their operator data once into device memory owned by the plan,
  * and captures one run into a graph on a stream of the plan's own: copies of the f_init[i]
  * and f_io[i] panels into the plan, the persistent kernel, the results back into f_io[i],
  * the reports into pinned host memory of the plan.  The graph keeps the device pointers of
@@ -240,7 +283,8 @@ cp_status cp_als_run_batched(cp_handle h, int32_t count, const cp_operator* A, c
  *
  * cp_batch_plan_run replays the graph after the work already queued on the handle's stream
  * and waits for it; reports: count * n_steps entries, problem-major, as cp_als_run_batched
- * (and the same CP_ERR_NOT_CONVERGED rule).  A plan is used by one thread at a time.
+ * (and the same CP_ERR_NOT_CONVERGED rule; in adaptive mode the final ranks are in the
+ * reports, the f_io descriptors given at creation are not updated).  A plan is used by one thread at a time.
  * cp_batch_plan_destroy waits for the plan's stream and frees everything the plan owns.
  * Errors: those of cp_als_run_batched; CP_ERR_HIP when the capture or instantiation fails. */
 typedef struct cp_batch_plan_s* cp_batch_plan;
@@ -258,8 +302,8 @@ cp_status cp_batch_plan_destroy(cp_batch_plan plan);
  * cp_tune_cluster times `sweeps` sweeps (tol 0) of the implicit step of Section 3.1 for f_n
  * from guess with every admissible W (each once to warm up, then timed with HIP events on the
  * handle's stream), records the fastest in the table and returns it in *best_w and its time
- * in *best_ms (nullable).  guess is left untouched (trials run on a copy the call allocates
- * and frees).
+ * in *best_ms (nullable).  guess is left untouched (trials run on a copy of it in the
+ * workspace).
  * Use of the table: a single problem (cp_als_step, cp_als_run, a plan of one problem) runs
  * with its tuned W when one is recorded, else with the largest admissible W.  A batch
  * (cp_als_run_batched, cp_batch_plan_create) gives every problem its tuned W (1 where none
@@ -274,6 +318,24 @@ cp_status cp_tune_cluster(cp_handle h, const cp_operator* A, const cp_operator* 
 cp_status cp_tune_save(cp_handle h, const char* path);
 cp_status cp_tune_load(cp_handle h, const char* path);
 cp_status cp_tune_clear(cp_handle h);
+
+/* Workspace sizes (bytes) for a caller-owned workspace (cp_set_workspace).  Arguments as in
+ * the calls they size; nothing is launched.
+ *  cp_workspace_size_step  : cp_als_run / cp_als_step (n_steps = 1) with these shapes and
+ *                            options, and with source non-null cp_als_step_source; also
+ *                            enough for cp_residual(A, B, f_io, f_init), cp_tune_cluster and
+ *                            cp_als_step_adaptive on f_io
+ *  cp_workspace_size_batched : cp_als_run_batched with these arguments
+ *  cp_workspace_size_inner : cp_inner(x, y) and cp_norm(x) (pass y = x)
+ *  cp_workspace_size_apply : cp_apply_operator(L, x, .) */
+cp_status cp_workspace_size_step(cp_handle h, const cp_operator* A, const cp_operator* B, const cp_tensor* f_init,
+                                 const cp_tensor* source, const cp_tensor* f_io, int32_t n_steps,
+                                 const cp_als_opts* opts, size_t* bytes);
+cp_status cp_workspace_size_batched(cp_handle h, int32_t count, const cp_operator* A, const cp_operator* B,
+                                    const cp_tensor* f_init, const cp_tensor* f_io, int32_t n_steps,
+                                    const cp_als_opts* opts, size_t* bytes);
+cp_status cp_workspace_size_inner(cp_handle h, const cp_tensor* x, const cp_tensor* y, size_t* bytes);
+cp_status cp_workspace_size_apply(cp_handle h, const cp_operator* L, const cp_tensor* x, size_t* bytes);
 
 #ifdef __cplusplus
 }

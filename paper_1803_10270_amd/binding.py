@@ -21,9 +21,10 @@ LIB_PATH = os.path.join(HERE, "libcpals.so")
 CP_MAX_DIMS = 8
 CP_MAX_OPS = 4
 
-CP_OK, CP_ERR_INVALID_ARG, CP_ERR_SHAPE, CP_ERR_UNSUPPORTED, CP_ERR_HIP, CP_ERR_NOT_CONVERGED = range(6)
+CP_OK, CP_ERR_INVALID_ARG, CP_ERR_SHAPE, CP_ERR_UNSUPPORTED, CP_ERR_HIP, CP_ERR_NOT_CONVERGED, CP_ERR_WORKSPACE = range(7)
 FLAG_NOT_CONVERGED, FLAG_PCG_MAXITER, FLAG_REGULARIZED, FLAG_NONFINITE, FLAG_SYNC_TIMEOUT = 1, 2, 4, 8, 16
 PREC_FP64, PREC_MIXED = 0, 1
+RANK_FIXED, RANK_ADAPTIVE = 0, 1
 OP_KIND = {"identity": 0, "diag": 1, "band": 2, "rank1": 3}
 
 
@@ -42,17 +43,22 @@ class cp_operator(C.Structure):
 
 
 class cp_als_opts(C.Structure):
-    _fields_ = [("tol", C.c_double), ("max_sweeps", C.c_int32), ("eps_reg", C.c_double),
-                ("pcg_tol", C.c_double), ("pcg_max_iter", C.c_int32), ("precision", C.c_int32)]
+    _fields_ = [("tol", C.c_double), ("max_sweeps", C.c_int32), ("precision", C.c_int32),
+                ("eps_reg", C.c_double), ("pcg_tol", C.c_double), ("pcg_max_iter", C.c_int32),
+                ("rank_mode", C.c_int32), ("tau_rank", C.c_double), ("rank_cap", C.c_int32),
+                ("replay_rank", C.c_int32), ("seed", C.c_uint64), ("report_residual", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class cp_als_report(C.Structure):
     _fields_ = [("sweeps", C.c_int32), ("pcg_iters", C.c_int32), ("eps_conv", C.c_double),
-                ("fnorm", C.c_double), ("flags", C.c_uint32), ("reserved", C.c_int32)]
+                ("fnorm", C.c_double), ("rel_residual", C.c_double), ("flags", C.c_uint32),
+                ("final_rank", C.c_int32), ("grown_rank", C.c_int32), ("reserved", C.c_int32)]
 
     def as_dict(self):
         return {"sweeps": self.sweeps, "pcg_iters": self.pcg_iters, "eps_conv": self.eps_conv,
-                "fnorm": self.fnorm, "flags": self.flags}
+                "fnorm": self.fnorm, "rel_residual": self.rel_residual, "flags": self.flags,
+                "final_rank": self.final_rank, "grown_rank": self.grown_rank}
 
 
 class CpalsError(RuntimeError):
@@ -74,6 +80,13 @@ def lib() -> C.CDLL:
         P = C.POINTER
         sigs = {
             "cp_create": [P(H), C.c_void_p], "cp_destroy": [H], "cp_set_stream": [H, C.c_void_p],
+            "cp_set_workspace": [H, C.c_void_p, C.c_size_t],
+            "cp_workspace_size_step": [H, P(cp_operator), P(cp_operator), P(cp_tensor), P(cp_tensor), P(cp_tensor),
+                                       C.c_int32, P(cp_als_opts), P(C.c_size_t)],
+            "cp_workspace_size_batched": [H, C.c_int32, P(cp_operator), P(cp_operator), P(cp_tensor), P(cp_tensor),
+                                          C.c_int32, P(cp_als_opts), P(C.c_size_t)],
+            "cp_workspace_size_inner": [H, P(cp_tensor), P(cp_tensor), P(C.c_size_t)],
+            "cp_workspace_size_apply": [H, P(cp_operator), P(cp_tensor), P(C.c_size_t)],
             "cp_set_cluster": [H, C.c_int32],
             "cp_inner": [H, P(cp_tensor), P(cp_tensor), C.c_void_p],
             "cp_norm": [H, P(cp_tensor), C.c_void_p],
@@ -136,8 +149,9 @@ def to_host(T) -> List[np.ndarray]:
     return [t.detach().cpu().numpy().T.copy() for t in T]
 
 
-def tensor_desc(T) -> cp_tensor:
-    """List of (r, n_k) float64 CUDA tensors -> cp_tensor (column-major n_k x r panels)."""
+def tensor_desc(T, rank: Optional[int] = None) -> cp_tensor:
+    """List of (r, n_k) float64 CUDA tensors -> cp_tensor (column-major n_k x r panels);
+    `rank` (<= r) describes only the first `rank` columns."""
     import torch
     desc = cp_tensor()
     desc.d = len(T)
@@ -150,6 +164,10 @@ def tensor_desc(T) -> cp_tensor:
         desc.n[k] = int(t.shape[1])
         desc.ld[k] = int(t.shape[1])
         desc.U[k] = t.data_ptr()
+    if rank is not None:
+        if not 1 <= rank <= desc.r:
+            raise ValueError("rank must be in 1..%d" % desc.r)
+        desc.r = int(rank)
     return desc
 
 
@@ -208,6 +226,15 @@ class Handle:
         """Workgroups that may share one problem (1 = one workgroup per problem)."""
         self.check(lib().cp_set_cluster(self.h, int(max_workgroups)))
 
+    def set_workspace(self, buf) -> None:
+        """Use the caller's device buffer (a CUDA tensor, kept alive here) as the workspace;
+        None returns to the library's own."""
+        self._ws = buf
+        if buf is None:
+            self.check(lib().cp_set_workspace(self.h, None, 0))
+        else:
+            self.check(lib().cp_set_workspace(self.h, C.c_void_p(buf.data_ptr()), buf.numel() * buf.element_size()))
+
     def close(self):
         if self.h:
             lib().cp_destroy(self.h)
@@ -247,11 +274,14 @@ def cp_apply_operator(h: Handle, L, x, y) -> None:
     h.check(lib().cp_apply_operator(h.h, C.byref(Ld.desc), C.byref(xd), C.byref(yd)))
 
 
-def cp_als_step(h: Handle, A, B, f_n, f_next, opts: Optional[cp_als_opts] = None) -> dict:
-    """One implicit step; f_next is in/out (guess in, solution out).  Returns the report."""
+def cp_als_step(h: Handle, A, B, f_n, f_next, opts: Optional[cp_als_opts] = None, rank: Optional[int] = None,
+                f_n_rank: Optional[int] = None) -> dict:
+    """One implicit step; f_next is in/out (guess in, solution out).  Returns the report.
+    Adaptive rank: f_next's panels hold opts.rank_cap columns and the first `rank` are the
+    guess; the report's final_rank says how many hold the result."""
     opts = default_opts() if opts is None else opts
     Ad, Bd = OperatorDesc(A), OperatorDesc(B)
-    fd, gd = tensor_desc(f_n), tensor_desc(f_next)
+    fd, gd = tensor_desc(f_n, f_n_rank), tensor_desc(f_next, rank)
     rep = cp_als_report()
     h.check(lib().cp_als_step(h.h, C.byref(Ad.desc), C.byref(Bd.desc), C.byref(fd), C.byref(gd), C.byref(opts),
                               C.byref(rep)), allow_not_converged=True)
@@ -259,12 +289,13 @@ def cp_als_step(h: Handle, A, B, f_n, f_next, opts: Optional[cp_als_opts] = None
 
 
 def cp_als_run(h: Handle, A, B, f_init, f_io, n_steps: int, opts: Optional[cp_als_opts] = None,
-               traj=None) -> List[dict]:
+               traj=None, rank: Optional[int] = None, f_init_rank: Optional[int] = None) -> List[dict]:
     """n_steps implicit steps in one launch; f_io in/out.  traj: optional float64 CUDA buffer of
-    n_steps * sum_k n_k r elements receiving every step's factors."""
+    n_steps * sum_k n_k r elements receiving every step's factors (r = the panels' columns).
+    rank / f_init_rank: the guess and f_init use only their first columns (adaptive rank)."""
     opts = default_opts() if opts is None else opts
     Ad, Bd = OperatorDesc(A), OperatorDesc(B)
-    fd, gd = tensor_desc(f_init), tensor_desc(f_io)
+    fd, gd = tensor_desc(f_init, f_init_rank), tensor_desc(f_io, rank)
     reps = (cp_als_report * n_steps)()
     if traj is not None:
         import torch
@@ -285,18 +316,31 @@ def cp_truncate(h: Handle, g, f, opts: Optional[cp_als_opts] = None) -> dict:
     return rep.as_dict()
 
 
-def cp_als_run_batched(h: Handle, As, Bs, f_inits, f_ios, n_steps: int,
-                       opts: Optional[cp_als_opts] = None) -> List[List[dict]]:
-    opts = default_opts() if opts is None else opts
+def _opts_array(opts, count):
+    """One cp_als_opts per problem from None, a single struct or a list of them."""
+    if opts is None:
+        opts = default_opts()
+    if isinstance(opts, cp_als_opts):
+        opts = [opts] * count
+    if len(opts) != count:
+        raise ValueError("need one cp_als_opts per problem")
+    return (cp_als_opts * count)(*opts)
+
+
+def cp_als_run_batched(h: Handle, As, Bs, f_inits, f_ios, n_steps: int, opts=None,
+                       ranks: Optional[Sequence[int]] = None) -> List[List[dict]]:
+    """opts: one cp_als_opts for all problems or a list (one each); ranks: guess ranks
+    (adaptive rank: the panels hold opts[i].rank_cap columns)."""
     count = len(As)
+    o_arr = _opts_array(opts, count)
     Ads = [OperatorDesc(a) for a in As]
     Bds = [OperatorDesc(b) for b in Bs]
     A_arr = (cp_operator * count)(*[a.desc for a in Ads])
     B_arr = (cp_operator * count)(*[b.desc for b in Bds])
     fi = (cp_tensor * count)(*[tensor_desc(f) for f in f_inits])
-    fo = (cp_tensor * count)(*[tensor_desc(f) for f in f_ios])
+    fo = (cp_tensor * count)(*[tensor_desc(f, None if ranks is None else ranks[i]) for i, f in enumerate(f_ios)])
     reps = (cp_als_report * (count * n_steps))()
-    h.check(lib().cp_als_run_batched(h.h, count, A_arr, B_arr, fi, fo, n_steps, C.byref(opts), reps),
+    h.check(lib().cp_als_run_batched(h.h, count, A_arr, B_arr, fi, fo, n_steps, o_arr, reps),
             allow_not_converged=True)
     return [[reps[i * n_steps + s].as_dict() for s in range(n_steps)] for i in range(count)]
 
@@ -312,10 +356,10 @@ def cp_als_step_source(h: Handle, A, B, f_n, source, f_next, opts: Optional[cp_a
     return rep.as_dict()
 
 
-def cp_residual(h: Handle, A, B, f, f_n) -> float:
-    """||A f - B f_n|| / ||B f_n|| on the device."""
+def cp_residual(h: Handle, A, B, f, f_n, f_rank: Optional[int] = None, f_n_rank: Optional[int] = None) -> float:
+    """||A f - B f_n|| / ||B f_n|| on the device (double-double)."""
     Ad, Bd = OperatorDesc(A), OperatorDesc(B)
-    fd, nd = tensor_desc(f), tensor_desc(f_n)
+    fd, nd = tensor_desc(f, f_rank), tensor_desc(f_n, f_n_rank)
     out = C.c_double(0.0)
     h.check(lib().cp_residual(h.h, C.byref(Ad.desc), C.byref(Bd.desc), C.byref(fd), C.byref(nd), C.byref(out)))
     return float(out.value)
@@ -351,6 +395,35 @@ def cp_tune_cluster(h: Handle, A, B, f_n, guess, opts: Optional[cp_als_opts] = N
     return int(w.value), float(ms.value)
 
 
+def workspace_size_step(h: Handle, A, B, f_init, f_io, n_steps: int = 1, opts: Optional[cp_als_opts] = None,
+                        source=None, rank: Optional[int] = None) -> int:
+    """Bytes of workspace cp_als_run / cp_als_step (/ cp_als_step_source with `source`) need."""
+    opts = default_opts() if opts is None else opts
+    Ad, Bd = OperatorDesc(A), OperatorDesc(B)
+    fd, gd = tensor_desc(f_init), tensor_desc(f_io, rank)
+    sd = tensor_desc(source) if source is not None else None
+    out = C.c_size_t(0)
+    h.check(lib().cp_workspace_size_step(h.h, C.byref(Ad.desc), C.byref(Bd.desc), C.byref(fd),
+                                         C.byref(sd) if sd is not None else None, C.byref(gd), n_steps, C.byref(opts),
+                                         C.byref(out)))
+    return int(out.value)
+
+
+def workspace_size_inner(h: Handle, x, y) -> int:
+    out = C.c_size_t(0)
+    xd, yd = tensor_desc(x), tensor_desc(y)
+    h.check(lib().cp_workspace_size_inner(h.h, C.byref(xd), C.byref(yd), C.byref(out)))
+    return int(out.value)
+
+
+def workspace_size_apply(h: Handle, L, x) -> int:
+    out = C.c_size_t(0)
+    Ld = OperatorDesc(L)
+    xd = tensor_desc(x)
+    h.check(lib().cp_workspace_size_apply(h.h, C.byref(Ld.desc), C.byref(xd), C.byref(out)))
+    return int(out.value)
+
+
 def cp_tune_save(h: Handle, path: str):
     h.check(lib().cp_tune_save(h.h, path.encode()))
 
@@ -368,9 +441,9 @@ class BatchPlan:
     must stay allocated while the plan lives; run() replays the captured run on their current
     contents (results into f_ios) and returns the reports."""
 
-    def __init__(self, h: Handle, As, Bs, f_inits, f_ios, n_steps: int, opts: Optional[cp_als_opts] = None):
-        opts = default_opts() if opts is None else opts
+    def __init__(self, h: Handle, As, Bs, f_inits, f_ios, n_steps: int, opts=None):
         self.h, self.count, self.n_steps = h, len(As), n_steps
+        o_arr = _opts_array(opts, self.count)
         self._keep = (list(f_inits), list(f_ios))
         Ads = [OperatorDesc(a) for a in As]
         Bds = [OperatorDesc(b) for b in Bs]
@@ -379,7 +452,7 @@ class BatchPlan:
         fi = (cp_tensor * self.count)(*[tensor_desc(f) for f in f_inits])
         fo = (cp_tensor * self.count)(*[tensor_desc(f) for f in f_ios])
         self.plan = C.c_void_p()
-        h.check(lib().cp_batch_plan_create(h.h, self.count, A_arr, B_arr, fi, fo, n_steps, C.byref(opts),
+        h.check(lib().cp_batch_plan_create(h.h, self.count, A_arr, B_arr, fi, fo, n_steps, o_arr,
                                            C.byref(self.plan)))
 
     def run(self) -> List[List[dict]]:

@@ -37,17 +37,24 @@ def compile_flags():
 
 
 def build(verbose: bool = False) -> str:
-    objs = []
+    from concurrent.futures import ThreadPoolExecutor
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
     cc = hipcc()
+    cmds = []
+    objs = []
     for src in SOURCES:
         obj = os.path.join(objdir, src.replace(".hip", ".o"))
-        cmd = [cc, *compile_flags(), "-c", os.path.join(CSRC, src), "-o", obj]
-        if verbose:
-            print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True)
+        cmds.append([cc, *compile_flags(), "-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
+    if verbose:
+        for cmd in cmds:
+            print(" ".join(cmd), flush=True)
+    # the translation units are independent: compile them side by side
+    with ThreadPoolExecutor(max_workers=len(cmds)) as ex:
+        for res in ex.map(lambda c: subprocess.run(c, capture_output=not verbose), cmds):
+            if res.returncode != 0:
+                raise RuntimeError("hipcc failed:\n%s" % ((res.stderr or b"").decode(errors="replace")))
     tmp = LIB + ".tmp"
     cmd = [cc, "--offload-arch=" + ARCH, "-shared", "-fPIC", *objs, "-o", tmp]
     if verbose:

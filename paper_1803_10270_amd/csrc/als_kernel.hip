@@ -22,6 +22,7 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <type_traits>
+#include "dd_device.h"
 #include "device_common.h"
 #include "mfma_f64.h"
 
@@ -47,6 +48,7 @@ struct Smem {
     double red[2 * NWAVES];
     double dots[CP_MAX_OPS * CP_MAX_OPS * CP_MAX_RANK];
     double colnorm[CP_MAX_DIMS * CP_MAX_RANK];
+    double gnrm[CP_MAX_DIMS];    // rank growth: t_k^T t_k
     double scratch[SCRATCH];
     PairRec pairs[LDS_PAIRS];
     StageSlot slots[(CP_MAX_DIMS - 1) * CP_MAX_OPS * CP_MAX_OPS];
@@ -1386,9 +1388,311 @@ __device__ __forceinline__ void scale_grams(int r0) {
 }
 
 // ------------------------------------------------------------------------------------
+// Step residual in double-double, rank growth and term dropping (adaptive rank).  A
+// problem that needs them runs on one workgroup, so every routine below covers all rows.
+// ------------------------------------------------------------------------------------
+
+// Columns of the stacked panel Z_k = [P_k | Q_k] of dimension k at ranks (r, r0): the
+// applied panel P_k = [O_A^a U_k]_a (in pb.P, formed by apply_panel) and Q_k = [O_B^b V_k]_b.
+__device__ __forceinline__ int stacked_cols(int k, int r, int r0) {
+    const Problem& pb = SMEM.pb;
+    return pb.mA[k] * r + pb.mB[k] * r0;
+}
+
+__device__ __forceinline__ const double* stacked_col(int k, int c, int r) {
+    const Problem& pb = SMEM.pb;
+    const int n = pb.n[k], M1 = pb.mA[k] * r;
+    return c < M1 ? pb.P + (int64_t)c * n : pb.Q + pb.offQ[k] + (int64_t)(c - M1) * n;
+}
+
+// Rdd_k[i + j N] = Z_k[:, i]^T Z_k[:, j] by compensated dot products (Dot2), stored as
+// (hi, lo).  Rows are staged through LDS in chunks (column c at Zs[c ld + j]); every thread
+// keeps EB entries over all rows.  P_k must have been formed.
+__device__ __forceinline__ void gram_dd(int k, int r, int r0) {
+    Smem& s = SMEM;
+    const Problem& pb = s.pb;
+    const int n = pb.n[k], N = stacked_cols(k, r, r0);
+    const int RB = min(64, SCRATCH / N - 1);
+    const int ld = RB + 1;
+    double* Zs = s.scratch;
+    double* out = pb.Rdd + 2 * pb.offR[k];
+    constexpr int EB = 8;
+    const int NN = N * N;
+    const float invN = __frcp_rn((float)N);
+    for (int e0 = 0; e0 < NN; e0 += EB * WG) {
+        double sh[EB], sc[EB];
+        int ei[EB], ej[EB];
+#pragma unroll
+        for (int u = 0; u < EB; ++u) {
+            sh[u] = sc[u] = 0.0;
+            const int e = min(e0 + tid_here() + u * WG, NN - 1);
+            ej[u] = fdiv(e, invN);
+            ei[u] = e - ej[u] * N;
+        }
+        for (int i0 = 0; i0 < n; i0 += RB) {
+            const int nr = min(RB, n - i0);
+            const float invnr = __frcp_rn((float)nr);
+            __syncthreads();
+            batched_loop<8>(
+                nr * N,
+                [&](int t) {
+                    const int c = fdiv(t, invnr);
+                    return ldg(stacked_col(k, c, r) + i0 + (t - c * nr));
+                },
+                [&](int t, double v) {
+                    const int c = fdiv(t, invnr);
+                    Zs[c * ld + (t - c * nr)] = v;
+                });
+            __syncthreads();
+            for (int j = 0; j < nr; ++j) {
+#pragma unroll
+                for (int u = 0; u < EB; ++u) dot2_step(Zs[ei[u] * ld + j], Zs[ej[u] * ld + j], sh[u], sc[u]);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < EB; ++u) {
+            const int e = e0 + tid_here() + u * WG;
+            if (e < NN) {
+                const dd v = dot2_result(sh[u], sc[u]);
+                stg(out + 2 * (int64_t)e, v.hi);
+                stg(out + 2 * (int64_t)e + 1, v.lo);
+            }
+        }
+    }
+    __syncthreads();
+}
+
+// Workgroup sum of two dd values in a fixed order (every thread gets the result).
+__device__ __forceinline__ void wg_sum_dd2(dd& a, dd& b) {
+    Smem& s = SMEM;
+    const int lane = tid_here() & 63, wave = tid_here() >> 6;
+    a = dd_wave_sum(a);
+    b = dd_wave_sum(b);
+    __syncthreads();
+    if (lane == 0) {
+        s.scratch[4 * wave + 0] = a.hi;
+        s.scratch[4 * wave + 1] = a.lo;
+        s.scratch[4 * wave + 2] = b.hi;
+        s.scratch[4 * wave + 3] = b.lo;
+    }
+    __syncthreads();
+    dd x{0.0, 0.0}, y{0.0, 0.0};
+    for (int w = 0; w < NWAVES; ++w) {
+        x = dd_add(x, dd{s.scratch[4 * w + 0], s.scratch[4 * w + 1]});
+        y = dd_add(y, dd{s.scratch[4 * w + 2], s.scratch[4 * w + 3]});
+    }
+    __syncthreads();
+    a = x;
+    b = y;
+}
+
+// rho = ||A f - g|| / ||g||, g = B f_n, f the factors U at rank r, f_n the factors V at rank
+// r0 (Q must hold [O_B^b V_k]_b).  The residual is the CP tensor with the stacked terms
+//   s < TA:  eta_e  prod_k O_A^{a(e,k)} U_k      (width r, columns a(e,k) r of Z_k)
+//   s >= TA: -zeta_z prod_k O_B^{b(z,k)} V_k     (width r0, columns mA_k r + b(z,k) r0)
+// so ||R||^2 = sum_{s,s'} c_s c_s' sum_{l,l'} prod_k Rdd_k[col(s,k) + l, col(s',k) + l'],
+// every product and sum in double-double; ||g||^2 is the part with s, s' >= TA.
+__device__ __forceinline__ double step_residual(int r, int r0) {
+    Smem& s = SMEM;
+    const Problem& pb = s.pb;
+    const int d = pb.d;
+    for (int k = 0; k < d; ++k) {
+        const int n = pb.n[k];
+        apply_panel(pb.opA[k], pb.mA[k], n, r, pb.U + pb.offU[k], pb.P, 0, n);
+        gram_dd(k, r, r0);
+    }
+    const int TA = pb.TA, S = pb.TA + pb.TB;
+    // stacked-term table in LDS: coefficient, width, first column per dimension
+    double* coefS = s.scratch + 64;
+    int32_t* colS = reinterpret_cast<int32_t*>(coefS + S);
+    for (int t = tid_here(); t < S; t += WG) {
+        const PairRec* tr = t < TA ? pb.termA + t : pb.termB + (t - TA);
+        coefS[t] = t < TA ? ldg(&tr->coef) : -ldg(&tr->coef);
+        const uint64_t sw = (uint64_t)__double_as_longlong(ldg(reinterpret_cast<const double*>(tr) + 1));
+        for (int k = 0; k < d; ++k) {
+            const int a = (int)((sw >> (8 * k)) & 0xffu);
+            colS[t * CP_MAX_DIMS + k] = t < TA ? a * r : pb.mA[k] * r + a * r0;
+        }
+    }
+    __syncthreads();
+    dd num{0.0, 0.0}, den{0.0, 0.0};
+    for (int sa = 0; sa < S; ++sa) {
+        const int wa = sa < TA ? r : r0;
+        for (int sb = 0; sb < S; ++sb) {
+            const int wb = sb < TA ? r : r0;
+            const double ca = coefS[sa], cb = coefS[sb];
+            const bool gpart = sa >= TA && sb >= TA;
+            const float inva = __frcp_rn((float)wa);
+            for (int p = tid_here(); p < wa * wb; p += WG) {
+                const int lp = fdiv(p, inva), l = p - lp * wa;
+                dd prod{1.0, 0.0};
+                for (int k = 0; k < d; ++k) {
+                    const int N = stacked_cols(k, r, r0);
+                    const int64_t e = (int64_t)(colS[sa * CP_MAX_DIMS + k] + l) +
+                                      (int64_t)(colS[sb * CP_MAX_DIMS + k] + lp) * N;
+                    const double* g = pb.Rdd + 2 * (pb.offR[k] + e);
+                    prod = dd_mul(prod, dd{ldg(g), ldg(g + 1)});
+                }
+                prod = dd_mul_d(dd_mul_d(prod, ca), cb);
+                num = dd_add(num, prod);
+                if (gpart) den = dd_add(den, prod);
+            }
+        }
+    }
+    wg_sum_dd2(num, den);
+    const double nv = fmax(num.hi + num.lo, 0.0), dv = den.hi + den.lo;
+    return dv > 0.0 ? sqrt(nv / dv) : sqrt(nv);
+}
+
+// SplitMix64 (Steele, Lea & Flood, OOPSLA 2014) in counter form: the output for the state
+// seed + (counter + 1) * gamma.
+__device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t counter) {
+    uint64_t z = seed + (counter + 1ull) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// cv_k = t_k^T Z_k (one wave per column, rows strided by lane) and gnrm[k] = t_k^T t_k;
+// P_k must hold dimension k's applied panel.
+__device__ __forceinline__ void growth_contract(int k, int r, int r0) {
+    Smem& s = SMEM;
+    const Problem& pb = s.pb;
+    const int n = pb.n[k], N = stacked_cols(k, r, r0);
+    const int lane = tid_here() & 63, wave = tid_here() >> 6;
+    const double* t = pb.tv + pb.offT[k];
+    double* cv = pb.cv + pb.offCv[k];
+    for (int c = wave; c <= N; c += NWAVES) {
+        const double* z = c < N ? stacked_col(k, c, r) : t;
+        double acc = 0.0;
+        for (int i = lane; i < n; i += 64) acc = fma(ldg(t + i), ldg(z + i), acc);
+        acc = wave_sum(acc);
+        if (lane == 0) {
+            if (c < N) stg(cv + c, acc);
+            else s.gnrm[k] = acc;
+        }
+    }
+    __syncthreads();
+}
+
+// The term appended when the rank grows from r: three sweeps of rank-1 ALS fitting the
+// residual tensor R = g - A f (g = B f_n), from the seeded start
+// t_k[i] = 2 u - 1, u = splitmix64(seed, ((step 64 + r) 8 + k) 2^32 + i) / 2^64 (top 53 bits),
+// k > 0 (dimension 0 is updated first, so its start is never read).  Update of dimension q:
+//   t_q = (sum_c Z_q[:, c] beta[c]) / prod_{k != q} t_k^T t_k, with
+//   beta[a r + l]          = -sum_{e: a(e,q) = a} eta_e  prod_{k != q} cv_k[a(e,k) r + l]
+//   beta[mA r + b r0 + l0] =  sum_{z: b(z,q) = b} zeta_z prod_{k != q} cv_k[mA_k r + b(z,k) r0 + l0]
+// (the exact minimiser of ||R - t|| over t_q).  The result becomes column r of every U_k.
+__device__ __forceinline__ void grow_term(int step, int r, int r0) {
+    Smem& s = SMEM;
+    const Problem& pb = s.pb;
+    const int d = pb.d;
+    for (int k = 0; k < d; ++k) {
+        double* t = pb.tv + pb.offT[k];
+        const uint64_t base = (((uint64_t)step * 64u + (uint64_t)r) * 8u + (uint64_t)k) << 32;
+        for (int i = tid_here(); i < pb.n[k]; i += WG) {
+            double v = 0.0;
+            if (k > 0) v = 2.0 * ((double)(splitmix64(pb.seed, base + (uint64_t)i) >> 11) * 0x1.0p-53) - 1.0;
+            stg(t + i, v);
+        }
+    }
+    __syncthreads();
+    for (int k = 1; k < d; ++k) {
+        apply_panel(pb.opA[k], pb.mA[k], pb.n[k], r, pb.U + pb.offU[k], pb.P, 0, pb.n[k]);
+        growth_contract(k, r, r0);
+    }
+    const int TA = pb.TA, TB = pb.TB;
+    for (int sweep = 0; sweep < 3; ++sweep) {
+        for (int q = 0; q < d; ++q) {
+            const int n = pb.n[q], N = stacked_cols(q, r, r0), M1 = pb.mA[q] * r;
+            double* beta = s.scratch;
+            for (int c = tid_here(); c < N; c += WG) {
+                const bool aside = c < M1;
+                const int blk = aside ? c / r : (c - M1) / r0;
+                const int l = aside ? c - blk * r : (c - M1) - blk * r0;
+                const int T = aside ? TA : TB;
+                double acc = 0.0;
+                for (int e = 0; e < T; ++e) {
+                    const PairRec* tr = aside ? pb.termA + e : pb.termB + e;
+                    const uint64_t sw = (uint64_t)__double_as_longlong(ldg(reinterpret_cast<const double*>(tr) + 1));
+                    if ((int)((sw >> (8 * q)) & 0xffu) != blk) continue;
+                    double prod = ldg(&tr->coef);
+                    for (int k = 0; k < d; ++k) {
+                        if (k == q) continue;
+                        const int a = (int)((sw >> (8 * k)) & 0xffu);
+                        const int col = aside ? a * r + l : pb.mA[k] * r + a * r0 + l;
+                        prod *= ldg(pb.cv + pb.offCv[k] + col);
+                    }
+                    acc += prod;
+                }
+                beta[c] = aside ? -acc : acc;
+            }
+            double nn = 1.0;
+            for (int k = 0; k < d; ++k)
+                if (k != q) nn *= s.gnrm[k];
+            apply_panel(pb.opA[q], pb.mA[q], n, r, pb.U + pb.offU[q], pb.P, 0, n);   // ends with a barrier
+            double* t = pb.tv + pb.offT[q];
+            const double inv = nn > 0.0 ? 1.0 / nn : 0.0;
+            for (int i = tid_here(); i < n; i += WG) {
+                double acc = 0.0;
+                for (int c = 0; c < N; ++c) acc = fma(ldg(stacked_col(q, c, r) + i), beta[c], acc);
+                stg(t + i, nn > 0.0 ? acc * inv : 0.0);
+            }
+            __syncthreads();
+            growth_contract(q, r, r0);
+        }
+    }
+    // column r of every factor
+    for (int k = 0; k < d; ++k) {
+        const double* t = pb.tv + pb.offT[k];
+        double* u = pb.U + pb.offU[k] + (int64_t)r * pb.n[k];
+        for (int i = tid_here(); i < pb.n[k]; i += WG) stg(u + i, ldg(t + i));
+    }
+    __syncthreads();
+}
+
+// Drops the terms of weight prod_k ||U_k[:, l]|| below 1e-14 of the largest (rank
+// reduction of Section 3.2); the kept columns move to the front in order, at least one is
+// kept.  Returns the new rank.
+__device__ __forceinline__ int drop_small_terms(int r) {
+    Smem& s = SMEM;
+    const Problem& pb = s.pb;
+    const int d = pb.d;
+    panel_colnorms();
+    int32_t* keep = reinterpret_cast<int32_t*>(s.scratch);
+    if (tid_here() == 0) {
+        auto weight = [&](int l) {
+            double p = 1.0;
+            for (int k = 0; k < d; ++k) p *= s.colnorm[k * r + l];
+            return p;
+        };
+        double wmax = 0.0;
+        for (int l = 0; l < r; ++l) wmax = fmax(wmax, weight(l));
+        int kept = 0;
+        for (int l = 0; l < r; ++l)
+            if (!(wmax > 0.0) || weight(l) >= 1e-14 * wmax) keep[1 + kept++] = l;
+        if (kept == 0) keep[1 + kept++] = 0;
+        keep[0] = kept;
+    }
+    __syncthreads();
+    const int kept = keep[0];
+    for (int j = 0; j < kept; ++j) {
+        const int l = keep[1 + j];
+        if (l == j) continue;
+        for (int k = 0; k < d; ++k) {
+            const int n = pb.n[k];
+            double* u = pb.U + pb.offU[k];
+            for (int i = tid_here(); i < n; i += WG) stg(u + i + (int64_t)j * n, ldg(u + i + (int64_t)l * n));
+        }
+        __syncthreads();
+    }
+    return kept;
+}
+
+// ------------------------------------------------------------------------------------
 // the persistent kernel
 // ------------------------------------------------------------------------------------
-enum : int { OP_STEP, OP_REFRESH, OP_UPDATE, OP_CG, OP_DELTA, OP_SWEEP, OP_REPORT, OP_DONE };
+enum : int { OP_STEP, OP_REFRESH, OP_UPDATE, OP_CG, OP_DELTA, OP_SWEEP, OP_RANK, OP_REPORT, OP_DONE };
 // phases of one dimension update's composite products
 enum : int { PH_RHS, PH_PRE_B, PH_MV_X, PH_PRE_R0, PH_MV_P0, PH_PRE_R, PH_MV_P };
 
@@ -1433,7 +1737,8 @@ __global__ void __launch_bounds__(WG) als_persistent(const Problem* __restrict__
     }
     __syncthreads();
     const Problem& pb = s.pb;
-    const int d = ufirst(pb.d), r = ufirst(pb.r);
+    const int d = ufirst(pb.d);
+    int r = ufirst(pb.r);   // the current rank (changes only in adaptive mode)
     const int n_steps = ufirst(pb.n_steps), max_sweeps = ufirst(pb.max_sweeps);
     const bool mixed = pb.precision == CP_PREC_MIXED;
     // mixed-precision form: sweeps with FP32 contractions until the increment reaches the
@@ -1451,6 +1756,16 @@ __global__ void __launch_bounds__(WG) als_persistent(const Problem* __restrict__
     double eps_low_min = 1e300;   // smallest increment of the FP32 sweeps of this step
     int low_stall = 0;            // FP32 sweeps since that minimum last improved
     int psel = 0;   // which of the two search-direction buffers holds p
+    int sweeps_done = 0;          // sweeps of the earlier solves of this step (rank growth)
+    int grown = r;                // rank before the drop of negligible terms
+    double rho = -1.0;            // step residual (when formed)
+    // the current rank into the LDS descriptor, which the routines read
+    auto set_rank = [&](int rn) {
+        __syncthreads();
+        if (tid_here() == 0) s.pb.r = rn;
+        __syncthreads();
+        r = ufirst(rn);
+    };
 
     while (op != OP_DONE) {
         op = ufirst(op);
@@ -1458,11 +1773,14 @@ __global__ void __launch_bounds__(WG) als_persistent(const Problem* __restrict__
             // a cluster barrier timed out: the problem is abandoned with a flag
             if (cpart == 0 && tid_here() == 0) {
                 cp_als_report rep;
-                rep.sweeps = sw;
+                rep.sweeps = sweeps_done + sw;
                 rep.pcg_iters = pcg_iters;
                 rep.eps_conv = eps;
                 rep.fnorm = fnorm;
+                rep.rel_residual = -1.0;
                 rep.flags = flags | CP_FLAG_NOT_CONVERGED | CP_FLAG_SYNC_TIMEOUT;
+                rep.final_rank = r;
+                rep.grown_rank = r;
                 rep.reserved = 0;
                 pb.reports[step < n_steps ? step : n_steps - 1] = rep;
             }
@@ -1490,6 +1808,8 @@ __global__ void __launch_bounds__(WG) als_persistent(const Problem* __restrict__
             eps_low_min = 1e300;
             low_stall = 0;
             pcg_iters = 0;
+            sweeps_done = 0;
+            rho = -1.0;
             flags = CP_FLAG_NOT_CONVERGED;
             eps = fnorm = dmax2 = 0.0;
             sw = 1;
@@ -1700,7 +2020,7 @@ __global__ void __launch_bounds__(WG) als_persistent(const Problem* __restrict__
                 done = true;   // the single FP64 refinement sweep is done
             }
             if (done || sw >= max_sweeps) {
-                op = OP_REPORT;
+                op = pb.report_residual ? OP_RANK : OP_REPORT;
             } else {
                 ++sw;
                 q = 0;
@@ -1714,28 +2034,63 @@ __global__ void __launch_bounds__(WG) als_persistent(const Problem* __restrict__
                     op = OP_UPDATE;
                 }
             }
+        } else if (op == OP_RANK) {
+            // the step residual (double-double); adaptive rank: grow while it is above tau
+            // (or below the replayed rank), else drop the negligible terms
+            rho = step_residual(r, r0);
+            const bool adapt = pb.rank_mode == CP_RANK_ADAPTIVE;
+            const bool want = pb.replay_rank >= 0 ? r < pb.replay_rank : rho > pb.tau_rank;
+            if (adapt && want && r < pb.rcap && !(flags & CP_FLAG_NONFINITE)) {
+                grow_term(step, r, r0);
+                set_rank(r + 1);
+                sweeps_done += sw;
+                // solve again from the current factors (the new column balanced with the rest)
+                panel_colnorms();
+                balance_scales();
+                scale_panels(true);
+                lowp = mixed && max_sweeps > 1;
+                eps_low_min = 1e300;
+                low_stall = 0;
+                flags = CP_FLAG_NOT_CONVERGED;
+                eps = fnorm = dmax2 = 0.0;
+                sw = 1;
+                q = 0;
+                k = 0;
+                k_end = d;
+                after = OP_UPDATE;
+                op = OP_REFRESH;
+            } else {
+                grown = r;
+                if (adapt) set_rank(drop_small_terms(r));
+                op = OP_REPORT;
+            }
         } else {   // OP_REPORT
             if (cpart == 0 && tid_here() == 0) {
                 cp_als_report rep;
-                rep.sweeps = sw;
+                rep.sweeps = sweeps_done + sw;
                 rep.pcg_iters = pcg_iters;
                 rep.eps_conv = eps;
                 rep.fnorm = fnorm;
+                rep.rel_residual = rho;
                 rep.flags = flags;
+                rep.final_rank = r;
+                rep.grown_rank = pb.report_residual ? grown : r;
                 rep.reserved = 0;
                 pb.reports[step] = rep;
             }
             if (pb.traj && cpart == 0) {
+                // step s at traj + s sum_k n_k rcap, dimension after dimension (n_k x rcap,
+                // the first r columns written)
                 double* dst = pb.traj + (int64_t)step * [&] {
                     int64_t tot = 0;
-                    for (int kk = 0; kk < d; ++kk) tot += (int64_t)pb.n[kk] * r;
+                    for (int kk = 0; kk < d; ++kk) tot += (int64_t)pb.n[kk] * pb.rcap;
                     return tot;
                 }();
                 int64_t o = 0;
                 for (int kk = 0; kk < d; ++kk) {
                     const int64_t cnt = (int64_t)pb.n[kk] * r;
                     for (int64_t t = tid_here(); t < cnt; t += WG) stg(dst + o + t, ldg(pb.U + pb.offU[kk] + t));
-                    o += cnt;
+                    o += (int64_t)pb.n[kk] * pb.rcap;
                 }
             }
             __syncthreads();
@@ -1743,6 +2098,52 @@ __global__ void __launch_bounds__(WG) als_persistent(const Problem* __restrict__
             op = (step < n_steps) ? OP_STEP : OP_DONE;
         }
     }
+}
+
+// The step residual alone (cp_residual): U holds f, V holds f_n; one workgroup.
+__global__ void __launch_bounds__(WG) residual_kernel(const Problem* __restrict__ problem) {
+    Smem& s = SMEM;
+    {
+        const uint32_t* src = reinterpret_cast<const uint32_t*>(problem);
+        uint32_t* dst = reinterpret_cast<uint32_t*>(&s.pb);
+        for (int t = tid_here(); t < (int)(sizeof(Problem) / 4); t += WG) dst[t] = src[t];
+        if (tid_here() == 0) {
+            s.ident.kind = CP_OP_IDENTITY;
+            s.ident.hbw = 0;
+            s.ident.data = nullptr;
+            s.part = 0;
+            s.W = 1;
+            s.bar_target = 0;
+            s.sync_ok = 1;
+            s.dcount = 0;
+            s.kc_key[0] = s.kc_key[1] = nullptr;
+        }
+    }
+    __syncthreads();
+    const Problem& pb = s.pb;
+    compute_Q_all(pb.r0);
+    const double rho = step_residual(pb.r, pb.r0);
+    if (tid_here() == 0) {
+        cp_als_report rep;
+        rep.sweeps = 0;
+        rep.pcg_iters = 0;
+        rep.eps_conv = 0.0;
+        rep.fnorm = 0.0;
+        rep.rel_residual = rho;
+        rep.flags = 0;
+        rep.final_rank = pb.r;
+        rep.grown_rank = pb.r;
+        rep.reserved = 0;
+        pb.reports[0] = rep;
+    }
+}
+
+hipError_t launch_residual(const Problem* d_problem, hipStream_t stream) {
+    hipError_t e = hipFuncSetAttribute((const void*)residual_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)sizeof(Smem));
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(residual_kernel, dim3(1), dim3(WG), sizeof(Smem), stream, d_problem);
+    return hipGetLastError();
 }
 
 size_t als_smem_bytes() { return sizeof(Smem); }

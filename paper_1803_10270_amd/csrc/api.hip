@@ -26,6 +26,7 @@ hipError_t prepare_als();
 hipError_t launch_als_prepared(const Problem* d_problems, int count, int W, const int32_t* wg_first, int total_wg,
                                hipStream_t stream);
 size_t als_smem_bytes();
+hipError_t launch_residual(const Problem* d_problem, hipStream_t stream);
 }  // namespace cpals
 
 using namespace cpals;
@@ -41,6 +42,7 @@ struct cp_handle_s {
     std::string err;
     void* ws = nullptr;
     size_t ws_bytes = 0;
+    bool ws_user = false;     // ws is the caller's (cp_set_workspace): never reallocated
 };
 
 namespace {
@@ -64,8 +66,14 @@ cp_status hip_fail(cp_handle h, hipError_t e, const char* what) {
         if (e_ != hipSuccess) return hip_fail(h, e_, what); \
     } while (0)
 
+// The handle's workspace holds at least `bytes`.  A library-owned workspace grows (the
+// stream is drained first: its old contents are not kept); a caller-owned one is never
+// reallocated, and a request beyond its size is CP_ERR_WORKSPACE.
 cp_status ensure_ws(cp_handle h, size_t bytes) {
     if (bytes <= h->ws_bytes) return CP_OK;
+    if (h->ws_user)
+        return fail(h, CP_ERR_WORKSPACE, "workspace too small: the call needs " + std::to_string(bytes) +
+                                             " bytes, cp_set_workspace gave " + std::to_string(h->ws_bytes));
     HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
     if (h->ws) {
         HIP_TRY(hipFree(h->ws), "hipFree");
@@ -77,6 +85,12 @@ cp_status ensure_ws(cp_handle h, size_t bytes) {
     h->ws_bytes = sz;
     return CP_OK;
 }
+
+bool adaptive(const cp_als_opts& o) { return o.rank_mode == CP_RANK_ADAPTIVE; }
+// the problem forms its step residual on the device (and then runs on one workgroup)
+bool with_residual(const cp_als_opts& o) { return adaptive(o) || o.report_residual != 0; }
+// columns every panel of the problem holds
+int rank_capacity(const cp_tensor& f_io, const cp_als_opts& o) { return adaptive(o) ? o.rank_cap : f_io.r; }
 
 cp_status check_tensor(cp_handle h, const cp_tensor* t, const char* name, int max_n) {
     if (!t) return fail(h, CP_ERR_INVALID_ARG, std::string(name) + " is null");
@@ -346,16 +360,18 @@ cp_status compose_t(cp_handle h, const cp_op1d& a, const cp_op1d& b, CompOp& out
 // Byte layout of one problem's device region.
 struct Layout {
     size_t problem, opdata, pairsC, pairsD, U, V, Q, G, X, P, Z, Cm, Dm, H0, Hinv, S, vec, reports, bar, gpart, spart, dpart,
-        total;
+        termA, termB, Rdd, tv, cv, total;
     size_t n_opdata, n_pairsC, n_pairsD;
     int64_t offU[CP_MAX_DIMS], offV[CP_MAX_DIMS], offQ[CP_MAX_DIMS], offG[CP_MAX_DIMS], offX[CP_MAX_DIMS];
-    int nmax, mAmax, mBmax, r0max;
+    int64_t offR[CP_MAX_DIMS], offT[CP_MAX_DIMS], offCv[CP_MAX_DIMS];
+    int nmax, mAmax, mBmax, r0max, rc;
 };
 
 struct Packed {
     Problem pb;
     std::vector<double> opdata;
     std::vector<PairRec> pairsC, pairsD;
+    std::vector<PairRec> termA, termB;   // the operators' terms (residual, growth)
     Layout lay;
     // host op data pointers in the same order as opdata, to rebase
     std::vector<std::pair<int, int>> opref;  // (side*CP_MAX_DIMS + k, a)
@@ -364,6 +380,8 @@ struct Packed {
 cp_status pack_problem(cp_handle h, const HostOp& A, const HostOp& B, const cp_tensor* f_init, const cp_tensor* f_io,
                        int n_steps, const cp_als_opts& o, int W, Packed& pk) {
     const int d = f_io->d, r = f_io->r, r0 = f_init->r;
+    const int rc = rank_capacity(*f_io, o);   // every panel holds rc columns
+    if (r > rc) return fail(h, CP_ERR_SHAPE, "the guess has more columns than rank_cap");
     Problem& pb = pk.pb;
     std::memset(&pb, 0, sizeof(pb));
     pb.d = d;
@@ -374,7 +392,8 @@ cp_status pack_problem(cp_handle h, const HostOp& A, const HostOp& B, const cp_t
     L.nmax = 0;
     L.mAmax = 0;
     L.mBmax = 0;
-    L.r0max = (n_steps > 1) ? std::max(r0, r) : r0;
+    L.rc = rc;
+    L.r0max = (n_steps > 1) ? std::max(r0, rc) : r0;
     for (int k = 0; k < d; ++k) {
         pb.n[k] = f_io->n[k];
         pb.mA[k] = A.m[k];
@@ -482,42 +501,70 @@ cp_status pack_problem(cp_handle h, const HostOp& A, const HostOp& B, const cp_t
     L.opdata = take(pk.opdata.size() * sizeof(double));
     L.pairsC = take(pk.pairsC.size() * sizeof(PairRec));
     L.pairsD = take(pk.pairsD.size() * sizeof(PairRec));
-    size_t nU = 0, nV = 0, nQ = 0, nG = 0, nX = 0;
+    size_t nU = 0, nV = 0, nQ = 0, nG = 0, nX = 0, nR = 0, nT = 0, nC = 0;
+    const bool res = with_residual(o);
     for (int k = 0; k < d; ++k) {
         L.offU[k] = (int64_t)nU;
-        nU += (size_t)pb.n[k] * r;
+        nU += (size_t)pb.n[k] * rc;
         L.offV[k] = (int64_t)nV;
         nV += (size_t)pb.n[k] * L.r0max;
         L.offQ[k] = (int64_t)nQ;
         nQ += (size_t)pb.n[k] * B.m[k] * L.r0max;
         L.offG[k] = (int64_t)nG;
-        nG += (size_t)(A.m[k] * r) * (A.m[k] * r);
+        nG += (size_t)(A.m[k] * rc) * (A.m[k] * rc);
         L.offX[k] = (int64_t)nX;
-        nX += (size_t)(A.m[k] * r) * (B.m[k] * L.r0max);
+        nX += (size_t)(A.m[k] * rc) * (B.m[k] * L.r0max);
+        // residual / growth: the stacked panel [P_k | Q_k] has mA rc + mB r0max columns
+        const size_t Nk = (size_t)A.m[k] * rc + (size_t)B.m[k] * L.r0max;
+        L.offR[k] = (int64_t)nR;
+        L.offT[k] = (int64_t)nT;
+        L.offCv[k] = (int64_t)nC;
+        if (res) {
+            nR += Nk * Nk;
+            nT += (size_t)pb.n[k];
+            nC += Nk;
+        }
     }
     L.U = take(nU * 8);
     L.V = take(nV * 8);
     L.Q = take(nQ * 8);
     L.G = take(nG * 8);
     L.X = take(nX * 8);
-    L.P = take((size_t)L.nmax * L.mAmax * r * 8);
-    L.Z = take((size_t)L.nmax * L.mAmax * r * 8);
-    L.Cm = take((size_t)(L.mAmax * r) * (L.mAmax * r) * 8);
-    L.Dm = take((size_t)(L.mAmax * r) * (L.mBmax * L.r0max) * 8);
-    L.H0 = take((size_t)r * r * 8);
-    L.Hinv = take((size_t)W * r * r * 8);
-    L.S = take((size_t)r * r * 8);
-    L.vec = take((size_t)7 * align_up((size_t)L.nmax * r * 8));
+    L.P = take((size_t)L.nmax * L.mAmax * rc * 8);
+    L.Z = take((size_t)L.nmax * L.mAmax * rc * 8);
+    L.Cm = take((size_t)(L.mAmax * rc) * (L.mAmax * rc) * 8);
+    L.Dm = take((size_t)(L.mAmax * rc) * (L.mBmax * L.r0max) * 8);
+    L.H0 = take((size_t)rc * rc * 8);
+    L.Hinv = take((size_t)W * rc * rc * 8);
+    L.S = take((size_t)rc * rc * 8);
+    L.vec = take((size_t)7 * align_up((size_t)L.nmax * rc * 8));
     L.reports = take((size_t)n_steps * sizeof(cp_als_report));
     size_t psz = 0;
     for (int k = 0; k < d; ++k)
-        psz = std::max(psz, (size_t)(A.m[k] * r) * (A.m[k] * r) + (size_t)(A.m[k] * r) * (B.m[k] * L.r0max));
+        psz = std::max(psz, (size_t)(A.m[k] * rc) * (A.m[k] * rc) + (size_t)(A.m[k] * rc) * (B.m[k] * L.r0max));
     pb.W = W;
     pb.psz = (int32_t)psz;
     L.bar = take(256);
     L.gpart = take(W > 1 ? (size_t)W * psz * 8 : 8);
-    L.spart = take(W > 1 ? (size_t)W * r * r * 8 : 8);
+    L.spart = take(W > 1 ? (size_t)W * rc * rc * 8 : 8);
     L.dpart = take((size_t)2 * W * 8 * 8);
+    // terms of A and B (coefficient, op index per dimension)
+    pk.termA.assign(A.T, PairRec{});
+    pk.termB.assign(B.T, PairRec{});
+    for (int side = 0; side < 2; ++side) {
+        const HostOp& X = side == 0 ? A : B;
+        std::vector<PairRec>& out = side == 0 ? pk.termA : pk.termB;
+        for (int e = 0; e < X.T; ++e) {
+            std::memset(&out[e], 0, sizeof(PairRec));
+            out[e].coef = X.coef[e];
+            for (int k = 0; k < d; ++k) out[e].slot[k] = (uint8_t)X.idx[(size_t)e * d + k];
+        }
+    }
+    L.termA = take((size_t)A.T * sizeof(PairRec));
+    L.termB = take((size_t)B.T * sizeof(PairRec));
+    L.Rdd = take(std::max<size_t>(nR, 1) * 16);
+    L.tv = take(std::max<size_t>(nT, 1) * 8);
+    L.cv = take(std::max<size_t>(nC, 1) * 8);
     L.total = off;
     L.n_opdata = pk.opdata.size();
     L.n_pairsC = pk.pairsC.size();
@@ -529,6 +576,14 @@ cp_status pack_problem(cp_handle h, const HostOp& A, const HostOp& B, const cp_t
     pb.max_sweeps = o.max_sweeps;
     pb.pcg_max = o.pcg_max_iter;
     pb.precision = o.precision;
+    pb.rcap = rc;
+    pb.rank_mode = o.rank_mode;
+    pb.replay_rank = adaptive(o) ? o.replay_rank : -1;
+    pb.report_residual = res ? 1 : 0;
+    pb.tau_rank = o.tau_rank;
+    pb.seed = o.seed;
+    pb.TA = A.T;
+    pb.TB = B.T;
     // op descriptors get device pointers at rebase time; remember offsets in elements
     for (int k = 0; k < d; ++k) {
         for (int i = 0; i < A.m[k] * A.m[k]; ++i) {
@@ -579,7 +634,15 @@ void rebase(Packed& pk, char* base, double* traj) {
         pb.offQ[k] = L.offQ[k];
         pb.offG[k] = L.offG[k];
         pb.offX[k] = L.offX[k];
+        pb.offR[k] = L.offR[k];
+        pb.offT[k] = L.offT[k];
+        pb.offCv[k] = L.offCv[k];
     }
+    pb.termA = reinterpret_cast<const PairRec*>(base + L.termA);
+    pb.termB = reinterpret_cast<const PairRec*>(base + L.termB);
+    pb.Rdd = reinterpret_cast<double*>(base + L.Rdd);
+    pb.tv = reinterpret_cast<double*>(base + L.tv);
+    pb.cv = reinterpret_cast<double*>(base + L.cv);
     pb.pairsC = reinterpret_cast<const PairRec*>(base + L.pairsC);
     pb.pairsD = reinterpret_cast<const PairRec*>(base + L.pairsD);
     pb.U = reinterpret_cast<double*>(base + L.U);
@@ -594,7 +657,7 @@ void rebase(Packed& pk, char* base, double* traj) {
     pb.H0 = reinterpret_cast<double*>(base + L.H0);
     pb.Hinv = reinterpret_cast<double*>(base + L.Hinv);
     pb.S = reinterpret_cast<double*>(base + L.S);
-    const size_t vstride = align_up((size_t)L.nmax * pb.r * 8);
+    const size_t vstride = align_up((size_t)L.nmax * L.rc * 8);
     char* vb = base + L.vec;
     pb.vb = reinterpret_cast<double*>(vb + 0 * vstride);
     pb.vx = reinterpret_cast<double*>(vb + 1 * vstride);
@@ -617,8 +680,16 @@ cp_status check_opts(cp_handle h, const cp_als_opts* o) {
         return fail(h, CP_ERR_INVALID_ARG, "bad ALS options");
     if (o->precision != CP_PREC_FP64 && o->precision != CP_PREC_MIXED)
         return fail(h, CP_ERR_INVALID_ARG, "bad precision");
+    if (o->rank_mode != CP_RANK_FIXED && o->rank_mode != CP_RANK_ADAPTIVE)
+        return fail(h, CP_ERR_INVALID_ARG, "bad rank_mode");
+    if (o->rank_mode == CP_RANK_ADAPTIVE &&
+        (!(o->tau_rank >= 0.0) || o->rank_cap < 1 || o->rank_cap > CP_MAX_RANK || o->replay_rank > CP_MAX_RANK))
+        return fail(h, CP_ERR_INVALID_ARG, "adaptive rank needs tau_rank >= 0 and 1 <= rank_cap <= CP_MAX_RANK");
+    if (o->report_residual != 0 && o->report_residual != 1)
+        return fail(h, CP_ERR_INVALID_ARG, "report_residual must be 0 or 1");
     return CP_OK;
 }
+
 
 cp_status copy_panels_in(cp_handle h, hipStream_t st, const cp_tensor* t, double* dst, const int64_t* off) {
     for (int k = 0; k < t->d; ++k)
@@ -703,11 +774,13 @@ std::string shape_key(const HostOp& A, const HostOp& B, const cp_tensor& f_init,
 // admissible), else the largest admissible.  Several problems: their tuned sizes (1 where
 // none is recorded), provided every workgroup of the launch fits on the device at once (a
 // cluster's workgroups wait for each other), else one workgroup each.
+// Problems that form their step residual (adaptive rank, report_residual) keep one workgroup.
 std::vector<int> choose_clusters(cp_handle h, int count, const HostOp* A, const HostOp* B, const cp_tensor* f_init,
-                                 const cp_tensor* f_io, const cp_als_opts& o) {
+                                 const cp_tensor* f_io, const cp_als_opts* o) {
     std::vector<int> W(count, 1);
     if (count == 1) {
-        auto it = h->tuned.find(shape_key(A[0], B[0], f_init[0], f_io[0], o));
+        if (with_residual(o[0])) return W;
+        auto it = h->tuned.find(shape_key(A[0], B[0], f_init[0], f_io[0], o[0]));
         W[0] = (it != h->tuned.end() && cluster_ok(h, A[0], B[0], f_io[0], it->second))
                    ? it->second : cluster_size(h, A[0], B[0], f_io[0]);
         return W;
@@ -715,8 +788,9 @@ std::vector<int> choose_clusters(cp_handle h, int count, const HostOp* A, const 
     if (h->tuned.empty()) return W;
     long total = 0;
     for (int i = 0; i < count; ++i) {
-        auto it = h->tuned.find(shape_key(A[i], B[i], f_init[i], f_io[i], o));
-        if (it != h->tuned.end() && cluster_ok(h, A[i], B[i], f_io[i], it->second)) W[i] = it->second;
+        auto it = h->tuned.find(shape_key(A[i], B[i], f_init[i], f_io[i], o[i]));
+        if (!with_residual(o[i]) && it != h->tuned.end() && cluster_ok(h, A[i], B[i], f_io[i], it->second))
+            W[i] = it->second;
         total += W[i];
     }
     if (total > h->n_cu) std::fill(W.begin(), W.end(), 1);
@@ -733,7 +807,7 @@ cp_status stage_problems(cp_handle h, int count, const HostOp* A, const HostOp* 
     S.base.resize(count);
     S.total = 0;
     for (int i = 0; i < count; ++i) {
-        cp_status st = pack_problem(h, A[i], B[i], &f_init[i], &f_io[i], n_steps, *o, W[i], S.pk[i]);
+        cp_status st = pack_problem(h, A[i], B[i], &f_init[i], &f_io[i], n_steps, o[i], W[i], S.pk[i]);
         if (st != CP_OK) return st;
         S.base[i] = S.total;
         S.total += align_up(S.pk[i].lay.total);
@@ -771,6 +845,12 @@ cp_status upload_static(cp_handle h, Staged& S, char* ws, double* traj, const cp
             HIP_TRY(hipMemcpyAsync(b + p.lay.pairsD, p.pairsD.data(), p.pairsD.size() * sizeof(PairRec),
                                    hipMemcpyHostToDevice, st),
                     "hipMemcpyAsync(pairsD)");
+        HIP_TRY(hipMemcpyAsync(b + p.lay.termA, p.termA.data(), p.termA.size() * sizeof(PairRec), hipMemcpyHostToDevice,
+                               st),
+                "hipMemcpyAsync(termA)");
+        HIP_TRY(hipMemcpyAsync(b + p.lay.termB, p.termB.data(), p.termB.size() * sizeof(PairRec), hipMemcpyHostToDevice,
+                               st),
+                "hipMemcpyAsync(termB)");
     }
     S.descs.resize(count);
     for (int j = 0; j < count; ++j) S.descs[j] = S.pk[order[j]].pb;
@@ -814,7 +894,11 @@ cp_status enqueue_run(cp_handle h, const Staged& S, const cp_tensor* f_init, cp_
                      : launch_als(S.d_desc, S.count, S.W[0], S.d_wg_first, S.total_wg, st),
             "als kernel launch");
     for (int i = 0; i < S.count; ++i) {
-        cp_status s2 = copy_panels_out(h, st, S.pk[i].pb.U, S.pk[i].pb.offU, &f_io[i]);
+        // every column the panels hold (in adaptive mode the final rank is known only from the
+        // reports; the columns past it are left over from the run)
+        cp_tensor out = f_io[i];
+        out.r = S.pk[i].lay.rc;
+        cp_status s2 = copy_panels_out(h, st, S.pk[i].pb.U, S.pk[i].pb.offU, &out);
         if (s2 != CP_OK) return s2;
         HIP_TRY(hipMemcpyAsync(rep + (size_t)i * S.n_steps, S.pk[i].pb.reports, (size_t)S.n_steps * sizeof(cp_als_report),
                                hipMemcpyDeviceToHost, st),
@@ -830,21 +914,36 @@ cp_status check_reports(cp_handle h, const cp_als_report* reports, int n) {
     return CP_OK;
 }
 
+// Packs, uploads and runs `count` problems (options o[i]) in the workspace from byte offset
+// `base` on; in adaptive mode f_io[i].r becomes the last step's rank.
 cp_status run_problems(cp_handle h, int count, const HostOp* A, const HostOp* B, const cp_tensor* f_init,
-                       cp_tensor* f_io, int n_steps, const cp_als_opts* o, cp_als_report* reports, double* traj) {
+                       cp_tensor* f_io, int n_steps, const cp_als_opts* o, cp_als_report* reports, double* traj,
+                       size_t base = 0) {
     // a problem may be shared by a cluster of workgroups (grid rows split between them)
     Staged S;
     cp_status st = stage_problems(h, count, A, B, f_init, f_io, n_steps, o,
-                                  choose_clusters(h, count, A, B, f_init, f_io, *o), S);
+                                  choose_clusters(h, count, A, B, f_init, f_io, o), S);
     if (st != CP_OK) return st;
-    st = ensure_ws(h, S.bytes);
+    st = ensure_ws(h, base + S.bytes);
     if (st != CP_OK) return st;
-    st = upload_static(h, S, static_cast<char*>(h->ws), traj, f_io, h->stream, false);
+    st = upload_static(h, S, static_cast<char*>(h->ws) + base, traj, f_io, h->stream, false);
     if (st != CP_OK) return st;
     st = enqueue_run(h, S, f_init, f_io, reports, h->stream);
     if (st != CP_OK) return st;
     HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+    for (int i = 0; i < count; ++i)
+        if (adaptive(o[i])) f_io[i].r = reports[(size_t)i * n_steps + n_steps - 1].final_rank;
     return check_reports(h, reports, count * n_steps);
+}
+
+// Workspace bytes of run_problems for these problems (nothing is launched).
+cp_status run_bytes(cp_handle h, int count, const HostOp* A, const HostOp* B, const cp_tensor* f_init,
+                    const cp_tensor* f_io, int n_steps, const cp_als_opts* o, size_t* bytes) {
+    Staged S;
+    cp_status st = stage_problems(h, count, A, B, f_init, f_io, n_steps, o,
+                                  choose_clusters(h, count, A, B, f_init, f_io, o), S);
+    if (st == CP_OK) *bytes = S.bytes;
+    return st;
 }
 
 cp_status prepare_step(cp_handle h, const cp_operator* A, const cp_operator* B, const cp_tensor* f_init,
@@ -859,6 +958,7 @@ cp_status prepare_step(cp_handle h, const cp_operator* A, const cp_operator* B, 
     if (n_steps < 1) return fail(h, CP_ERR_INVALID_ARG, "n_steps < 1");
     st = check_opts(h, opts);
     if (st != CP_OK) return st;
+    if (adaptive(*opts) && f_io->r > opts->rank_cap) return fail(h, CP_ERR_SHAPE, "f_io.r exceeds rank_cap");
     st = check_operator(h, A, "A", f_io->d, f_io->n, true, hA);
     if (st != CP_OK) return st;
     return check_operator(h, B, "B", f_io->d, f_io->n, false, hB);
@@ -897,11 +997,23 @@ cp_status cp_create(cp_handle* handle, void* hip_stream) {
 
 cp_status cp_destroy(cp_handle h) {
     if (!h) return CP_ERR_INVALID_ARG;
-    if (h->ws) {
+    if (h->ws && !h->ws_user) {
         (void)hipStreamSynchronize(h->stream);
         (void)hipFree(h->ws);
     }
     delete h;
+    return CP_OK;
+}
+
+cp_status cp_set_workspace(cp_handle h, void* dev_ptr, size_t bytes) {
+    if (!h) return CP_ERR_INVALID_ARG;
+    if ((!dev_ptr && bytes) || (reinterpret_cast<uintptr_t>(dev_ptr) % ALIGN) != 0)
+        return fail(h, CP_ERR_INVALID_ARG, "workspace must be a 256-byte aligned device pointer (or NULL, 0)");
+    HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+    if (h->ws && !h->ws_user) HIP_TRY(hipFree(h->ws), "hipFree");
+    h->ws = dev_ptr;
+    h->ws_bytes = dev_ptr ? bytes : 0;
+    h->ws_user = dev_ptr != nullptr;
     return CP_OK;
 }
 
@@ -922,24 +1034,32 @@ cp_status cp_set_cluster(cp_handle h, int32_t max_workgroups) {
 
 cp_status cp_als_default_opts(cp_als_opts* o) {
     if (!o) return CP_ERR_INVALID_ARG;
+    std::memset(o, 0, sizeof(*o));
     o->tol = 1e-8;
     o->max_sweeps = 200;
+    o->precision = CP_PREC_FP64;
     o->eps_reg = 1e-10;
     o->pcg_tol = 1e-14;
     o->pcg_max_iter = 100;
-    o->precision = CP_PREC_FP64;
+    o->rank_mode = CP_RANK_FIXED;
+    o->tau_rank = 1e-6;
+    o->rank_cap = CP_MAX_RANK;
+    o->replay_rank = -1;
+    o->seed = 0;
+    o->report_residual = 0;
     return CP_OK;
 }
 
-static cp_status inner_impl(cp_handle h, const cp_tensor* x, const cp_tensor* y, double* out_dev, bool sq) {
-    if (!h) return CP_ERR_INVALID_ARG;
+}  // extern "C"
+
+namespace {
+
+cp_status inner_job(cp_handle h, const cp_tensor* x, const cp_tensor* y, GramJob& job, int& nch) {
     cp_status st = check_tensor(h, x, "x", 1 << 28);
     if (st != CP_OK) return st;
     st = check_tensor(h, y, "y", 1 << 28);
     if (st != CP_OK) return st;
-    if (!out_dev) return fail(h, CP_ERR_INVALID_ARG, "out_dev is null");
     if (x->d != y->d) return fail(h, CP_ERR_SHAPE, "x and y differ in d");
-    GramJob job;
     std::memset(&job, 0, sizeof(job));
     job.d = x->d;
     job.rx = x->r;
@@ -952,60 +1072,84 @@ static cp_status inner_impl(cp_handle h, const cp_tensor* x, const cp_tensor* y,
         job.ldy[k] = y->ld[k];
         job.n[k] = x->n[k];
     }
-    const int nch = gram_chunks(job.n, job.d, job.chunk0, job.chunk_rows);
-    st = ensure_ws(h, (size_t)(nch + x->d) * x->r * y->r * 8 + 256);   // chunk partials, then the d Grams
-    if (st != CP_OK) return st;
-    HIP_TRY(launch_inner(job, static_cast<double*>(h->ws), out_dev, sq, h->stream), "inner launch");
+    nch = gram_chunks(job.n, job.d, job.chunk0, job.chunk_rows);
     return CP_OK;
 }
 
-cp_status cp_inner(cp_handle h, const cp_tensor* x, const cp_tensor* y, double* out_dev) {
-    return inner_impl(h, x, y, out_dev, false);
+// chunk partials, then the d Grams
+size_t inner_bytes(const GramJob& job, int nch) { return (size_t)(nch + job.d) * job.rx * job.ry * 8 + 256; }
+
+cp_status inner_impl(cp_handle h, const cp_tensor* x, const cp_tensor* y, double* out_dev, bool sq, size_t base) {
+    if (!h) return CP_ERR_INVALID_ARG;
+    if (!out_dev) return fail(h, CP_ERR_INVALID_ARG, "out_dev is null");
+    GramJob job;
+    int nch = 0;
+    cp_status st = inner_job(h, x, y, job, nch);
+    if (st != CP_OK) return st;
+    st = ensure_ws(h, base + inner_bytes(job, nch));
+    if (st != CP_OK) return st;
+    HIP_TRY(launch_inner(job, reinterpret_cast<double*>(static_cast<char*>(h->ws) + base), out_dev, sq, h->stream),
+            "inner launch");
+    return CP_OK;
 }
 
-cp_status cp_norm(cp_handle h, const cp_tensor* x, double* out_dev) { return inner_impl(h, x, x, out_dev, true); }
-
-cp_status cp_apply_operator(cp_handle h, const cp_operator* L, const cp_tensor* x, cp_tensor* y) {
-    if (!h) return CP_ERR_INVALID_ARG;
-    cp_status st = check_tensor(h, x, "x", 1 << 28);
-    if (st != CP_OK) return st;
-    if (!y) return fail(h, CP_ERR_INVALID_ARG, "y is null");
-    if (y->d != x->d) return fail(h, CP_ERR_SHAPE, "y.d != x.d");
-    HostOp hL;
-    st = check_operator(h, L, "L", x->d, x->n, false, hL);
-    if (st != CP_OK) return st;
-    if ((int64_t)y->r != (int64_t)hL.T * x->r) return fail(h, CP_ERR_SHAPE, "y.r must equal n_terms * x.r");
-    for (int k = 0; k < x->d; ++k) {
-        if (y->n[k] != x->n[k] || y->ld[k] < y->n[k] || !y->U[k]) return fail(h, CP_ERR_SHAPE, "bad y panel");
-    }
-    // upload op data, coef and op_index
+// Operator application: the operators' data, coefficients and term table go to the host blob
+// (uploaded to the workspace at `base`); the job's device pointers refer to that copy.
+struct ApplyPlan {
+    HostOp L;
     std::vector<double> blob;
     std::vector<size_t> offs[CP_MAX_DIMS];
-    for (int k = 0; k < x->d; ++k)
-        for (int a = 0; a < hL.m[k]; ++a) {
-            const cp_op1d& op = hL.ops[k][a];
-            offs[k].push_back(blob.size());
-            blob.insert(blob.end(), op.data, op.data + op_data_len(op));
-            while (blob.size() % 4) blob.push_back(0.0);
-        }
-    const size_t coef_off = blob.size();
-    blob.insert(blob.end(), hL.coef.begin(), hL.coef.end());
-    while (blob.size() % 4) blob.push_back(0.0);
-    const size_t idx_off_bytes = blob.size() * 8;
-    const size_t total = idx_off_bytes + hL.idx.size() * 4 + 256;
-    st = ensure_ws(h, total);
+    size_t coef_off = 0, idx_off_bytes = 0, bytes = 0;
+};
+
+cp_status apply_plan(cp_handle h, const cp_operator* L, const cp_tensor* x, const cp_tensor* y, ApplyPlan& P) {
+    cp_status st = check_tensor(h, x, "x", 1 << 28);
     if (st != CP_OK) return st;
-    char* ws = static_cast<char*>(h->ws);
-    HIP_TRY(hipMemcpyAsync(ws, blob.data(), blob.size() * 8, hipMemcpyHostToDevice, h->stream), "upload op data");
-    HIP_TRY(hipMemcpyAsync(ws + idx_off_bytes, hL.idx.data(), hL.idx.size() * 4, hipMemcpyHostToDevice, h->stream),
+    st = check_operator(h, L, "L", x->d, x->n, false, P.L);
+    if (st != CP_OK) return st;
+    if (y) {
+        if (y->d != x->d) return fail(h, CP_ERR_SHAPE, "y.d != x.d");
+        if ((int64_t)y->r != (int64_t)P.L.T * x->r) return fail(h, CP_ERR_SHAPE, "y.r must equal n_terms * x.r");
+        for (int k = 0; k < x->d; ++k)
+            if (y->n[k] != x->n[k] || y->ld[k] < y->n[k] || !y->U[k]) return fail(h, CP_ERR_SHAPE, "bad y panel");
+    }
+    P.blob.clear();
+    for (int k = 0; k < x->d; ++k) {
+        P.offs[k].clear();
+        for (int a = 0; a < P.L.m[k]; ++a) {
+            const cp_op1d& op = P.L.ops[k][a];
+            P.offs[k].push_back(P.blob.size());
+            P.blob.insert(P.blob.end(), op.data, op.data + op_data_len(op));
+            while (P.blob.size() % 4) P.blob.push_back(0.0);
+        }
+    }
+    P.coef_off = P.blob.size();
+    P.blob.insert(P.blob.end(), P.L.coef.begin(), P.L.coef.end());
+    while (P.blob.size() % 4) P.blob.push_back(0.0);
+    P.idx_off_bytes = P.blob.size() * 8;
+    P.bytes = P.idx_off_bytes + P.L.idx.size() * 4 + 256;
+    return CP_OK;
+}
+
+cp_status apply_impl(cp_handle h, const cp_operator* L, const cp_tensor* x, cp_tensor* y, size_t base) {
+    if (!h) return CP_ERR_INVALID_ARG;
+    if (!y) return fail(h, CP_ERR_INVALID_ARG, "y is null");
+    ApplyPlan P;
+    cp_status st = apply_plan(h, L, x, y, P);
+    if (st != CP_OK) return st;
+    st = ensure_ws(h, base + P.bytes);
+    if (st != CP_OK) return st;
+    char* ws = static_cast<char*>(h->ws) + base;
+    HIP_TRY(hipMemcpyAsync(ws, P.blob.data(), P.blob.size() * 8, hipMemcpyHostToDevice, h->stream), "upload op data");
+    HIP_TRY(hipMemcpyAsync(ws + P.idx_off_bytes, P.L.idx.data(), P.L.idx.size() * 4, hipMemcpyHostToDevice, h->stream),
             "upload op index");
     ApplyJob job;
     std::memset(&job, 0, sizeof(job));
     job.d = x->d;
     job.r = x->r;
-    job.n_terms = hL.T;
-    job.coef = reinterpret_cast<const double*>(ws) + coef_off;
-    job.op_index = reinterpret_cast<const int32_t*>(ws + idx_off_bytes);
+    job.n_terms = P.L.T;
+    job.coef = reinterpret_cast<const double*>(ws) + P.coef_off;
+    job.op_index = reinterpret_cast<const int32_t*>(ws + P.idx_off_bytes);
     int max_n = 0;
     for (int k = 0; k < x->d; ++k) {
         job.X[k] = x->U[k];
@@ -1014,10 +1158,10 @@ cp_status cp_apply_operator(cp_handle h, const cp_operator* L, const cp_tensor* 
         job.ldy[k] = y->ld[k];
         job.n[k] = x->n[k];
         max_n = std::max(max_n, x->n[k]);
-        for (int a = 0; a < hL.m[k]; ++a) {
-            job.ops[k][a].kind = hL.ops[k][a].kind;
-            job.ops[k][a].hbw = hL.ops[k][a].half_bw;
-            job.ops[k][a].data = reinterpret_cast<const double*>(ws) + offs[k][a];
+        for (int a = 0; a < P.L.m[k]; ++a) {
+            job.ops[k][a].kind = P.L.ops[k][a].kind;
+            job.ops[k][a].hbw = P.L.ops[k][a].half_bw;
+            job.ops[k][a].data = reinterpret_cast<const double*>(ws) + P.offs[k][a];
         }
     }
     HIP_TRY(launch_apply(job, max_n, h->stream), "apply launch");
@@ -1026,50 +1170,32 @@ cp_status cp_apply_operator(cp_handle h, const cp_operator* L, const cp_tensor* 
     return CP_OK;
 }
 
-cp_status cp_als_run(cp_handle h, const cp_operator* A, const cp_operator* B, const cp_tensor* f_init, cp_tensor* f_io,
-                     int32_t n_steps, const cp_als_opts* opts, cp_als_report* reports, double* traj) {
-    if (!h) return CP_ERR_INVALID_ARG;
-    if (!reports) return fail(h, CP_ERR_INVALID_ARG, "reports is null");
-    HostOp hA, hB;
-    cp_status st = prepare_step(h, A, B, f_init, f_io, n_steps, opts, hA, hB);
-    if (st != CP_OK) return st;
-    if (n_steps > 1 && f_init->r > f_io->r) {
-        // V holds rank max(r0, r); fine.  Nothing to reject.
-    }
-    return run_problems(h, 1, &hA, &hB, f_init, f_io, n_steps, opts, reports, traj);
-}
-
-cp_status cp_als_step(cp_handle h, const cp_operator* A, const cp_operator* B, const cp_tensor* f_n, cp_tensor* f_next,
-                      const cp_als_opts* opts, cp_als_report* report) {
-    return cp_als_run(h, A, B, f_n, f_next, 1, opts, report, nullptr);
-}
-
-cp_status cp_truncate(cp_handle h, const cp_tensor* g, cp_tensor* f, const cp_als_opts* opts, cp_als_report* report) {
-    if (!h) return CP_ERR_INVALID_ARG;
-    if (!g || !f) return fail(h, CP_ERR_INVALID_ARG, "null tensor");
-    if (g->d < 1 || g->d > CP_MAX_DIMS) return fail(h, CP_ERR_SHAPE, "g: d out of range");
+// The identity operator on the grid of t (one term, one op per dimension).
+struct IdentityOp {
     cp_op1d ident[CP_MAX_DIMS];
     double one = 1.0;
     int32_t idx[CP_MAX_DIMS] = {0};
     cp_operator I;
-    std::memset(&I, 0, sizeof(I));
-    I.d = g->d;
-    I.n_terms = 1;
-    I.coef = &one;
-    I.op_index = idx;
-    for (int k = 0; k < g->d; ++k) {
-        ident[k] = cp_op1d{CP_OP_IDENTITY, g->n[k], 0, nullptr};
-        I.n_ops[k] = 1;
-        I.ops[k] = &ident[k];
+    explicit IdentityOp(const cp_tensor& t) {
+        std::memset(&I, 0, sizeof(I));
+        I.d = t.d;
+        I.n_terms = 1;
+        I.coef = &one;
+        I.op_index = idx;
+        for (int k = 0; k < t.d; ++k) {
+            ident[k] = cp_op1d{CP_OP_IDENTITY, t.n[k], 0, nullptr};
+            I.n_ops[k] = 1;
+            I.ops[k] = &ident[k];
+        }
     }
-    return cp_als_run(h, &I, &I, g, f, 1, opts, report, nullptr);
-}
+};
 
-cp_status cp_als_step_source(cp_handle h, const cp_operator* A, const cp_operator* B, const cp_tensor* f_n,
-                             const cp_tensor* source, cp_tensor* f_next, const cp_als_opts* opts,
-                             cp_als_report* report) {
-    if (!h) return CP_ERR_INVALID_ARG;
-    if (!source) return cp_als_step(h, A, B, f_n, f_next, opts, report);
+// The right-hand side tensor g = B f_n + c of a forced step, placed at the start of the
+// workspace: its descriptor (panel k at element offset goff[k] of the workspace; until
+// placed, the panel pointers name a placeholder that is never dereferenced) and byte size.
+double g_placeholder;
+cp_status source_tensor(cp_handle h, const cp_operator* B, const cp_tensor* f_n, const cp_tensor* source, cp_tensor& g,
+                        size_t* goff, size_t& bytes) {
     cp_status st = check_tensor(h, f_n, "f_n", CP_MAX_N);
     if (st != CP_OK) return st;
     st = check_tensor(h, source, "source", CP_MAX_N);
@@ -1082,101 +1208,134 @@ cp_status cp_als_step_source(cp_handle h, const cp_operator* A, const cp_operato
     const int64_t rr = rb + source->r;
     if (B->n_terms < 1 || rr > CP_MAX_RANK)
         return fail(h, CP_ERR_SHAPE, "n_terms(B) * rank(f_n) + rank(source) exceeds CP_MAX_RANK");
-    // right-hand side tensor g = B f_n + source as one CP tensor: the applied terms of B f_n
-    // (coefficients in dimension 0) followed by the source's columns
-    size_t nel = 0;
-    for (int k = 0; k < f_n->d; ++k) nel += (size_t)f_n->n[k] * rr;
-    double* gbuf = nullptr;
-    HIP_TRY(hipMalloc(&gbuf, nel * 8), "hipMalloc(rhs tensor)");
-    cp_tensor g, gb;
     std::memset(&g, 0, sizeof(g));
     g.d = f_n->d;
     g.r = (int32_t)rr;
-    size_t off = 0;
+    size_t nel = 0;
     for (int k = 0; k < g.d; ++k) {
         g.n[k] = f_n->n[k];
         g.ld[k] = f_n->n[k];
-        g.U[k] = gbuf + off;
-        off += (size_t)f_n->n[k] * rr;
+        g.U[k] = &g_placeholder;
+        goff[k] = nel;
+        nel += (size_t)f_n->n[k] * rr;
     }
-    gb = g;
-    gb.r = (int32_t)rb;
-    st = cp_apply_operator(h, B, f_n, &gb);
-    hipError_t e = hipSuccess;
-    for (int k = 0; st == CP_OK && e == hipSuccess && k < g.d; ++k)
-        e = hipMemcpy2DAsync(g.U[k] + (size_t)rb * g.ld[k], (size_t)g.ld[k] * 8, source->U[k], (size_t)source->ld[k] * 8,
-                             (size_t)g.n[k] * 8, source->r, hipMemcpyDeviceToDevice, h->stream);
-    if (st == CP_OK && e != hipSuccess) st = hip_fail(h, e, "hipMemcpy2DAsync(source)");
-    if (st == CP_OK || st == CP_ERR_NOT_CONVERGED) {
-        // A f_{n+1} = g with the identity on the right
-        cp_op1d ident[CP_MAX_DIMS];
-        double one = 1.0;
-        int32_t idx[CP_MAX_DIMS] = {0};
-        cp_operator I;
-        std::memset(&I, 0, sizeof(I));
-        I.d = g.d;
-        I.n_terms = 1;
-        I.coef = &one;
-        I.op_index = idx;
-        for (int k = 0; k < g.d; ++k) {
-            ident[k] = cp_op1d{CP_OP_IDENTITY, g.n[k], 0, nullptr};
-            I.n_ops[k] = 1;
-            I.ops[k] = &ident[k];
-        }
-        st = cp_als_run(h, A, &I, &g, f_next, 1, opts, report, nullptr);
-    }
-    (void)hipStreamSynchronize(h->stream);
-    (void)hipFree(gbuf);
+    bytes = align_up(nel * 8);
+    return CP_OK;
+}
+
+// Residual problem: f at the U side, f_n at the V side, one step, residual only.
+cp_status residual_setup(cp_handle h, const cp_operator* A, const cp_operator* B, const cp_tensor* f,
+                         const cp_tensor* f_n, HostOp& hA, HostOp& hB, cp_als_opts& o) {
+    cp_als_default_opts(&o);
+    o.report_residual = 1;
+    cp_status st = prepare_step(h, A, B, f_n, f, 1, &o, hA, hB);
     return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+cp_status cp_inner(cp_handle h, const cp_tensor* x, const cp_tensor* y, double* out_dev) {
+    return inner_impl(h, x, y, out_dev, false, 0);
+}
+
+cp_status cp_norm(cp_handle h, const cp_tensor* x, double* out_dev) { return inner_impl(h, x, x, out_dev, true, 0); }
+
+cp_status cp_apply_operator(cp_handle h, const cp_operator* L, const cp_tensor* x, cp_tensor* y) {
+    return apply_impl(h, L, x, y, 0);
+}
+
+cp_status cp_als_run(cp_handle h, const cp_operator* A, const cp_operator* B, const cp_tensor* f_init, cp_tensor* f_io,
+                     int32_t n_steps, const cp_als_opts* opts, cp_als_report* reports, double* traj) {
+    if (!h) return CP_ERR_INVALID_ARG;
+    if (!reports) return fail(h, CP_ERR_INVALID_ARG, "reports is null");
+    HostOp hA, hB;
+    cp_status st = prepare_step(h, A, B, f_init, f_io, n_steps, opts, hA, hB);
+    if (st != CP_OK) return st;
+    return run_problems(h, 1, &hA, &hB, f_init, f_io, n_steps, opts, reports, traj);
+}
+
+cp_status cp_als_step(cp_handle h, const cp_operator* A, const cp_operator* B, const cp_tensor* f_n, cp_tensor* f_next,
+                      const cp_als_opts* opts, cp_als_report* report) {
+    return cp_als_run(h, A, B, f_n, f_next, 1, opts, report, nullptr);
+}
+
+cp_status cp_truncate(cp_handle h, const cp_tensor* g, cp_tensor* f, const cp_als_opts* opts, cp_als_report* report) {
+    if (!h) return CP_ERR_INVALID_ARG;
+    if (!g || !f) return fail(h, CP_ERR_INVALID_ARG, "null tensor");
+    if (g->d < 1 || g->d > CP_MAX_DIMS) return fail(h, CP_ERR_SHAPE, "g: d out of range");
+    IdentityOp I(*g);
+    return cp_als_run(h, &I.I, &I.I, g, f, 1, opts, report, nullptr);
+}
+
+cp_status cp_als_step_source(cp_handle h, const cp_operator* A, const cp_operator* B, const cp_tensor* f_n,
+                             const cp_tensor* source, cp_tensor* f_next, const cp_als_opts* opts,
+                             cp_als_report* report) {
+    if (!h) return CP_ERR_INVALID_ARG;
+    if (!source) return cp_als_step(h, A, B, f_n, f_next, opts, report);
+    if (!report) return fail(h, CP_ERR_INVALID_ARG, "report is null");
+    // g = B f_n + source as one CP tensor at the start of the workspace: the applied terms
+    // of B f_n (coefficients in dimension 0) followed by the source's columns; the operator
+    // blob of the application and the packed step follow it
+    cp_tensor g;
+    size_t gbytes = 0, goff[CP_MAX_DIMS];
+    cp_status st = source_tensor(h, B, f_n, source, g, goff, gbytes);
+    if (st != CP_OK) return st;
+    IdentityOp I(g);
+    HostOp hA, hB;
+    st = prepare_step(h, A, &I.I, &g, f_next, 1, opts, hA, hB);
+    if (st != CP_OK) return st;
+    cp_tensor gb = g;
+    gb.r = B->n_terms * f_n->r;
+    ApplyPlan P;
+    st = apply_plan(h, B, f_n, &gb, P);
+    if (st != CP_OK) return st;
+    size_t rbytes = 0;
+    st = run_bytes(h, 1, &hA, &hB, &g, f_next, 1, opts, &rbytes);
+    if (st != CP_OK) return st;
+    // the whole workspace first: a library-owned one is not reallocated (emptied) midway
+    st = ensure_ws(h, gbytes + std::max(P.bytes, rbytes));
+    if (st != CP_OK) return st;
+    for (int k = 0; k < g.d; ++k) {
+        g.U[k] = static_cast<double*>(h->ws) + goff[k];
+        gb.U[k] = g.U[k];
+    }
+    st = apply_impl(h, B, f_n, &gb, gbytes);
+    if (st != CP_OK) return st;
+    for (int k = 0; k < g.d; ++k)
+        HIP_TRY(hipMemcpy2DAsync(g.U[k] + (size_t)gb.r * g.ld[k], (size_t)g.ld[k] * 8, source->U[k],
+                                 (size_t)source->ld[k] * 8, (size_t)g.n[k] * 8, source->r, hipMemcpyDeviceToDevice,
+                                 h->stream),
+                "hipMemcpy2DAsync(source)");
+    // A f_{n+1} = g with the identity on the right
+    return run_problems(h, 1, &hA, &hB, &g, f_next, 1, opts, report, nullptr, gbytes);
 }
 
 cp_status cp_residual(cp_handle h, const cp_operator* A, const cp_operator* B, const cp_tensor* f,
                       const cp_tensor* f_n, double* rel_residual) {
     if (!h) return CP_ERR_INVALID_ARG;
     if (!A || !B || !f || !f_n || !rel_residual) return fail(h, CP_ERR_INVALID_ARG, "null argument");
-    cp_status st = check_tensor(h, f, "f", CP_MAX_N);
+    HostOp hA, hB;
+    cp_als_opts o;
+    cp_status st = residual_setup(h, A, B, f, f_n, hA, hB, o);
     if (st != CP_OK) return st;
-    st = check_tensor(h, f_n, "f_n", CP_MAX_N);
+    Staged S;
+    st = stage_problems(h, 1, &hA, &hB, f_n, f, 1, &o, std::vector<int>(1, 1), S);
     if (st != CP_OK) return st;
-    if (f->d != f_n->d || A->n_terms < 1 || B->n_terms < 1) return fail(h, CP_ERR_SHAPE, "f and f_n differ in d");
-    // A f and B f_n as CP tensors in one allocation, then <Af,Af> - 2 <Af,Bf_n> + <Bf_n,Bf_n>
-    const int ra = A->n_terms * f->r, rb = B->n_terms * f_n->r;
-    size_t nel = 0;
-    for (int k = 0; k < f->d; ++k) nel += (size_t)f->n[k] * (ra + rb);
-    double* buf = nullptr;
-    HIP_TRY(hipMalloc(&buf, nel * 8 + 3 * 8), "hipMalloc(residual)");
-    cp_tensor af, bg;
-    std::memset(&af, 0, sizeof(af));
-    af.d = f->d;
-    af.r = ra;
-    bg = af;
-    bg.r = rb;
-    size_t off = 0;
-    for (int k = 0; k < f->d; ++k) {
-        af.n[k] = bg.n[k] = f->n[k];
-        af.ld[k] = bg.ld[k] = f->n[k];
-        af.U[k] = buf + off;
-        off += (size_t)f->n[k] * ra;
-        bg.U[k] = buf + off;
-        off += (size_t)f->n[k] * rb;
-    }
-    double* dots = buf + off;
-    st = cp_apply_operator(h, A, f, &af);
-    if (st == CP_OK) st = cp_apply_operator(h, B, f_n, &bg);
-    if (st == CP_OK) st = cp_inner(h, &af, &af, dots);
-    if (st == CP_OK) st = cp_inner(h, &af, &bg, dots + 1);
-    if (st == CP_OK) st = cp_inner(h, &bg, &bg, dots + 2);
-    double v[3] = {0.0, 0.0, 0.0};
-    if (st == CP_OK) {
-        hipError_t e = hipMemcpyAsync(v, dots, sizeof(v), hipMemcpyDeviceToHost, h->stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
-        if (e != hipSuccess) st = hip_fail(h, e, "residual copy");
-    }
-    (void)hipStreamSynchronize(h->stream);
-    (void)hipFree(buf);
+    st = ensure_ws(h, S.bytes);
     if (st != CP_OK) return st;
-    const double num = std::max(v[0] - 2.0 * v[1] + v[2], 0.0);
-    *rel_residual = v[2] > 0.0 ? std::sqrt(num / v[2]) : std::sqrt(num);
+    st = upload_static(h, S, static_cast<char*>(h->ws), nullptr, f, h->stream, false);
+    if (st != CP_OK) return st;
+    const Problem& pb = S.pk[0].pb;
+    st = copy_panels_in(h, h->stream, f_n, pb.V, pb.offV);
+    if (st == CP_OK) st = copy_panels_in(h, h->stream, f, pb.U, pb.offU);
+    if (st != CP_OK) return st;
+    HIP_TRY(launch_residual(S.d_desc, h->stream), "residual launch");
+    cp_als_report rep;
+    HIP_TRY(hipMemcpyAsync(&rep, pb.reports, sizeof(rep), hipMemcpyDeviceToHost, h->stream), "hipMemcpyAsync(report)");
+    HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+    *rel_residual = rep.rel_residual;
     return CP_OK;
 }
 
@@ -1184,78 +1343,19 @@ cp_status cp_als_step_adaptive(cp_handle h, const cp_operator* A, const cp_opera
                                cp_tensor* f_next, int32_t r_start, double tau, const cp_als_opts* opts,
                                cp_als_report* report, int32_t* final_rank, double* rel_residual) {
     if (!h) return CP_ERR_INVALID_ARG;
-    if (!f_next || !report || !final_rank || !rel_residual) return fail(h, CP_ERR_INVALID_ARG, "null argument");
+    if (!f_next || !opts || !report || !final_rank || !rel_residual) return fail(h, CP_ERR_INVALID_ARG, "null argument");
     const int cap = f_next->r;
     if (r_start < 1 || r_start > cap || !(tau >= 0.0)) return fail(h, CP_ERR_INVALID_ARG, "need 1 <= r_start <= cap, tau >= 0");
-    cp_status st = check_tensor(h, f_next, "f_next", CP_MAX_N);
-    if (st != CP_OK) return st;
+    cp_als_opts o = *opts;
+    o.rank_mode = CP_RANK_ADAPTIVE;
+    o.tau_rank = tau;
+    o.rank_cap = cap;
     cp_tensor f = *f_next;
-    int r = r_start;
-    int sweeps = 0, pcg = 0;
-    double rho = 0.0;
-    uint32_t state = 0x9e3779b9u;
-    for (;;) {
-        f.r = r;
-        cp_als_report rp;
-        st = cp_als_step(h, A, B, f_n, &f, opts, &rp);
-        if (st != CP_OK && st != CP_ERR_NOT_CONVERGED) return st;
-        sweeps += rp.sweeps;
-        pcg += rp.pcg_iters;
-        *report = rp;
-        const cp_status conv = st;
-        st = cp_residual(h, A, B, &f, f_n, &rho);
-        if (st != CP_OK) return st;
-        st = conv;
-        if (rho <= tau || r == cap) break;
-        // one more term: seeded values in every dimension but the first, zero there (it
-        // adds nothing until the next update of the first dimension sizes it)
-        for (int k = 0; k < f.d; ++k) {
-            std::vector<double> col(f.n[k], 0.0);
-            if (k > 0)
-                for (double& x : col) {
-                    state ^= state << 13;
-                    state ^= state >> 17;
-                    state ^= state << 5;
-                    x = ((double)state / 4294967296.0) - 0.5;
-                }
-            HIP_TRY(hipMemcpyAsync(f.U[k] + (size_t)r * f.ld[k], col.data(), col.size() * 8, hipMemcpyHostToDevice,
-                                   h->stream),
-                    "hipMemcpyAsync(new column)");
-            HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
-        }
-        ++r;
-    }
-    // drop terms whose weight prod_k ||U_k[:, l]|| is below 1e-14 of the largest (their
-    // columns are moved out; the kept columns keep their order)
-    std::vector<double> w(r, 1.0);
-    for (int k = 0; k < f.d; ++k) {
-        std::vector<double> panel((size_t)f.n[k] * r);
-        HIP_TRY(hipMemcpy2DAsync(panel.data(), (size_t)f.n[k] * 8, f.U[k], (size_t)f.ld[k] * 8, (size_t)f.n[k] * 8, r,
-                                 hipMemcpyDeviceToHost, h->stream),
-                "hipMemcpy2DAsync(weights)");
-        HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
-        for (int l = 0; l < r; ++l) {
-            double s2 = 0.0;
-            for (int i = 0; i < f.n[k]; ++i) s2 += panel[(size_t)l * f.n[k] + i] * panel[(size_t)l * f.n[k] + i];
-            w[l] *= std::sqrt(s2);
-        }
-    }
-    const double wmax = *std::max_element(w.begin(), w.end());
-    int kept = 0;
-    for (int l = 0; l < r; ++l) {
-        if (!(w[l] >= 1e-14 * wmax)) continue;
-        if (kept != l)
-            for (int k = 0; k < f.d; ++k)
-                HIP_TRY(hipMemcpyAsync(f.U[k] + (size_t)kept * f.ld[k], f.U[k] + (size_t)l * f.ld[k], (size_t)f.n[k] * 8,
-                                       hipMemcpyDeviceToDevice, h->stream),
-                        "hipMemcpyAsync(compact)");
-        ++kept;
-    }
-    HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
-    report->sweeps = sweeps;
-    report->pcg_iters = pcg;
-    *final_rank = std::max(kept, 1);
-    *rel_residual = rho;
+    f.r = r_start;
+    const cp_status st = cp_als_run(h, A, B, f_n, &f, 1, &o, report, nullptr);
+    if (st != CP_OK && st != CP_ERR_NOT_CONVERGED) return st;
+    *final_rank = report->final_rank;
+    *rel_residual = report->rel_residual;
     return st;
 }
 
@@ -1263,10 +1363,11 @@ cp_status cp_als_run_batched(cp_handle h, int32_t count, const cp_operator* A, c
                              const cp_tensor* f_init, cp_tensor* f_io, int32_t n_steps, const cp_als_opts* opts,
                              cp_als_report* reports) {
     if (!h) return CP_ERR_INVALID_ARG;
-    if (count < 1 || !A || !B || !f_init || !f_io || !reports) return fail(h, CP_ERR_INVALID_ARG, "bad batch arguments");
+    if (count < 1 || !A || !B || !f_init || !f_io || !opts || !reports)
+        return fail(h, CP_ERR_INVALID_ARG, "bad batch arguments");
     std::vector<HostOp> hA(count), hB(count);
     for (int i = 0; i < count; ++i) {
-        cp_status st = prepare_step(h, &A[i], &B[i], &f_init[i], &f_io[i], n_steps, opts, hA[i], hB[i]);
+        cp_status st = prepare_step(h, &A[i], &B[i], &f_init[i], &f_io[i], n_steps, &opts[i], hA[i], hB[i]);
         if (st != CP_OK) return fail(h, st, "problem " + std::to_string(i) + ": " + h->err);
     }
     return run_problems(h, count, hA.data(), hB.data(), f_init, f_io, n_steps, opts, reports, nullptr);
@@ -1310,11 +1411,11 @@ cp_status cp_batch_plan_create(cp_handle h, int32_t count, const cp_operator* A,
                                const cp_tensor* f_init, cp_tensor* f_io, int32_t n_steps, const cp_als_opts* opts,
                                cp_batch_plan* plan) {
     if (!h) return CP_ERR_INVALID_ARG;
-    if (count < 1 || !A || !B || !f_init || !f_io || !plan) return fail(h, CP_ERR_INVALID_ARG, "bad plan arguments");
+    if (count < 1 || !A || !B || !f_init || !f_io || !opts || !plan) return fail(h, CP_ERR_INVALID_ARG, "bad plan arguments");
     *plan = nullptr;
     std::vector<HostOp> hA(count), hB(count);
     for (int i = 0; i < count; ++i) {
-        cp_status st = prepare_step(h, &A[i], &B[i], &f_init[i], &f_io[i], n_steps, opts, hA[i], hB[i]);
+        cp_status st = prepare_step(h, &A[i], &B[i], &f_init[i], &f_io[i], n_steps, &opts[i], hA[i], hB[i]);
         if (st != CP_OK) return fail(h, st, "problem " + std::to_string(i) + ": " + h->err);
     }
     cp_batch_plan p = new (std::nothrow) cp_batch_plan_s();
@@ -1324,7 +1425,7 @@ cp_status cp_batch_plan_create(cp_handle h, int32_t count, const cp_operator* A,
     p->f_init.assign(f_init, f_init + count);
     p->f_io.assign(f_io, f_io + count);
     cp_status st = stage_problems(h, count, hA.data(), hB.data(), f_init, f_io, n_steps, opts,
-                                  choose_clusters(h, count, hA.data(), hB.data(), f_init, f_io, *opts), p->S);
+                                  choose_clusters(h, count, hA.data(), hB.data(), f_init, f_io, opts), p->S);
     hipError_t e = hipSuccess;
     const char* what = "";
     if (st == CP_OK) {
@@ -1396,27 +1497,38 @@ cp_status cp_tune_cluster(cp_handle h, const cp_operator* A, const cp_operator* 
     HostOp hA, hB;
     cp_status st = prepare_step(h, A, B, f_n, guess, 1, opts, hA, hB);
     if (st != CP_OK) return st;
+    if (with_residual(*opts)) return fail(h, CP_ERR_INVALID_ARG, "problems that form the step residual run on one workgroup");
     cp_als_opts o = *opts;
     o.tol = 0.0;              // every candidate runs the same number of sweeps
     o.max_sweeps = sweeps;
-    // a device copy of the guess, refreshed before every trial (the caller's stays untouched)
+    // a copy of the guess at the start of the workspace, refreshed before every trial (the
+    // caller's stays untouched); the trial's packed problem follows it
     size_t nel = 0;
     for (int k = 0; k < guess->d; ++k) nel += (size_t)guess->n[k] * guess->r;
-    double* scratch = nullptr;
-    HIP_TRY(hipMalloc(&scratch, nel * 8), "hipMalloc(tuning)");
+    const size_t gbytes = align_up(nel * 8);
+    const int wmax = cluster_size(h, hA, hB, *guess);
+    size_t need = 0;
+    for (int W = 1; W <= wmax; W *= 2) {
+        Staged S;
+        st = stage_problems(h, 1, &hA, &hB, f_n, guess, 1, &o, std::vector<int>(1, W), S);
+        if (st != CP_OK) return st;
+        need = std::max(need, S.bytes);
+    }
+    st = ensure_ws(h, gbytes + need);
+    if (st != CP_OK) return st;
     cp_tensor g = *guess;
     size_t off = 0;
     for (int k = 0; k < g.d; ++k) {
-        g.U[k] = scratch + off;
+        g.U[k] = reinterpret_cast<double*>(static_cast<char*>(h->ws)) + off;
         g.ld[k] = g.n[k];
         off += (size_t)g.n[k] * g.r;
     }
+    char* trial_ws = static_cast<char*>(h->ws) + gbytes;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     int best = 1;
     float tbest = -1.0f;
     hipError_t he = hipEventCreate(&e0);
     if (he == hipSuccess) he = hipEventCreate(&e1);
-    const int wmax = cluster_size(h, hA, hB, *guess);
     for (int W = 1; he == hipSuccess && st == CP_OK && W <= wmax; W *= 2) {
         float ms = 0.0f;
         for (int rep = 0; rep < 2 && st == CP_OK && he == hipSuccess; ++rep) {   // the first run warms up
@@ -1426,8 +1538,7 @@ cp_status cp_tune_cluster(cp_handle h, const cp_operator* A, const cp_operator* 
             Staged S;
             cp_als_report rp;
             if (he == hipSuccess) st = stage_problems(h, 1, &hA, &hB, f_n, &g, 1, &o, std::vector<int>(1, W), S);
-            if (st == CP_OK) st = ensure_ws(h, S.bytes);
-            if (st == CP_OK) st = upload_static(h, S, static_cast<char*>(h->ws), nullptr, &g, h->stream, false);
+            if (st == CP_OK) st = upload_static(h, S, trial_ws, nullptr, &g, h->stream, false);
             if (st == CP_OK && he == hipSuccess) he = hipEventRecord(e0, h->stream);
             if (st == CP_OK && he == hipSuccess) st = enqueue_run(h, S, f_n, &g, &rp, h->stream);
             if (st == CP_OK && he == hipSuccess) he = hipEventRecord(e1, h->stream);
@@ -1439,9 +1550,9 @@ cp_status cp_tune_cluster(cp_handle h, const cp_operator* A, const cp_operator* 
             best = W;
         }
     }
+    (void)hipStreamSynchronize(h->stream);   // no copy from a released host buffer may be pending
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
-    (void)hipFree(scratch);
     if (st != CP_OK) return st;
     if (he != hipSuccess) return hip_fail(h, he, "cluster tuning");
     h->tuned[shape_key(hA, hB, *f_n, *guess, *opts)] = best;
@@ -1503,6 +1614,103 @@ cp_status cp_tune_load(cp_handle h, const char* path) {
 cp_status cp_tune_clear(cp_handle h) {
     if (!h) return CP_ERR_INVALID_ARG;
     h->tuned.clear();
+    return CP_OK;
+}
+
+// ---------------------------------------------------------------------------------------
+// workspace sizes
+// ---------------------------------------------------------------------------------------
+cp_status cp_workspace_size_step(cp_handle h, const cp_operator* A, const cp_operator* B, const cp_tensor* f_init,
+                                 const cp_tensor* source, const cp_tensor* f_io, int32_t n_steps,
+                                 const cp_als_opts* opts, size_t* bytes) {
+    if (!h) return CP_ERR_INVALID_ARG;
+    if (!bytes) return fail(h, CP_ERR_INVALID_ARG, "bytes is null");
+    cp_status st;
+    if (source) {
+        cp_tensor g;
+        size_t gbytes = 0, goff[CP_MAX_DIMS];
+        st = source_tensor(h, B, f_init, source, g, goff, gbytes);
+        if (st != CP_OK) return st;
+        IdentityOp I(g);
+        HostOp hA, hB;
+        st = prepare_step(h, A, &I.I, &g, f_io, 1, opts, hA, hB);
+        if (st != CP_OK) return st;
+        cp_tensor gb = g;
+        gb.r = B->n_terms * f_init->r;
+        ApplyPlan P;
+        st = apply_plan(h, B, f_init, &gb, P);
+        if (st != CP_OK) return st;
+        size_t rb = 0;
+        st = run_bytes(h, 1, &hA, &hB, &g, f_io, 1, opts, &rb);
+        if (st != CP_OK) return st;
+        *bytes = gbytes + std::max(P.bytes, rb);
+        return CP_OK;
+    }
+    HostOp hA, hB;
+    st = prepare_step(h, A, B, f_init, f_io, n_steps, opts, hA, hB);
+    if (st != CP_OK) return st;
+    size_t need = 0;
+    st = run_bytes(h, 1, &hA, &hB, f_init, f_io, n_steps, opts, &need);
+    if (st != CP_OK) return st;
+    // cp_residual(A, B, f_io, f_init)
+    cp_als_opts ro;
+    cp_als_default_opts(&ro);
+    ro.report_residual = 1;
+    Staged S;
+    st = stage_problems(h, 1, &hA, &hB, f_init, f_io, 1, &ro, std::vector<int>(1, 1), S);
+    if (st != CP_OK) return st;
+    need = std::max(need, S.bytes);
+    // cp_tune_cluster(A, B, f_init, f_io): a copy of the guess, then each trial
+    if (!with_residual(*opts)) {
+        cp_als_opts o = *opts;
+        o.tol = 0.0;
+        size_t nel = 0;
+        for (int k = 0; k < f_io->d; ++k) nel += (size_t)f_io->n[k] * f_io->r;
+        size_t trial = 0;
+        for (int W = 1; W <= cluster_size(h, hA, hB, *f_io); W *= 2) {
+            Staged T;
+            st = stage_problems(h, 1, &hA, &hB, f_init, f_io, 1, &o, std::vector<int>(1, W), T);
+            if (st != CP_OK) return st;
+            trial = std::max(trial, T.bytes);
+        }
+        need = std::max(need, align_up(nel * 8) + trial);
+    }
+    *bytes = need;
+    return CP_OK;
+}
+
+cp_status cp_workspace_size_batched(cp_handle h, int32_t count, const cp_operator* A, const cp_operator* B,
+                                    const cp_tensor* f_init, const cp_tensor* f_io, int32_t n_steps,
+                                    const cp_als_opts* opts, size_t* bytes) {
+    if (!h) return CP_ERR_INVALID_ARG;
+    if (count < 1 || !A || !B || !f_init || !f_io || !opts || !bytes)
+        return fail(h, CP_ERR_INVALID_ARG, "bad batch arguments");
+    std::vector<HostOp> hA(count), hB(count);
+    for (int i = 0; i < count; ++i) {
+        cp_status st = prepare_step(h, &A[i], &B[i], &f_init[i], &f_io[i], n_steps, &opts[i], hA[i], hB[i]);
+        if (st != CP_OK) return fail(h, st, "problem " + std::to_string(i) + ": " + h->err);
+    }
+    return run_bytes(h, count, hA.data(), hB.data(), f_init, f_io, n_steps, opts, bytes);
+}
+
+cp_status cp_workspace_size_inner(cp_handle h, const cp_tensor* x, const cp_tensor* y, size_t* bytes) {
+    if (!h) return CP_ERR_INVALID_ARG;
+    if (!bytes) return fail(h, CP_ERR_INVALID_ARG, "bytes is null");
+    GramJob job;
+    int nch = 0;
+    cp_status st = inner_job(h, x, y, job, nch);
+    if (st != CP_OK) return st;
+    *bytes = inner_bytes(job, nch);
+    return CP_OK;
+}
+
+cp_status cp_workspace_size_apply(cp_handle h, const cp_operator* L, const cp_tensor* x, size_t* bytes) {
+    if (!h) return CP_ERR_INVALID_ARG;
+    if (!bytes) return fail(h, CP_ERR_INVALID_ARG, "bytes is null");
+    ApplyPlan P;
+    cp_status st = apply_plan(h, L, x, nullptr, P);
+    if (st != CP_OK) return st;
+    *bytes = P.bytes;
     return CP_OK;
 }
 

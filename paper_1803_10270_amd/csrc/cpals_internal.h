@@ -19,6 +19,8 @@ struct OpDev {
 // Pair record (e, z) for the Hadamard assembly of one block of C (or D) of dimension q:
 // the product coefficient and, for the j-th dimension k != q (increasing k), the index
 // a + b * mA[k] of the block (a, b) of G_k (or X_k) that it multiplies in.
+// The same record holds one term of an operator (termA / termB): coef eta_e and, for
+// every dimension k, the index of its distinct 1-D operator.
 struct PairRec {
     double coef;
     uint8_t slot[CP_MAX_DIMS];
@@ -64,6 +66,21 @@ struct Problem {
     // options
     double tol, eps_reg, pcg_tol;
     int32_t max_sweeps, pcg_max, precision, pad_;
+    // rank control: r above is the rank the first step starts from; every panel holds rcap
+    // columns (rcap = r in fixed mode)
+    int32_t rcap, rank_mode, replay_rank, report_residual;
+    double tau_rank;
+    uint64_t seed;
+    // the operators' terms (residual and growth): coef, and per dimension the op index
+    int32_t TA, TB;
+    const PairRec* termA;
+    const PairRec* termB;
+    // step residual in double-double: Grams of the stacked panel [P_k | Q_k] of dimension k,
+    // entry e as (hi, lo) at Rdd[2 (offR[k] + e)]
+    double* Rdd;  int64_t offR[CP_MAX_DIMS];
+    // growth term: t_k (n_k) at tv + offT[k]; t_k^T [P_k | Q_k] at cv + offCv[k]
+    double* tv;   int64_t offT[CP_MAX_DIMS];
+    double* cv;   int64_t offCv[CP_MAX_DIMS];
     // outputs
     cp_als_report* reports;   // device array of n_steps
     double* traj;             // nullable: n_steps * sum_k n_k r

@@ -24,7 +24,9 @@ def declared_functions():
 def test_header_declares_the_entry_points():
     names = declared_functions()
     for required in ("cp_inner", "cp_norm", "cp_apply_operator", "cp_als_step", "cp_truncate", "cp_als_run",
-                     "cp_als_run_batched", "cp_create", "cp_destroy"):
+                     "cp_als_run_batched", "cp_create", "cp_destroy", "cp_set_workspace", "cp_residual",
+                     "cp_workspace_size_step", "cp_workspace_size_batched", "cp_workspace_size_inner",
+                     "cp_workspace_size_apply"):
         assert required in names
 
 
@@ -38,6 +40,8 @@ def test_library_exports_every_declared_symbol():
 def test_default_options():
     o = B.default_opts()
     assert o.tol == 1e-8 and o.max_sweeps == 200 and o.eps_reg == 1e-10 and o.precision == B.PREC_FP64
+    assert o.rank_mode == B.RANK_FIXED and o.replay_rank == -1 and o.rank_cap == 64 and o.report_residual == 0
+    assert o.tau_rank == 1e-6 and o.seed == 0
 
 
 def test_struct_layouts_match_c():
@@ -52,6 +56,9 @@ int main(void) {
          sizeof(cp_tensor), sizeof(cp_op1d), sizeof(cp_operator), sizeof(cp_als_opts), sizeof(cp_als_report));
   P(cp_tensor, U) P(cp_tensor, ld) P(cp_operator, ops) P(cp_operator, n_ops) P(cp_als_opts, precision)
   P(cp_als_opts, pcg_tol) P(cp_als_report, flags) P(cp_als_report, fnorm) P(cp_op1d, data)
+  P(cp_als_opts, rank_mode) P(cp_als_opts, tau_rank) P(cp_als_opts, rank_cap) P(cp_als_opts, replay_rank)
+  P(cp_als_opts, seed) P(cp_als_opts, report_residual) P(cp_als_report, rel_residual)
+  P(cp_als_report, final_rank) P(cp_als_report, grown_rank)
   return 0;
 }
 '''
@@ -77,6 +84,10 @@ int main(void) {
     assert vals["cp_als_report.flags"] == B.cp_als_report.flags.offset
     assert vals["cp_als_report.fnorm"] == B.cp_als_report.fnorm.offset
     assert vals["cp_op1d.data"] == B.cp_op1d.data.offset
+    for f in ("rank_mode", "tau_rank", "rank_cap", "replay_rank", "seed", "report_residual"):
+        assert vals["cp_als_opts." + f] == getattr(B.cp_als_opts, f).offset, f
+    for f in ("rel_residual", "final_rank", "grown_rank"):
+        assert vals["cp_als_report." + f] == getattr(B.cp_als_report, f).offset, f
 
 
 def test_missing_library_fails_loudly(monkeypatch):
