@@ -198,6 +198,20 @@ cp_status cp_inner(cp_handle h, const cp_tensor* x, const cp_tensor* y, double* 
 /* ||x|| = sqrt(max(<x,x>, 0)).  out_dev: one double in device memory. */
 cp_status cp_norm(cp_handle h, const cp_tensor* x, double* out_dev);
 
+/* cp_inner for callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same scalar product and kernels,
+ * with the chunk partials in a file-scope device array of the library (4 MiB per GPU, held
+ * until the process ends) instead of the handle's workspace.  The call allocates nothing
+ * (no hipMalloc, hipFree or allocating library routine); the array's device address is taken
+ * once per device by cp_create.  The row chunks are capped so that the partials and the d
+ * Grams fit in the array (fewer, longer chunks for large ranks), so the result may differ
+ * from cp_inner's by reduction order (rounding).  Every call on a GPU shares that GPU's array
+ * and every entry it reads is written first by the same call; calls that overlap on one GPU
+ * (other streams, other threads) race.  CP_ERR_SHAPE when the partials of one chunk per
+ * dimension and the Grams, (2 d rank(x) rank(y)) doubles, do not fit -- never for
+ * d <= CP_MAX_DIMS and ranks <= CP_MAX_RANK (at most 1 MiB). */
+cp_status cp_inner_noalloc(cp_handle h, const cp_tensor* x, const cp_tensor* y, double* out_dev);
+
 /* y = L x as a CP tensor of rank n_terms * x.r (operator application, Section 3.2):
  * column e*x.r + l of y.U[k] is E_k^e X_k[:, l], with coef[e] multiplied into dimension 0.
  * y must have y.r == L.n_terms * x.r and the same n; y's panels are overwritten and must not

@@ -90,6 +90,7 @@ def lib() -> C.CDLL:
             "cp_set_cluster": [H, C.c_int32],
             "cp_inner": [H, P(cp_tensor), P(cp_tensor), C.c_void_p],
             "cp_norm": [H, P(cp_tensor), C.c_void_p],
+            "cp_inner_noalloc": [H, P(cp_tensor), P(cp_tensor), C.c_void_p],
             "cp_apply_operator": [H, P(cp_operator), P(cp_tensor), P(cp_tensor)],
             "cp_als_step": [H, P(cp_operator), P(cp_operator), P(cp_tensor), P(cp_tensor), P(cp_als_opts),
                             P(cp_als_report)],
@@ -260,6 +261,12 @@ def cp_inner(h: Handle, x, y, out) -> None:
     """out (1-element float64 CUDA tensor) <- <x, y>."""
     xd, yd = tensor_desc(x), tensor_desc(y)
     h.check(lib().cp_inner(h.h, C.byref(xd), C.byref(yd), C.c_void_p(out.data_ptr())))
+
+
+def cp_inner_noalloc(h: Handle, x, y, out) -> None:
+    """out (1-element float64 CUDA tensor) <- <x, y> without allocating device memory."""
+    xd, yd = tensor_desc(x), tensor_desc(y)
+    h.check(lib().cp_inner_noalloc(h.h, C.byref(xd), C.byref(yd), C.c_void_p(out.data_ptr())))
 
 
 def cp_norm(h: Handle, x, out) -> None:

@@ -16,7 +16,9 @@
 
 namespace cpals {
 // defined in basic_kernels.hip
-int gram_chunks(const int32_t* n, int d, int32_t* chunk0, int32_t* chunk_rows);
+int gram_chunks(const int32_t* n, int d, int32_t* chunk0, int32_t* chunk_rows, int max_chunks);
+hipError_t noalloc_scratch_init(int device);
+double* noalloc_scratch(int device);
 hipError_t launch_inner(const GramJob& job, double* partial, double* out, bool sqrt_out, hipStream_t st);
 hipError_t launch_apply(const ApplyJob& job, int max_n, hipStream_t st);
 // defined in als_kernel.hip
@@ -991,6 +993,11 @@ cp_status cp_create(cp_handle* handle, void* hip_stream) {
     int ncu = 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h->device) == hipSuccess && ncu > 0)
         h->n_cu = ncu;
+    // the device address of this GPU's scratch array (cp_inner_noalloc), once per device
+    if (noalloc_scratch_init(h->device) != hipSuccess) {
+        delete h;
+        return CP_ERR_HIP;
+    }
     *handle = h;
     return CP_OK;
 }
@@ -1072,7 +1079,7 @@ cp_status inner_job(cp_handle h, const cp_tensor* x, const cp_tensor* y, GramJob
         job.ldy[k] = y->ld[k];
         job.n[k] = x->n[k];
     }
-    nch = gram_chunks(job.n, job.d, job.chunk0, job.chunk_rows);
+    nch = gram_chunks(job.n, job.d, job.chunk0, job.chunk_rows, 1 << 30);
     return CP_OK;
 }
 
@@ -1244,6 +1251,28 @@ cp_status cp_norm(cp_handle h, const cp_tensor* x, double* out_dev) { return inn
 
 cp_status cp_apply_operator(cp_handle h, const cp_operator* L, const cp_tensor* x, cp_tensor* y) {
     return apply_impl(h, L, x, y, 0);
+}
+
+cp_status cp_inner_noalloc(cp_handle h, const cp_tensor* x, const cp_tensor* y, double* out_dev) {
+    if (!h) return CP_ERR_INVALID_ARG;
+    if (!out_dev) return fail(h, CP_ERR_INVALID_ARG, "out_dev is null");
+    GramJob job;
+    int nch = 0;
+    cp_status st = inner_job(h, x, y, job, nch);
+    if (st != CP_OK) return st;
+    // as many row chunks as the scratch holds partials for (beside the d Grams)
+    const size_t slot = (size_t)job.rx * job.ry * 8;
+    const size_t slots = (NOALLOC_SCRATCH_BYTES - 256) / slot;
+    if (slots < (size_t)2 * job.d)
+        return fail(h, CP_ERR_SHAPE, "cp_inner_noalloc: d * rank(x) * rank(y) exceeds the " +
+                                         std::to_string(NOALLOC_SCRATCH_BYTES) + "-byte scratch");
+    nch = gram_chunks(job.n, job.d, job.chunk0, job.chunk_rows, (int)std::min<size_t>(slots - job.d, 1 << 30));
+    if (inner_bytes(job, nch) > NOALLOC_SCRATCH_BYTES)
+        return fail(h, CP_ERR_SHAPE, "cp_inner_noalloc: the partials exceed the scratch");
+    double* scr = noalloc_scratch(h->device);
+    if (!scr) return fail(h, CP_ERR_HIP, "cp_inner_noalloc: no scratch address for this device");
+    HIP_TRY(launch_inner(job, scr, out_dev, false, h->stream), "inner launch");
+    return CP_OK;
 }
 
 cp_status cp_als_run(cp_handle h, const cp_operator* A, const cp_operator* B, const cp_tensor* f_init, cp_tensor* f_io,

@@ -2,6 +2,7 @@
 // application of a separable operator (Section 3.2).  These are HBM-bound: each factor
 // panel is read once from HBM.
 #include <hip/hip_runtime.h>
+#include <mutex>
 #include "cpals_internal.h"
 #include "mfma_f64.h"
 
@@ -147,9 +148,9 @@ __global__ void __launch_bounds__(GT) gram_finish(GramJob job, const double* __r
 
 // Row chunks per dimension: at least 256 rows each, and no more than MAX_CHUNKS / d chunks
 // per dimension (long panels get longer chunks).
-int gram_chunks(const int32_t* n, int d, int32_t* chunk0, int32_t* chunk_rows) {
+int gram_chunks(const int32_t* n, int d, int32_t* chunk0, int32_t* chunk_rows, int max_chunks) {
     chunk0[0] = 0;
-    const int per_dim = MAX_CHUNKS / d;
+    const int per_dim = (max_chunks < MAX_CHUNKS ? max_chunks : MAX_CHUNKS) / d;
     for (int k = 0; k < d; ++k) {
         int rows = 256;
         while ((n[k] + rows - 1) / rows > per_dim) rows *= 2;
@@ -321,6 +322,42 @@ hipError_t launch_apply(const ApplyJob& job, int max_n, hipStream_t st) {
     if (rb < 1) rb = 1;
     hipLaunchKernelGGL(apply_columns, dim3(cols, rb), dim3(GT), 0, st, job);
     return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------
+// Scratch of the allocation-free scalar product: one file-scope device array per GPU,
+// reached from the host only through the address hipGetSymbolAddress gives for the
+// device that is current (the array's name is not a device address in host code).
+// ------------------------------------------------------------------------------------
+static __device__ __align__(256) double scratch[NOALLOC_SCRATCH_BYTES / sizeof(double)];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+double* scratch_ptr[MAX_DEVICES] = {nullptr};
+}  // namespace
+
+hipError_t noalloc_scratch_init(int device) {
+    static std::mutex mu;
+    if (device < 0 || device >= MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (scratch_ptr[device]) return hipSuccess;
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return e;
+    if (cur != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e == hipSuccess) scratch_ptr[device] = static_cast<double*>(p);
+    if (cur != device) {
+        const hipError_t e2 = hipSetDevice(cur);
+        if (e == hipSuccess) e = e2;
+    }
+    return e;
+}
+
+double* noalloc_scratch(int device) {
+    if (device < 0 || device >= MAX_DEVICES) return nullptr;
+    return scratch_ptr[device];
 }
 
 }  // namespace cpals

@@ -9,6 +9,9 @@ constexpr int WG = 256;           // threads of the persistent ALS workgroup (4 
                                   // so each wave may hold 512 registers, accumulators in AGPRs)
 constexpr int NWAVES = WG / 64;
 
+// Device scratch of the allocation-free scalar product (cp_inner_noalloc), per GPU.
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)4 << 20;
+
 // One distinct 1-D operator on the device.
 struct OpDev {
     int32_t kind;      // cp_op_kind
