@@ -274,6 +274,25 @@ cp_status cp_als_run(cp_handle h, const cp_operator* A, const cp_operator* B, co
 cp_status cp_truncate(cp_handle h, const cp_tensor* g, cp_tensor* f, const cp_als_opts* opts,
                       cp_als_report* report);
 
+/* One explicit second-order Adams-Bashforth step f_{n+2} = f_{n+1} + (dt/2) L (3 f_{n+1} - f_n)
+ * (Section 3.2, eq. AB2_), split as the paper splits it into additions, one operator
+ * application and rank reductions to at most cap = f_next->r columns:
+ *   i)   w = 3 f_{n+1} - f_n (f_cur's columns scaled by 3, then f_prev's by -1, the scalars in
+ *        dimension 0), reduced by ALS (cp_truncate) from its leading cap columns when its
+ *        rank rank(f_prev) + rank(f_cur) exceeds cap;
+ *   ii)  y = L w, reduced when L.n_terms * rank(w) > cap: the ALS fit of L w at rank cap
+ *        (cp_als_step with A = I, B = L, f_n = w, so L w is never formed) from the leading cap
+ *        columns of L w (the first terms of L applied to w);
+ *   iii) f_{n+2} = f_{n+1} + (dt/2) y (f_cur's columns, then y's), reduced from its leading
+ *        cap columns when rank(f_cur) + rank(y) > cap.
+ * Reductions use opts (fixed rank).  reports: 3 entries (sweeps 0 for a reduction that was
+ * not needed).  f_next (capacity cap columns, not overlapping the inputs) receives the result
+ * and f_next->r its rank.  Requires rank(f_prev) + rank(f_cur) <= CP_MAX_RANK and
+ * rank(f_cur) + rank(y) <= CP_MAX_RANK.  Temporaries live in the workspace
+ * (cp_workspace_size_ab2). */
+cp_status cp_ab2_step(cp_handle h, const cp_operator* L, double dt, const cp_tensor* f_prev, const cp_tensor* f_cur,
+                      cp_tensor* f_next, const cp_als_opts* opts, cp_als_report* reports);
+
 /* Many independent problems advanced in one persistent launch (one workgroup per problem, or
  * the tuned cluster sizes: see cp_tune_cluster).
  * Arrays of length count: A[i], B[i] (host descriptions), f_init[i], f_io[i] and opts[i]
@@ -341,7 +360,8 @@ cp_status cp_tune_clear(cp_handle h);
  *                            cp_als_step_adaptive on f_io
  *  cp_workspace_size_batched : cp_als_run_batched with these arguments
  *  cp_workspace_size_inner : cp_inner(x, y) and cp_norm(x) (pass y = x)
- *  cp_workspace_size_apply : cp_apply_operator(L, x, .) */
+ *  cp_workspace_size_apply : cp_apply_operator(L, x, .)
+ *  cp_workspace_size_ab2   : cp_ab2_step(L, ., f_prev, f_cur, f_next, opts, .) */
 cp_status cp_workspace_size_step(cp_handle h, const cp_operator* A, const cp_operator* B, const cp_tensor* f_init,
                                  const cp_tensor* source, const cp_tensor* f_io, int32_t n_steps,
                                  const cp_als_opts* opts, size_t* bytes);
@@ -350,6 +370,8 @@ cp_status cp_workspace_size_batched(cp_handle h, int32_t count, const cp_operato
                                     const cp_als_opts* opts, size_t* bytes);
 cp_status cp_workspace_size_inner(cp_handle h, const cp_tensor* x, const cp_tensor* y, size_t* bytes);
 cp_status cp_workspace_size_apply(cp_handle h, const cp_operator* L, const cp_tensor* x, size_t* bytes);
+cp_status cp_workspace_size_ab2(cp_handle h, const cp_operator* L, const cp_tensor* f_prev, const cp_tensor* f_cur,
+                                const cp_tensor* f_next, const cp_als_opts* opts, size_t* bytes);
 
 #ifdef __cplusplus
 }

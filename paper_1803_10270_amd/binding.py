@@ -97,6 +97,10 @@ def lib() -> C.CDLL:
             "cp_als_run": [H, P(cp_operator), P(cp_operator), P(cp_tensor), P(cp_tensor), C.c_int32,
                            P(cp_als_opts), P(cp_als_report), C.c_void_p],
             "cp_truncate": [H, P(cp_tensor), P(cp_tensor), P(cp_als_opts), P(cp_als_report)],
+            "cp_ab2_step": [H, P(cp_operator), C.c_double, P(cp_tensor), P(cp_tensor), P(cp_tensor), P(cp_als_opts),
+                            P(cp_als_report)],
+            "cp_workspace_size_ab2": [H, P(cp_operator), P(cp_tensor), P(cp_tensor), P(cp_tensor), P(cp_als_opts),
+                                      P(C.c_size_t)],
             "cp_als_run_batched": [H, C.c_int32, P(cp_operator), P(cp_operator), P(cp_tensor), P(cp_tensor),
                                    C.c_int32, P(cp_als_opts), P(cp_als_report)],
             "cp_als_default_opts": [P(cp_als_opts)],
@@ -332,6 +336,18 @@ def _opts_array(opts, count):
     if len(opts) != count:
         raise ValueError("need one cp_als_opts per problem")
     return (cp_als_opts * count)(*opts)
+
+
+def cp_ab2_step(h: Handle, L, dt: float, f_prev, f_cur, f_next, opts: Optional[cp_als_opts] = None):
+    """One explicit AB2 step (apply, add, rank-reduce) into f_next (panels of cap columns).
+    Returns (rank of the result, the three reductions' reports)."""
+    opts = default_opts() if opts is None else opts
+    Ld = OperatorDesc(L)
+    pd, cd, nd = tensor_desc(f_prev), tensor_desc(f_cur), tensor_desc(f_next)
+    reps = (cp_als_report * 3)()
+    h.check(lib().cp_ab2_step(h.h, C.byref(Ld.desc), float(dt), C.byref(pd), C.byref(cd), C.byref(nd), C.byref(opts),
+                              reps), allow_not_converged=True)
+    return int(nd.r), [r.as_dict() for r in reps]
 
 
 def cp_als_run_batched(h: Handle, As, Bs, f_inits, f_ios, n_steps: int, opts=None,

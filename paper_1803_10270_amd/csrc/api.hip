@@ -1744,3 +1744,256 @@ cp_status cp_workspace_size_apply(cp_handle h, const cp_operator* L, const cp_te
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------------------
+// explicit second-order Adams-Bashforth step (Section 3.2)
+// ---------------------------------------------------------------------------------------
+namespace {
+
+// A tensor placed in the workspace: element offsets of its panels (column-major n_k x r);
+// until bound, the panel pointers name the placeholder.
+struct WsTensor {
+    cp_tensor t;
+    size_t off[CP_MAX_DIMS];
+};
+
+// Places a d-dimensional tensor of `cols` columns at byte offset `at`; returns the next
+// free (aligned) byte offset.
+size_t ws_place(WsTensor& w, int d, const int32_t* n, int cols, size_t at) {
+    std::memset(&w.t, 0, sizeof(w.t));
+    w.t.d = d;
+    w.t.r = cols;
+    size_t el = at / 8;
+    for (int k = 0; k < d; ++k) {
+        w.t.n[k] = n[k];
+        w.t.ld[k] = n[k];
+        w.t.U[k] = &g_placeholder;
+        w.off[k] = el;
+        el += (size_t)n[k] * cols;
+    }
+    return align_up(el * 8);
+}
+
+void ws_bind(cp_handle h, WsTensor& w) {
+    for (int k = 0; k < w.t.d; ++k) w.t.U[k] = static_cast<double*>(h->ws) + w.off[k];
+}
+
+// Columns [c0, c0 + cols) of t.
+cp_tensor col_view(const cp_tensor& t, int c0, int cols) {
+    cp_tensor v = t;
+    v.r = cols;
+    for (int k = 0; k < t.d; ++k) v.U[k] = t.U[k] + (size_t)c0 * t.ld[k];
+    return v;
+}
+
+// alpha times the identity on the grid of t (one term, the coefficient in dimension 0).
+struct ScaledIdentity {
+    cp_op1d ident[CP_MAX_DIMS];
+    double coef;
+    int32_t idx[CP_MAX_DIMS] = {0};
+    cp_operator op;
+    ScaledIdentity(const cp_tensor& t, double alpha) : coef(alpha) {
+        std::memset(&op, 0, sizeof(op));
+        op.d = t.d;
+        op.n_terms = 1;
+        op.coef = &coef;
+        op.op_index = idx;
+        for (int k = 0; k < t.d; ++k) {
+            ident[k] = cp_op1d{CP_OP_IDENTITY, t.n[k], 0, nullptr};
+            op.n_ops[k] = 1;
+            op.ops[k] = &ident[k];
+        }
+    }
+};
+
+cp_status copy_cols(cp_handle h, const cp_tensor& src, cp_tensor& dst, int cols) {
+    for (int k = 0; k < src.d; ++k)
+        HIP_TRY(hipMemcpy2DAsync(dst.U[k], (size_t)dst.ld[k] * 8, src.U[k], (size_t)src.ld[k] * 8, (size_t)src.n[k] * 8,
+                                 cols, hipMemcpyDeviceToDevice, h->stream),
+                "hipMemcpy2DAsync(columns)");
+    return CP_OK;
+}
+
+void skipped_report(cp_als_report* r, int rank) {
+    std::memset(r, 0, sizeof(*r));
+    r->rel_residual = -1.0;
+    r->final_rank = rank;
+    r->grown_rank = rank;
+}
+
+// Shapes of the three reductions of an AB2 step and the workspace they need.
+struct Ab2Plan {
+    int d = 0, cap = 0, rp = 0, rc = 0, rw = 0, rw2 = 0, T = 0, tlead = 0, ry = 0, rs = 0;
+    bool red1 = false, red2 = false, red3 = false;
+    WsTensor W, Wr, Yg, Y, S;
+    size_t temps = 0, nested = 0;
+};
+
+cp_status ab2_plan(cp_handle h, const cp_operator* L, const cp_tensor* f_prev, const cp_tensor* f_cur,
+                   const cp_tensor* f_next, const cp_als_opts* opts, Ab2Plan& P) {
+    cp_status st = check_tensor(h, f_prev, "f_prev", CP_MAX_N);
+    if (st == CP_OK) st = check_tensor(h, f_cur, "f_cur", CP_MAX_N);
+    if (st == CP_OK) st = check_tensor(h, f_next, "f_next", CP_MAX_N);
+    if (st == CP_OK) st = check_opts(h, opts);
+    if (st != CP_OK) return st;
+    if (adaptive(*opts)) return fail(h, CP_ERR_INVALID_ARG, "the AB2 reductions keep a fixed rank cap (rank_mode fixed)");
+    const int d = f_cur->d;
+    if (f_prev->d != d || f_next->d != d) return fail(h, CP_ERR_SHAPE, "f_prev, f_cur, f_next differ in d");
+    for (int k = 0; k < d; ++k)
+        if (f_prev->n[k] != f_cur->n[k] || f_next->n[k] != f_cur->n[k])
+            return fail(h, CP_ERR_SHAPE, "f_prev, f_cur, f_next differ in n");
+    HostOp hL;
+    st = check_operator(h, L, "L", d, f_cur->n, false, hL);
+    if (st != CP_OK) return st;
+    P.d = d;
+    P.cap = f_next->r;
+    P.rp = f_prev->r;
+    P.rc = f_cur->r;
+    P.T = L->n_terms;
+    P.rw = P.rp + P.rc;
+    if (P.rw > CP_MAX_RANK) return fail(h, CP_ERR_SHAPE, "rank(f_prev) + rank(f_cur) exceeds CP_MAX_RANK");
+    P.red1 = P.rw > P.cap;
+    P.rw2 = std::min(P.rw, P.cap);
+    P.red2 = (int64_t)P.T * P.rw2 > P.cap;
+    P.tlead = P.red2 ? (P.cap + P.rw2 - 1) / P.rw2 : P.T;
+    P.ry = P.red2 ? P.cap : P.T * P.rw2;
+    P.rs = P.rc + P.ry;
+    if (P.rs > CP_MAX_RANK) return fail(h, CP_ERR_SHAPE, "rank(f_cur) + the reduced rank exceeds CP_MAX_RANK");
+    P.red3 = P.rs > P.cap;
+    const int32_t* n = f_cur->n;
+    size_t off = 0;
+    off = ws_place(P.W, d, n, P.rw, off);
+    off = ws_place(P.Wr, d, n, P.cap, off);
+    off = ws_place(P.Yg, d, n, P.tlead * P.rw2, off);
+    off = ws_place(P.Y, d, n, P.ry, off);
+    off = ws_place(P.S, d, n, P.rs, off);
+    P.temps = off;
+    // the nested calls run after the temporaries: the largest of their needs
+    size_t need = 0, b = 0;
+    ApplyPlan AP;
+    st = apply_plan(h, L, f_cur, nullptr, AP);
+    if (st != CP_OK) return st;
+    need = std::max(need, AP.bytes);
+    IdentityOp I(*f_cur);
+    HostOp hI, hI2;
+    if (P.red1) {
+        st = prepare_step(h, &I.I, &I.I, &P.W.t, &P.Wr.t, 1, opts, hI, hI2);
+        if (st == CP_OK) st = run_bytes(h, 1, &hI, &hI2, &P.W.t, &P.Wr.t, 1, opts, &b);
+        if (st != CP_OK) return st;
+        need = std::max(need, b);
+    }
+    if (P.red2) {
+        cp_tensor wv = P.Wr.t;
+        wv.r = P.rw2;
+        HostOp hA, hB;
+        st = prepare_step(h, &I.I, L, &wv, &P.Y.t, 1, opts, hA, hB);
+        if (st == CP_OK) st = run_bytes(h, 1, &hA, &hB, &wv, &P.Y.t, 1, opts, &b);
+        if (st != CP_OK) return st;
+        need = std::max(need, b);
+    }
+    if (P.red3) {
+        cp_tensor fo = *f_next;
+        HostOp hA, hB;
+        st = prepare_step(h, &I.I, &I.I, &P.S.t, &fo, 1, opts, hA, hB);
+        if (st == CP_OK) st = run_bytes(h, 1, &hA, &hB, &P.S.t, &fo, 1, opts, &b);
+        if (st != CP_OK) return st;
+        need = std::max(need, b);
+    }
+    P.nested = need;
+    return CP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+cp_status cp_ab2_step(cp_handle h, const cp_operator* L, double dt, const cp_tensor* f_prev, const cp_tensor* f_cur,
+                      cp_tensor* f_next, const cp_als_opts* opts, cp_als_report* reports) {
+    if (!h) return CP_ERR_INVALID_ARG;
+    if (!reports || !std::isfinite(dt)) return fail(h, CP_ERR_INVALID_ARG, "reports is null or dt is not finite");
+    Ab2Plan P;
+    cp_status st = ab2_plan(h, L, f_prev, f_cur, f_next, opts, P);
+    if (st != CP_OK) return st;
+    st = ensure_ws(h, P.temps + P.nested);
+    if (st != CP_OK) return st;
+    for (WsTensor* w : {&P.W, &P.Wr, &P.Yg, &P.Y, &P.S}) ws_bind(h, *w);
+    const size_t base = P.temps;
+    IdentityOp I(*f_cur);
+    cp_status worst = CP_OK;
+    auto keep = [&](cp_status s) {
+        if (s == CP_ERR_NOT_CONVERGED) worst = s;
+        return s == CP_OK || s == CP_ERR_NOT_CONVERGED;
+    };
+    // i) w = 3 f_{n+1} - f_n (the scalars in dimension 0), reduced to rank <= cap
+    {
+        ScaledIdentity three(*f_cur, 3.0), minus(*f_prev, -1.0);
+        cp_tensor a = col_view(P.W.t, 0, P.rc), b = col_view(P.W.t, P.rc, P.rp);
+        st = apply_impl(h, &three.op, f_cur, &a, base);
+        if (st == CP_OK) st = apply_impl(h, &minus.op, f_prev, &b, base);
+        if (st != CP_OK) return st;
+    }
+    cp_tensor wv = P.W.t;
+    if (P.red1) {
+        st = copy_cols(h, P.W.t, P.Wr.t, P.cap);   // start: the leading cap columns
+        if (st != CP_OK) return st;
+        HostOp hA, hB;
+        st = prepare_step(h, &I.I, &I.I, &P.W.t, &P.Wr.t, 1, opts, hA, hB);
+        if (st == CP_OK) st = run_problems(h, 1, &hA, &hB, &P.W.t, &P.Wr.t, 1, opts, &reports[0], nullptr, base);
+        if (!keep(st)) return st;
+        wv = P.Wr.t;
+    } else {
+        skipped_report(&reports[0], P.rw);
+    }
+    // ii) y = L w, reduced (the ALS fit of L w, from its leading cap columns)
+    if (P.red2) {
+        cp_operator lead = *L;
+        lead.n_terms = P.tlead;
+        st = apply_impl(h, &lead, &wv, &P.Yg.t, base);
+        if (st == CP_OK) st = copy_cols(h, P.Yg.t, P.Y.t, P.cap);
+        if (st != CP_OK) return st;
+        HostOp hA, hB;
+        st = prepare_step(h, &I.I, L, &wv, &P.Y.t, 1, opts, hA, hB);
+        if (st == CP_OK) st = run_problems(h, 1, &hA, &hB, &wv, &P.Y.t, 1, opts, &reports[1], nullptr, base);
+        if (!keep(st)) return st;
+    } else {
+        st = apply_impl(h, L, &wv, &P.Y.t, base);
+        if (st != CP_OK) return st;
+        skipped_report(&reports[1], P.ry);
+    }
+    // iii) f_{n+2} = f_{n+1} + (dt / 2) y, reduced
+    {
+        ScaledIdentity one(*f_cur, 1.0), half(P.Y.t, 0.5 * dt);
+        cp_tensor a = col_view(P.S.t, 0, P.rc), b = col_view(P.S.t, P.rc, P.ry);
+        st = apply_impl(h, &one.op, f_cur, &a, base);
+        if (st == CP_OK) st = apply_impl(h, &half.op, &P.Y.t, &b, base);
+        if (st != CP_OK) return st;
+    }
+    if (P.red3) {
+        st = copy_cols(h, P.S.t, *f_next, P.cap);
+        if (st != CP_OK) return st;
+        HostOp hA, hB;
+        st = prepare_step(h, &I.I, &I.I, &P.S.t, f_next, 1, opts, hA, hB);
+        if (st == CP_OK) st = run_problems(h, 1, &hA, &hB, &P.S.t, f_next, 1, opts, &reports[2], nullptr, base);
+        if (!keep(st)) return st;
+    } else {
+        st = copy_cols(h, P.S.t, *f_next, P.rs);
+        if (st != CP_OK) return st;
+        HIP_TRY(hipStreamSynchronize(h->stream), "hipStreamSynchronize");
+        skipped_report(&reports[2], P.rs);
+        f_next->r = P.rs;
+    }
+    return worst != CP_OK ? fail(h, worst, "an AB2 rank reduction reached max_sweeps") : CP_OK;
+}
+
+cp_status cp_workspace_size_ab2(cp_handle h, const cp_operator* L, const cp_tensor* f_prev, const cp_tensor* f_cur,
+                                const cp_tensor* f_next, const cp_als_opts* opts, size_t* bytes) {
+    if (!h) return CP_ERR_INVALID_ARG;
+    if (!bytes) return fail(h, CP_ERR_INVALID_ARG, "bytes is null");
+    Ab2Plan P;
+    cp_status st = ab2_plan(h, L, f_prev, f_cur, f_next, opts, P);
+    if (st != CP_OK) return st;
+    *bytes = P.temps + P.nested;
+    return CP_OK;
+}
+
+}  // extern "C"
