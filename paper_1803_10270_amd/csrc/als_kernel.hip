@@ -641,10 +641,82 @@ __device__ __forceinline__ uint32_t factor_precond_t(double lam) {
     return fl;
 }
 
+// r <= 32: wave 0 alone inverts the 32 x 32 matrix [H0 + lam I, 0; 0, I] by Gauss-Jordan in
+// registers.  Lane l holds column l & 31 of rows 16 (l >> 5) .. 16 (l >> 5) + 15; the pivot,
+// the pivot row entry of the lane's column and the pivot column entries of the lane's rows
+// arrive by cross-lane permutes, so the 32 pivots need no workgroup barrier.  The pivot
+// loop is unrolled so that every register index is fixed.  Same arithmetic per entry as the
+// LDS form above (select-based update, Newton-refined reciprocal); the padding block stays
+// the identity and does not touch the leading r x r block.
+__device__ __forceinline__ uint32_t factor_precond_wave(double lam) {
+    Smem& s = SMEM;
+    const Problem& pb = s.pb;
+    const int r = pb.r, rr = r * r;
+    __syncthreads();
+    if (tid_here() < 64) {
+        const int lane = tid_here();
+        const int j = lane & 31, h = lane >> 5;
+        double M[16];
+        double dmax = 0.0;
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int i = 16 * h + u;
+            double v = (i == j) ? 1.0 : 0.0;
+            if (i < r && j < r) {
+                v = ldg(pb.H0 + i + j * r);
+                if (i == j) {
+                    v += lam;
+                    dmax = fmax(dmax, v);
+                }
+            }
+            M[u] = v;
+        }
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) dmax = fmax(dmax, __shfl_xor(dmax, off, 64));
+        uint32_t fl = 0;
+#pragma unroll
+        for (int p = 0; p < 32; ++p) {
+            const int ph = p >> 4, pu = p & 15;
+            double piv = __shfl(M[pu], p + 32 * ph, 64);
+            if (p < r) {
+                if (!(piv > 1e-12 * dmax)) fl |= CP_FLAG_REGULARIZED;
+                if (!(piv > 0.0)) piv = (lam > 0.0) ? lam : 1e-300;
+            }
+            const double ip = recip_nr(piv);
+            const double rv = __shfl(M[pu], j + 32 * ph, 64);
+            double cv[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) cv[u] = __shfl(M[u], p + 32 * h, 64);
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const int i = 16 * h + u;
+                const double e = (j == p) ? 1.0 : rv;
+                const double base = (j == p) ? 0.0 : M[u];
+                M[u] = (i == p) ? e * ip : fma(-cv[u] * ip, e, base);
+            }
+        }
+        // symmetrised (the preconditioner of CG must be symmetric) through a transposed copy
+        double* T = s.scratch;
+#pragma unroll
+        for (int u = 0; u < 16; ++u) T[(16 * h + u) + 32 * j] = M[u];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        double* Hout = pb.Hinv + (int64_t)ufirst(s.part) * rr;
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int i = 16 * h + u;
+            if (i < r && j < r) stg(Hout + i + j * r, 0.5 * (M[u] + T[j + 32 * i]));
+        }
+        if (lane == 0) s.iflag = fl;
+    }
+    __syncthreads();
+    return s.iflag;
+}
+
 __device__ __forceinline__ uint32_t factor_precond(double lam) {
-    constexpr int PER_SMALL = (32 * 32 + WG - 1) / WG;
     constexpr int PER_FULL = (CP_MAX_RANK * CP_MAX_RANK + WG - 1) / WG;
-    return (SMEM.pb.r <= 32) ? factor_precond_t<PER_SMALL>(lam) : factor_precond_t<PER_FULL>(lam);
+    return (SMEM.pb.r <= 32) ? factor_precond_wave(lam) : factor_precond_t<PER_FULL>(lam);
 }
 
 // ------------------------------------------------------------------------------------
@@ -1733,6 +1805,8 @@ __global__ void __launch_bounds__(WG) als_persistent(const Problem* __restrict__
             s.sync_ok = 1;
             s.dcount = 0;
             s.kc_key[0] = s.kc_key[1] = nullptr;
+            // this workgroup's copy of the assembled blocks
+
         }
     }
     __syncthreads();
