@@ -135,7 +135,10 @@ typedef enum { CP_RANK_FIXED = 0, CP_RANK_ADAPTIVE = 1 } cp_rank_mode;
  *  tol          : stop when eps_conv = max_q ||Delta f_q|| / ||f|| <= tol after a sweep
  *                 (increment test of Section 3.1 / Appendix B, on the represented tensor)
  *  max_sweeps   : cap on Gauss-Seidel sweeps per solve (>= 1)
- *  precision    : CP_PREC_FP64, or CP_PREC_MIXED (FP32 contractions, FP64 solves/checks)
+ *  precision    : CP_PREC_FP64, or CP_PREC_MIXED: sweeps with the Gram, right-hand-side and
+ *                 matvec contractions in FP32 on the matrix cores (solves, scalars and checks
+ *                 in FP64) until the increment stalls at the FP32 floor, then the Grams in
+ *                 FP64 and FP64 sweeps until eps_conv <= tol
  *  eps_reg      : every per-dimension system is shifted by
  *                 lambda_q = eps_reg * trace(M_q) / (n_q r)  (regularisation, Section 2.1)
  *  pcg_tol      : relative residual target of the per-dimension PCG solve
@@ -184,7 +187,7 @@ typedef struct {
     int32_t final_rank;    /* rank of f_{n+1}                                           */
     int32_t grown_rank;    /* rank before small terms were dropped (replay_rank value   */
                            /* that reproduces this step's growth decisions)             */
-    int32_t reserved;
+    int32_t low_sweeps;    /* sweeps with FP32 contractions (CP_PREC_MIXED), of sweeps  */
 } cp_als_report;
 
 /* Fill `opts` with the defaults (tol 1e-8, max_sweeps 200, FP64, eps_reg 1e-10, pcg_tol
@@ -297,11 +300,12 @@ cp_status cp_ab2_step(cp_handle h, const cp_operator* L, double dt, const cp_ten
  * the tuned cluster sizes: see cp_tune_cluster).
  * Arrays of length count: A[i], B[i] (host descriptions), f_init[i], f_io[i] and opts[i]
  * (each problem has its own options: tolerance, rank mode and cap) as in cp_als_run;
- * reports: count * n_steps entries, problem-major.  In adaptive mode f_io[i].r is updated to
- * problem i's final rank. */
+ * reports: count * n_steps entries, problem-major; traj (nullable, host array of count device
+ * pointers, entries nullable): problem i's trajectory buffer as cp_als_run's.  In adaptive
+ * mode f_io[i].r is updated to problem i's final rank. */
 cp_status cp_als_run_batched(cp_handle h, int32_t count, const cp_operator* A, const cp_operator* B,
                              const cp_tensor* f_init, cp_tensor* f_io, int32_t n_steps,
-                             const cp_als_opts* opts, cp_als_report* reports);
+                             const cp_als_opts* opts, cp_als_report* reports, double* const* traj);
 
 /* The batched run captured once and replayed (the many-instance form of Section 3.1's time
  * stepping, launched as a HIP graph).

@@ -53,12 +53,12 @@ class cp_als_opts(C.Structure):
 class cp_als_report(C.Structure):
     _fields_ = [("sweeps", C.c_int32), ("pcg_iters", C.c_int32), ("eps_conv", C.c_double),
                 ("fnorm", C.c_double), ("rel_residual", C.c_double), ("flags", C.c_uint32),
-                ("final_rank", C.c_int32), ("grown_rank", C.c_int32), ("reserved", C.c_int32)]
+                ("final_rank", C.c_int32), ("grown_rank", C.c_int32), ("low_sweeps", C.c_int32)]
 
     def as_dict(self):
         return {"sweeps": self.sweeps, "pcg_iters": self.pcg_iters, "eps_conv": self.eps_conv,
                 "fnorm": self.fnorm, "rel_residual": self.rel_residual, "flags": self.flags,
-                "final_rank": self.final_rank, "grown_rank": self.grown_rank}
+                "final_rank": self.final_rank, "grown_rank": self.grown_rank, "low_sweeps": self.low_sweeps}
 
 
 class CpalsError(RuntimeError):
@@ -102,7 +102,7 @@ def lib() -> C.CDLL:
             "cp_workspace_size_ab2": [H, P(cp_operator), P(cp_tensor), P(cp_tensor), P(cp_tensor), P(cp_als_opts),
                                       P(C.c_size_t)],
             "cp_als_run_batched": [H, C.c_int32, P(cp_operator), P(cp_operator), P(cp_tensor), P(cp_tensor),
-                                   C.c_int32, P(cp_als_opts), P(cp_als_report)],
+                                   C.c_int32, P(cp_als_opts), P(cp_als_report), C.c_void_p],
             "cp_als_default_opts": [P(cp_als_opts)],
             "cp_residual": [H, P(cp_operator), P(cp_operator), P(cp_tensor), P(cp_tensor), P(C.c_double)],
             "cp_als_step_adaptive": [H, P(cp_operator), P(cp_operator), P(cp_tensor), P(cp_tensor), C.c_int32,
@@ -351,9 +351,10 @@ def cp_ab2_step(h: Handle, L, dt: float, f_prev, f_cur, f_next, opts: Optional[c
 
 
 def cp_als_run_batched(h: Handle, As, Bs, f_inits, f_ios, n_steps: int, opts=None,
-                       ranks: Optional[Sequence[int]] = None) -> List[List[dict]]:
+                       ranks: Optional[Sequence[int]] = None, trajs=None) -> List[List[dict]]:
     """opts: one cp_als_opts for all problems or a list (one each); ranks: guess ranks
-    (adaptive rank: the panels hold opts[i].rank_cap columns)."""
+    (adaptive rank: the panels hold opts[i].rank_cap columns); trajs: None or one float64
+    CUDA buffer (or None) per problem receiving its steps' factors as cp_als_run's traj."""
     count = len(As)
     o_arr = _opts_array(opts, count)
     Ads = [OperatorDesc(a) for a in As]
@@ -363,7 +364,12 @@ def cp_als_run_batched(h: Handle, As, Bs, f_inits, f_ios, n_steps: int, opts=Non
     fi = (cp_tensor * count)(*[tensor_desc(f) for f in f_inits])
     fo = (cp_tensor * count)(*[tensor_desc(f, None if ranks is None else ranks[i]) for i, f in enumerate(f_ios)])
     reps = (cp_als_report * (count * n_steps))()
-    h.check(lib().cp_als_run_batched(h.h, count, A_arr, B_arr, fi, fo, n_steps, o_arr, reps),
+    tp = None
+    if trajs is not None:
+        if len(trajs) != count:
+            raise ValueError("need one trajectory buffer (or None) per problem")
+        tp = (C.c_void_p * count)(*[t.data_ptr() if t is not None else None for t in trajs])
+    h.check(lib().cp_als_run_batched(h.h, count, A_arr, B_arr, fi, fo, n_steps, o_arr, reps, tp),
             allow_not_converged=True)
     return [[reps[i * n_steps + s].as_dict() for s in range(n_steps)] for i in range(count)]
 

@@ -1816,8 +1816,9 @@ __global__ void __launch_bounds__(WG) als_persistent(const Problem* __restrict__
     const int n_steps = ufirst(pb.n_steps), max_sweeps = ufirst(pb.max_sweeps);
     const bool mixed = pb.precision == CP_PREC_MIXED;
     // mixed-precision form: sweeps with FP32 contractions until the increment reaches the
-    // FP32 floor (or the sweep budget is nearly spent), then one FP64 refinement sweep
-    // (with tol = 0 the caller asks for exactly max_sweeps sweeps: FP32 until the last one)
+    // FP32 floor (or the sweep budget is nearly spent), then the Grams again in FP64 and FP64
+    // sweeps until eps_conv <= tol, as the plain method (with tol = 0 the caller asks for
+    // exactly max_sweeps sweeps: FP32 until the last one)
     const double tol_low = pb.tol > 0.0 ? fmax(pb.tol, 1e-6) : 0.0;
 
     int op = OP_STEP;
@@ -1831,6 +1832,7 @@ __global__ void __launch_bounds__(WG) als_persistent(const Problem* __restrict__
     int low_stall = 0;            // FP32 sweeps since that minimum last improved
     int psel = 0;   // which of the two search-direction buffers holds p
     int sweeps_done = 0;          // sweeps of the earlier solves of this step (rank growth)
+    int low_sweeps = 0;           // sweeps of this step with FP32 contractions
     int grown = r;                // rank before the drop of negligible terms
     double rho = -1.0;            // step residual (when formed)
     // the current rank into the LDS descriptor, which the routines read
@@ -1855,7 +1857,7 @@ __global__ void __launch_bounds__(WG) als_persistent(const Problem* __restrict__
                 rep.flags = flags | CP_FLAG_NOT_CONVERGED | CP_FLAG_SYNC_TIMEOUT;
                 rep.final_rank = r;
                 rep.grown_rank = r;
-                rep.reserved = 0;
+                rep.low_sweeps = low_sweeps;
                 pb.reports[step < n_steps ? step : n_steps - 1] = rep;
             }
             break;
@@ -1883,6 +1885,7 @@ __global__ void __launch_bounds__(WG) als_persistent(const Problem* __restrict__
             low_stall = 0;
             pcg_iters = 0;
             sweeps_done = 0;
+            low_sweeps = 0;
             rho = -1.0;
             flags = CP_FLAG_NOT_CONVERGED;
             eps = fnorm = dmax2 = 0.0;
@@ -2068,6 +2071,7 @@ __global__ void __launch_bounds__(WG) als_persistent(const Problem* __restrict__
             scale_grams(r0);
             cluster_sync();
             const bool was_low = lowp;
+            if (was_low) ++low_sweeps;
             bool refresh_all = false;
             bool done = false;
             if (!isfinite(eps)) {
@@ -2090,8 +2094,6 @@ __global__ void __launch_bounds__(WG) als_persistent(const Problem* __restrict__
             } else if (eps <= pb.tol) {
                 flags &= ~CP_FLAG_NOT_CONVERGED;
                 done = true;
-            } else if (mixed) {
-                done = true;   // the single FP64 refinement sweep is done
             }
             if (done || sw >= max_sweeps) {
                 op = pb.report_residual ? OP_RANK : OP_REPORT;
@@ -2149,7 +2151,7 @@ __global__ void __launch_bounds__(WG) als_persistent(const Problem* __restrict__
                 rep.flags = flags;
                 rep.final_rank = r;
                 rep.grown_rank = pb.report_residual ? grown : r;
-                rep.reserved = 0;
+                rep.low_sweeps = low_sweeps;
                 pb.reports[step] = rep;
             }
             if (pb.traj && cpart == 0) {
@@ -2207,7 +2209,7 @@ __global__ void __launch_bounds__(WG) residual_kernel(const Problem* __restrict_
         rep.flags = 0;
         rep.final_rank = pb.r;
         rep.grown_rank = pb.r;
-        rep.reserved = 0;
+        rep.low_sweeps = 0;
         pb.reports[0] = rep;
     }
 }

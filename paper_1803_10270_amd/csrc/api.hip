@@ -821,7 +821,7 @@ cp_status stage_problems(cp_handle h, int count, const HostOp* A, const HostOp* 
 // Rebases the packed problems onto device memory `ws` and uploads their static data and the
 // descriptor array (ordered by estimated cost, largest first, so that the longest problems
 // start first when workgroups outnumber CUs).
-cp_status upload_static(cp_handle h, Staged& S, char* ws, double* traj, const cp_tensor* f_io, hipStream_t st,
+cp_status upload_static(cp_handle h, Staged& S, char* ws, double* const* traj, const cp_tensor* f_io, hipStream_t st,
                         bool wait) {
     const int count = S.count;
     std::vector<int> order(count);
@@ -836,7 +836,7 @@ cp_status upload_static(cp_handle h, Staged& S, char* ws, double* traj, const cp
     for (int i = 0; i < count; ++i) {
         Packed& p = S.pk[i];
         char* b = ws + S.base[i];
-        rebase(p, b, traj);
+        rebase(p, b, traj ? traj[i] : nullptr);
         HIP_TRY(hipMemcpyAsync(b + p.lay.opdata, p.opdata.data(), p.opdata.size() * 8, hipMemcpyHostToDevice, st),
                 "hipMemcpyAsync(opdata)");
         if (!p.pairsC.empty())
@@ -919,7 +919,7 @@ cp_status check_reports(cp_handle h, const cp_als_report* reports, int n) {
 // Packs, uploads and runs `count` problems (options o[i]) in the workspace from byte offset
 // `base` on; in adaptive mode f_io[i].r becomes the last step's rank.
 cp_status run_problems(cp_handle h, int count, const HostOp* A, const HostOp* B, const cp_tensor* f_init,
-                       cp_tensor* f_io, int n_steps, const cp_als_opts* o, cp_als_report* reports, double* traj,
+                       cp_tensor* f_io, int n_steps, const cp_als_opts* o, cp_als_report* reports, double* const* traj,
                        size_t base = 0) {
     // a problem may be shared by a cluster of workgroups (grid rows split between them)
     Staged S;
@@ -1282,7 +1282,7 @@ cp_status cp_als_run(cp_handle h, const cp_operator* A, const cp_operator* B, co
     HostOp hA, hB;
     cp_status st = prepare_step(h, A, B, f_init, f_io, n_steps, opts, hA, hB);
     if (st != CP_OK) return st;
-    return run_problems(h, 1, &hA, &hB, f_init, f_io, n_steps, opts, reports, traj);
+    return run_problems(h, 1, &hA, &hB, f_init, f_io, n_steps, opts, reports, traj ? &traj : nullptr);
 }
 
 cp_status cp_als_step(cp_handle h, const cp_operator* A, const cp_operator* B, const cp_tensor* f_n, cp_tensor* f_next,
@@ -1390,7 +1390,7 @@ cp_status cp_als_step_adaptive(cp_handle h, const cp_operator* A, const cp_opera
 
 cp_status cp_als_run_batched(cp_handle h, int32_t count, const cp_operator* A, const cp_operator* B,
                              const cp_tensor* f_init, cp_tensor* f_io, int32_t n_steps, const cp_als_opts* opts,
-                             cp_als_report* reports) {
+                             cp_als_report* reports, double* const* traj) {
     if (!h) return CP_ERR_INVALID_ARG;
     if (count < 1 || !A || !B || !f_init || !f_io || !opts || !reports)
         return fail(h, CP_ERR_INVALID_ARG, "bad batch arguments");
@@ -1399,7 +1399,7 @@ cp_status cp_als_run_batched(cp_handle h, int32_t count, const cp_operator* A, c
         cp_status st = prepare_step(h, &A[i], &B[i], &f_init[i], &f_io[i], n_steps, &opts[i], hA[i], hB[i]);
         if (st != CP_OK) return fail(h, st, "problem " + std::to_string(i) + ": " + h->err);
     }
-    return run_problems(h, count, hA.data(), hB.data(), f_init, f_io, n_steps, opts, reports, nullptr);
+    return run_problems(h, count, hA.data(), hB.data(), f_init, f_io, n_steps, opts, reports, traj);
 }
 
 }  // extern "C"

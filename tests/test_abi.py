@@ -58,7 +58,7 @@ int main(void) {
   P(cp_als_opts, pcg_tol) P(cp_als_report, flags) P(cp_als_report, fnorm) P(cp_op1d, data)
   P(cp_als_opts, rank_mode) P(cp_als_opts, tau_rank) P(cp_als_opts, rank_cap) P(cp_als_opts, replay_rank)
   P(cp_als_opts, seed) P(cp_als_opts, report_residual) P(cp_als_report, rel_residual)
-  P(cp_als_report, final_rank) P(cp_als_report, grown_rank)
+  P(cp_als_report, final_rank) P(cp_als_report, grown_rank) P(cp_als_report, low_sweeps)
   return 0;
 }
 '''
@@ -86,7 +86,7 @@ int main(void) {
     assert vals["cp_op1d.data"] == B.cp_op1d.data.offset
     for f in ("rank_mode", "tau_rank", "rank_cap", "replay_rank", "seed", "report_residual"):
         assert vals["cp_als_opts." + f] == getattr(B.cp_als_opts, f).offset, f
-    for f in ("rel_residual", "final_rank", "grown_rank"):
+    for f in ("rel_residual", "final_rank", "grown_rank", "low_sweeps"):
         assert vals["cp_als_report." + f] == getattr(B.cp_als_report, f).offset, f
 
 
