@@ -536,7 +536,7 @@ def main():
                     help="plain: the headline line; otherwise that leg alone")
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--batch-steps", type=int, default=20)
-    ap.add_argument("--batch-max-sweeps", type=int, default=1000)
+    ap.add_argument("--batch-max-sweeps", type=int, default=6000)
     ap.add_argument("--plain-sample", type=int, default=8)
     ap.add_argument("--mixed-steps", type=int, default=50)
     ap.add_argument("--learned-train-trajs", type=int, default=100)

@@ -295,6 +295,59 @@ def kinetic_cn(seed: int = 0, n: int = 128, nu: float = 1.0, dt: float = 0.01, f
                    {"nu": nu, "seed": seed, "maxwellian": m, "w": w})
 
 
+def bgk_linear_cn(seed: int = 0, n: int = 32, nu: float = 1.0, dt: float = 0.01, field_rank: int = 3,
+                  eps: float = 0.1, cap: int = 8, n_steps: int = 10, tol: float = 1e-8, vmax: float = 5.0,
+                  x_dependent: bool = True) -> Problem:
+    """The linearised BGK equation with a fixed equilibrium (Section 4.2, eqs. BGK_LIN, opL):
+    f_t = L f + nu f_eq,  L = -sum_i diag(v_i) D_{x_i} - nu I,  f_eq = M(v) (x) 1_x, in 3 space
+    + 3 velocity dimensions (dims 0-2: x, 3-5: v).  Crank-Nicolson with the source applied once:
+    A f_{n+1} = B f_n + c, A = I - dt/2 L, B = I + dt/2 L (4 terms each), c = dt nu f_eq
+    (rank 1, in problem.meta["source"]).  f0 = f_eq + eps M(v) g with g a sum of field_rank
+    separable low-frequency trig products (x-independent when x_dependent is False)."""
+    rng = np.random.default_rng(seed)
+    x = grid(n)
+    v = grid(n, -vmax, vmax)
+    hv = 2 * vmax / n
+    m = maxwellian_1d(v, hv)
+    xops = [op_identity(n), op_central_diff(n)]
+    vops = [op_identity(n), op_diag(v)]
+    ops = [list(xops) for _ in range(3)] + [list(vops) for _ in range(3)]
+    idx = np.zeros((4, 6), np.int32)
+    for i in range(3):
+        idx[1 + i, i] = 1
+        idx[1 + i, 3 + i] = 1
+    coefL = np.array([-nu, -1.0, -1.0, -1.0])
+    cA = -0.5 * dt * coefL
+    cA[0] += 1.0
+    cB = 0.5 * dt * coefL
+    cB[0] += 1.0
+    A = SepOperator(cA, idx.copy(), ops)
+    B = SepOperator(cB, idx.copy(), ops)
+    feq = [np.ones((n, 1)) for _ in range(3)] + [m[:, None].copy() for _ in range(3)]
+    source = [f.copy() for f in feq]
+    source[0] = source[0] * (dt * nu)
+    R = field_rank
+    U = [np.concatenate([f, np.zeros((n, R))], axis=1) for f in feq]
+    for l in range(R):
+        for k in range(6):
+            coord = x if k < 3 else v * (np.pi / vmax)
+            if k < 3 and not x_dependent:
+                g = np.ones(n)
+            else:
+                g = np.zeros(n)
+                for f in range(1, 4):
+                    a, b = rng.standard_normal(2)
+                    g += a * np.cos(f * coord) + b * np.sin(f * coord)
+                g /= np.max(np.abs(g))
+            if k >= 3:
+                g = g * m
+            U[k][:, 1 + l] = g
+        U[0][:, 1 + l] *= eps / R
+    return Problem("bgk_linear_cn", A, B, U, pad_rank(U, cap, seed), cap, dt, n_steps, tol,
+                   {"nu": nu, "seed": seed, "maxwellian": m, "feq": feq, "source": source, "hx": 2 * np.pi / n,
+                    "hv": hv})
+
+
 def config(i: int, seed: int = 0) -> Problem:
     """The five configurations (1-based), full size."""
     if i == 1:

@@ -320,3 +320,55 @@ def test_residual_and_distance_match_full_grid():
     g = full_operator(B) @ cp_full(V).reshape(-1)
     assert abs(O.residual(A, B, U, V) - np.linalg.norm(R) / np.linalg.norm(g)) <= 1e-12
     assert abs(O.rel_distance(U, V) - rel(cp_full(U), cp_full(V))) <= 1e-12
+
+
+# ---------------------------------------------------------------- linearised BGK (fixed f_eq)
+
+def bgk_gamma(p):
+    nu, dt = p.meta["nu"], p.dt
+    return (1.0 - 0.5 * nu * dt) / (1.0 + 0.5 * nu * dt)
+
+
+def cp_mass(U):
+    """Sum of the represented tensor over the grid (products of the factors' column sums)."""
+    return float(np.sum(np.prod([u.sum(axis=0) for u in U], axis=0)))
+
+
+def test_bgk_equilibrium_is_fixed_point():
+    """f = f_eq = M(v) (x) 1_x: v.grad_x f_eq = 0 and the relaxation term vanishes, so the
+    forced Crank-Nicolson step A f = B f_eq + dt nu f_eq has f_eq as its exact solution."""
+    p = W.bgk_linear_cn(seed=0, n=8, cap=1)
+    feq = p.meta["feq"]
+    U, rep = O.als_step(p.A, p.B, feq, feq, tol=1e-14, max_sweeps=50, eps_reg=0.0, source=p.meta["source"])
+    assert O.rel_distance(U, feq) <= 1e-12
+
+
+def test_bgk_x_independent_relaxation_is_exact():
+    """An x-independent perturbation h(v) of f_eq is not transported, and f - f_eq decays by
+    exactly gamma = (1 - nu dt/2) / (1 + nu dt/2) per step (the relaxation experiment of
+    Section 4.2): after N steps f_N = f_eq + gamma^N (f_0 - f_eq)."""
+    p = W.bgk_linear_cn(seed=3, n=8, field_rank=1, cap=2, dt=0.05, x_dependent=False)
+    g = bgk_gamma(p)
+    U = [u.copy() for u in p.f0]
+    for _ in range(4):
+        U, _ = O.als_step(p.A, p.B, U, U, tol=1e-14, max_sweeps=100, eps_reg=0.0, source=p.meta["source"])
+    pert = [u[:, 1:].copy() for u in p.f0]
+    pert[0] *= g ** 4
+    expect = [np.concatenate([f, q], axis=1) for f, q in zip(p.meta["feq"], pert)]
+    assert O.rel_distance(U, expect) <= 1e-11
+
+
+def test_bgk_mass_relaxes_at_the_exact_rate():
+    """Transport conserves the grid sum (periodic differences), so the full-grid step gives
+    M_{n+1} - M_eq = gamma (M_n - M_eq) for any f; the CP-ALS steps follow it to the ALS
+    residual (an x-dependent rank-4 state, rank cap 8, three steps)."""
+    p = W.bgk_linear_cn(seed=5, n=8, field_rank=3, cap=8, dt=0.05, eps=0.3)
+    g = bgk_gamma(p)
+    Meq = cp_mass(p.meta["feq"])
+    M0 = cp_mass(p.f0)
+    U, G = p.f0, p.guess
+    for s in range(3):
+        U, rep = O.als_step(p.A, p.B, U, G, tol=1e-12, max_sweeps=200, source=p.meta["source"])
+        G = U
+        pred = Meq + g ** (s + 1) * (M0 - Meq)
+        assert abs(cp_mass(U) - pred) <= 1e-9 * abs(Meq)
