@@ -348,6 +348,78 @@ def bgk_linear_cn(seed: int = 0, n: int = 32, nu: float = 1.0, dt: float = 0.01,
                     "hv": hv})
 
 
+CD6 = np.array([-1.0, 9.0, -45.0, 0.0, 45.0, -9.0, 1.0]) / 60.0   # 6th-order first derivative, offsets -3..3
+
+
+def op_central_diff6(x: np.ndarray) -> Op1D:
+    """Sixth-order periodic central difference on the uniform grid x (band, half width 3)."""
+    n = x.size
+    h = (x[1] - x[0])
+    return Op1D("band", n, np.repeat((CD6 / h)[:, None], n, axis=1), 3)
+
+
+def op_times_diff6(x: np.ndarray) -> Op1D:
+    """diag(x) times the sixth-order central difference (band, half width 3)."""
+    n = x.size
+    h = (x[1] - x[0])
+    return Op1D("band", n, (CD6 / h)[:, None] * x[None, :], 3)
+
+
+def spiral_generator(C: np.ndarray, x: np.ndarray) -> SepOperator:
+    """L f = -sum_{j,k} C_jk z_k d f / d z_j as a separable operator of N^2 terms in the
+    ordering of the paper's Table (tab:ordering0): term (j, k) has z_j d/dz_j in dimension j when
+    j = k, else d/dz_j in dimension j and z_k in dimension k, coefficient -C_jk.  Distinct
+    operators per dimension: [I, D, Z, Z D]."""
+    N = C.shape[0]
+    n = x.size
+    ops = [[op_identity(n), op_central_diff6(x), op_diag(x), op_times_diff6(x)] for _ in range(N)]
+    idx = np.zeros((N * N, N), np.int32)
+    coef = np.zeros(N * N)
+    for j in range(N):
+        for k in range(N):
+            t = j * N + k
+            if j == k:
+                idx[t, j] = 3
+            else:
+                idx[t, j] = 1
+                idx[t, k] = 2
+            coef[t] = -C[j, k]
+    return SepOperator(coef, idx, ops)
+
+
+def spiral_matrix(seed: int, N: int, decay: float = 0.5) -> np.ndarray:
+    """Seeded C = decay I + K with K skew-symmetric (K = (G - G^T)/2, G ~ N(0, 1)): complex
+    eigenvalues with real part decay > 0, a stable spiral of the characteristics."""
+    rng = np.random.default_rng(seed)
+    G = rng.standard_normal((N, N))
+    return decay * np.eye(N) + 0.5 * (G - G.T)
+
+
+def spiral_advection_cn(seed: int = 0, N: int = 6, n: int = 64, b: float = 6.0, dt: float = 0.01, cap: int = 4,
+                        n_steps: int = 10, tol: float = 1e-8) -> Problem:
+    """The paper's advection benchmark with a linear velocity field (Section 4.1, eq. PDE-advR):
+    f_t + sum_j (C z)_j df/dz_j = 0 on the periodic box [-b, b)^N, f0 = exp(-|z|^2) (rank 1),
+    exact solution f0(exp(-t C) z) (eq. solutionF).  Sixth-order central differences;
+    Crank-Nicolson A = I - dt/2 L, B = I + dt/2 L with N^2 + 1 terms each."""
+    x = grid(n, -b, b)
+    C = spiral_matrix(seed, N)
+    L = spiral_generator(C, x)
+    T = L.n_terms
+    idx = np.concatenate([np.zeros((1, N), np.int32), L.op_index], axis=0)
+    A = SepOperator(np.concatenate([[1.0], -0.5 * dt * L.coef]), idx.copy(), L.ops)
+    B = SepOperator(np.concatenate([[1.0], 0.5 * dt * L.coef]), idx.copy(), L.ops)
+    f0 = [np.exp(-x * x)[:, None] for _ in range(N)]
+    return Problem("spiral_advection_cn", A, B, f0, pad_rank(f0, cap, seed), cap, dt, n_steps, tol,
+                   {"C": C, "L": L, "x": x, "b": b, "terms": T})
+
+
+def spiral_exact(C: np.ndarray, z: np.ndarray, t: float) -> float:
+    """f(z, t) = exp(-|exp(-t C) z|^2) (eq. solutionF with f0 = exp(-|z|^2))."""
+    from scipy.linalg import expm
+    y = expm(-t * C) @ np.asarray(z, dtype=np.float64)
+    return float(np.exp(-y @ y))
+
+
 def config(i: int, seed: int = 0) -> Problem:
     """The five configurations (1-based), full size."""
     if i == 1:
