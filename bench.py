@@ -23,12 +23,14 @@ reports converged / total steps and its residuals rho:
   mixed    FP32 matrix-core sweeps followed by FP64 sweeps to the tolerance, against FP64
            throughout, on the kinetic Crank-Nicolson workload (d = 6, n = 128, rank 64,
            50 steps).
-It also reports the HBM rates of the streaming kernels (cp_inner, cp_apply_operator) and, as
+Under "next" it times the paper's other steps and experiments (damped Jacobi sweeps, the
+linearised BGK equation, the linear-velocity advection with the implicit and the explicit AB2
+step).  It also reports the HBM rates of the streaming kernels (cp_inner, cp_apply_operator) and, as
 cpu_baseline, one converged step of the FP64 oracle on the host (all cores; a single thread
 beside it).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-forms]
-    python bench.py --form learned|batched|mixed|streaming   (that leg alone)
+    python bench.py --form learned|batched|mixed|next|streaming   (that leg alone)
     python bench.py --form calibrate   (a 1 GiB device copy: the load that calibrates the
                                         rocprofv3 FETCH_SIZE / WRITE_SIZE counters)
 
@@ -472,6 +474,127 @@ def bench_streaming(log):
     return out
 
 
+def _at_point(U, x, b, z):
+    """A CP tensor (host factors) at (z, ..., z) by trigonometric interpolation of its
+    periodic factor columns."""
+    n = U[0].shape[0]
+    k = np.fft.fftfreq(n, 1.0 / n)
+    ph = np.exp(1j * k * np.pi * (z - x[0]) / b)
+    vals = np.ones(U[0].shape[1])
+    for u in U:
+        vals = vals * np.real(ph @ (np.fft.fft(u, axis=0) / n))
+    return float(vals.sum())
+
+
+def bench_next(args, log):
+    """The paper's other steps and experiments, each timed on one MI355X:
+      jacobi  the headline workload with damped Jacobi sweeps (Appendix B, damping 1/4)
+              against Gauss-Seidel, same tolerance;
+      bgk     the linearised BGK equation with a fixed equilibrium (Section 4.2), d = 6,
+              n = 64, rank cap 8, Crank-Nicolson with the source dt nu f_eq, 20 steps; the grid
+              mass against its exact relaxation;
+      spiral  the linear-velocity advection of Section 4.1 at N = 6 (37-term implicit step),
+              n = 64, rank 4, 10 Crank-Nicolson steps; the relative error at z* against the
+              exact solution;
+      ab2     the same generator (36 terms) stepped explicitly by AB2 (Section 3.2), rank cap
+              8 (the applied generator L w has a far higher rank than the solution), 20 steps
+              of dt = 0.005 from the Crank-Nicolson first level."""
+    import torch
+    from paper_1803_10270_amd import binding as B
+    from paper_1803_10270_amd import workloads as W
+    h = B.Handle()
+    out = {}
+    # --- Jacobi vs Gauss-Seidel on the headline workload
+    p = W.advection_ie_variable(seed=args.seed)
+    K = 3
+    res = {}
+    for name, mode in (("gauss_seidel", B.SWEEP_GAUSS_SEIDEL), ("jacobi", B.SWEEP_JACOBI)):
+        V, U = B.to_device(p.f0), B.to_device(p.guess)
+        o = B.default_opts(tol=TOL, max_sweeps=4000, sweep_mode=mode)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps = B.cp_als_run(h, p.A, p.B, V, U, K, o)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        res[name] = {"steps_per_s": K / dt, "sweeps": [q["sweeps"] for q in reps],
+                     "converged": "%d/%d" % (sum(1 for q in reps if not (q["flags"] & B.FLAG_NOT_CONVERGED)), K)}
+        res[name]["_U"] = U
+    res["rel_distance_final_states"] = rel_distance_dev(h, res["jacobi"].pop("_U"), res["gauss_seidel"].pop("_U"))
+    out["jacobi"] = dict(workload="advection_ie_variable d=6 n=256 r=32, %d steps, tol 1e-8" % K, **res)
+    log("next: jacobi %.2f steps/s (%s sweeps) vs gauss-seidel %.2f (%s)" % (
+        res["jacobi"]["steps_per_s"], res["jacobi"]["sweeps"], res["gauss_seidel"]["steps_per_s"],
+        res["gauss_seidel"]["sweeps"]))
+    # --- linearised BGK, fixed equilibrium
+    p = W.bgk_linear_cn(seed=args.seed, n=64, cap=8, field_rank=3, eps=0.3, dt=0.01)
+    K = 20
+    src = B.to_device(p.meta["source"])
+    U = B.to_device(p.f0)
+    G = B.to_device(p.guess)
+    o = B.default_opts(tol=TOL, max_sweeps=args.max_sweeps)
+    nu, dtb = p.meta["nu"], p.dt
+    gam = (1 - 0.5 * nu * dtb) / (1 + 0.5 * nu * dtb)
+    mass = lambda F: float(np.sum(np.prod([f.sum(axis=0) for f in F], axis=0)))
+    Meq, M0 = mass(p.meta["feq"]), mass(p.f0)
+    reps = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s_ in range(K):
+        nxt = [g.clone() for g in G]
+        reps.append(B.cp_als_step_source(h, p.A, p.B, U, src, nxt, o))
+        U, G = nxt, nxt
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    Mk = mass(B.to_host(U))
+    out["bgk"] = {"workload": "bgk_linear_cn d=6 (3x+3v) n=64 rank 8, CN dt=0.01, nu=1, %d steps" % K,
+                  "steps_per_s": K / dt, "mean_sweeps": float(np.mean([q["sweeps"] for q in reps])),
+                  "converged": "%d/%d" % (sum(1 for q in reps if not (q["flags"] & B.FLAG_NOT_CONVERGED)), K),
+                  "mass_rel_error_vs_exact_relaxation": abs(Mk - (Meq + gam ** K * (M0 - Meq))) / abs(Meq)}
+    log("next: bgk %.2f steps/s" % out["bgk"]["steps_per_s"])
+    # --- spiral advection, implicit (37 terms) and explicit AB2 (36 terms)
+    zs = 0.698835274542439
+    p = W.spiral_advection_cn(seed=args.seed, N=6, n=64, cap=4)
+    x, b, C = p.meta["x"], p.meta["b"], p.meta["C"]
+    K = 10
+    V, U = B.to_device(p.f0), B.to_device(p.guess)
+    o = B.default_opts(tol=TOL, max_sweeps=args.max_sweeps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = B.cp_als_run(h, p.A, p.B, V, U, K, o)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    fe = W.spiral_exact(C, np.full(6, zs), K * p.dt)
+    out["spiral"] = {"workload": "spiral advection N=6 n=64 on [-6,6)^6, 37-term CN, rank 4, dt=0.01, %d steps" % K,
+                     "steps_per_s": K / dt, "mean_sweeps": float(np.mean([q["sweeps"] for q in reps])),
+                     "converged": "%d/%d" % (sum(1 for q in reps if not (q["flags"] & B.FLAG_NOT_CONVERGED)), K),
+                     "rel_error_at_zstar": abs(_at_point(B.to_host(U), x, b, zs) - fe) / fe}
+    log("next: spiral %.2f steps/s" % out["spiral"]["steps_per_s"])
+    dta, K = 0.005, 20
+    pa = W.spiral_advection_cn(seed=args.seed, N=6, n=64, dt=dta, cap=8)
+    L = pa.meta["L"]
+    g1 = B.to_device(pa.guess)
+    B.cp_als_step(h, pa.A, pa.B, B.to_device(pa.f0), g1, B.default_opts(tol=1e-12, max_sweeps=300))
+    Fp, Fc = B.to_device(pa.f0), [u.clone() for u in g1]
+    oa = B.default_opts(tol=1e-12, max_sweeps=300)
+    sweeps = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(K):
+        outp = [torch.zeros((8, 64), dtype=torch.float64, device="cuda") for _ in range(6)]
+        rank, reps = B.cp_ab2_step(h, L, dta, Fp, Fc, outp, oa)
+        sweeps.append(sum(q["sweeps"] for q in reps))
+        Fp, Fc = Fc, [u[:rank].contiguous() for u in outp]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    fe = W.spiral_exact(C, np.full(6, zs), (K + 1) * dta)
+    out["ab2"] = {"workload": "spiral advection N=6 n=64, explicit AB2 with 36-term generator, rank cap 8, "
+                              "dt=0.005, %d steps" % K,
+                  "steps_per_s": K / dt, "mean_reduction_sweeps": float(np.mean(sweeps)),
+                  "rel_error_at_zstar": abs(_at_point(B.to_host(Fc), x, b, zs) - fe) / fe}
+    log("next: ab2 %.2f steps/s" % out["ab2"]["steps_per_s"])
+    h.close()
+    return out
+
+
 def bench_calibrate(log):
     """A device-to-device copy of 1 GiB (torch): the load whose FETCH_SIZE and WRITE_SIZE
     counters, against the bytes it must move, give the factors that turn the counters into
@@ -532,7 +655,8 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-forms", action="store_true", help="skip the learned, batched and mixed forms")
-    ap.add_argument("--form", default="plain", choices=["plain", "learned", "batched", "mixed", "streaming", "calibrate"],
+    ap.add_argument("--form", default="plain",
+                    choices=["plain", "learned", "batched", "mixed", "next", "streaming", "calibrate"],
                     help="plain: the headline line; otherwise that leg alone")
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--batch-steps", type=int, default=20)
@@ -558,7 +682,7 @@ def main():
     def log(msg):
         print(msg, file=sys.stderr, flush=True)
 
-    single = {"learned": bench_learned, "batched": bench_batched, "mixed": bench_mixed}
+    single = {"learned": bench_learned, "batched": bench_batched, "mixed": bench_mixed, "next": bench_next}
     if args.form in single:
         print(json.dumps(single[args.form](args, log)), flush=True)
         return
@@ -605,7 +729,8 @@ def main():
         out["roofline"]["traffic"] = tr["bytes_per_step"] * args.steps
     if not args.no_forms:
         forms = {}
-        for name, fn in (("learned", bench_learned), ("batched", bench_batched), ("mixed", bench_mixed)):
+        for name, fn in (("learned", bench_learned), ("batched", bench_batched), ("mixed", bench_mixed),
+                         ("next", bench_next)):
             try:
                 forms[name] = fn(args, log)
             except Exception as e:   # a form that cannot run is reported, the headline stands

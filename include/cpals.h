@@ -130,6 +130,7 @@ typedef struct {
 
 typedef enum { CP_PREC_FP64 = 0, CP_PREC_MIXED = 1 } cp_precision;
 typedef enum { CP_RANK_FIXED = 0, CP_RANK_ADAPTIVE = 1 } cp_rank_mode;
+typedef enum { CP_SWEEP_GAUSS_SEIDEL = 0, CP_SWEEP_JACOBI = 1 } cp_sweep_mode;
 
 /* ALS options.
  *  tol          : stop when eps_conv = max_q ||Delta f_q|| / ||f|| <= tol after a sweep
@@ -158,7 +159,13 @@ typedef enum { CP_RANK_FIXED = 0, CP_RANK_ADAPTIVE = 1 } cp_rank_mode;
  *  tau_rank, rank_cap, replay_rank, seed : see rank_mode (rank_cap <= CP_MAX_RANK; the
  *                 output panels must hold rank_cap columns)
  *  report_residual : 1: every step's rho (double-double) into report.rel_residual (the
- *                 problem then runs on one workgroup); adaptive mode always reports it */
+ *                 problem then runs on one workgroup); adaptive mode always reports it
+ *  sweep_mode   : CP_SWEEP_GAUSS_SEIDEL (Section 3.1: q = 1..d in turn, each update from the
+ *                 factors already updated) or CP_SWEEP_JACOBI (Appendix B, Algorithm 1: every
+ *                 dimension solved from the factors at the start of the sweep, then every
+ *                 factor moved by `damping` of its change, U_q <- U_q + damping (U_q' - U_q);
+ *                 the paper divides the change by 4).  eps_conv uses the undamped changes.
+ *  damping      : the Jacobi step fraction, 0 < damping <= 1 (default 0.25) */
 typedef struct {
     double tol;
     int32_t max_sweeps;
@@ -172,7 +179,8 @@ typedef struct {
     int32_t replay_rank;
     uint64_t seed;
     int32_t report_residual;
-    int32_t reserved;
+    int32_t sweep_mode;
+    double damping;
 } cp_als_opts;
 
 /* Per-step report (HOST memory, filled after the call's single stream synchronisation). */
@@ -192,7 +200,7 @@ typedef struct {
 
 /* Fill `opts` with the defaults (tol 1e-8, max_sweeps 200, FP64, eps_reg 1e-10, pcg_tol
  * 1e-14, pcg_max_iter 100, fixed rank, tau_rank 1e-6, rank_cap CP_MAX_RANK, replay_rank -1,
- * seed 0, report_residual 0). */
+ * seed 0, report_residual 0, Gauss-Seidel sweeps, damping 0.25). */
 cp_status cp_als_default_opts(cp_als_opts* opts);
 
 /* <x, y> = sum_{l,l'} prod_k <X_k[:,l], Y_k[:,l']>  (scalar product of CP tensors,

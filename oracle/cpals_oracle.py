@@ -266,11 +266,21 @@ def update_dim(A, B, U: List[np.ndarray], V, q: int, eps_reg: float = 1e-10, sou
 
 
 def als_step(A, B, V: Sequence[np.ndarray], U_init: Sequence[np.ndarray], tol: float = 1e-8,
-             max_sweeps: int = 200, eps_reg: float = 1e-10, source=None):
-    """One implicit time step A f_{n+1} = B f_n (+ c) by Gauss-Seidel ALS (Section 3.1).
+             max_sweeps: int = 200, eps_reg: float = 1e-10, source=None, sweep: str = "gauss-seidel",
+             damping: float = 0.25):
+    """One implicit time step A f_{n+1} = B f_n (+ c) by ALS.
+
+    sweep = "gauss-seidel" (Section 3.1): q = 1..d in turn, each update using the factors
+    already updated in this sweep.  sweep = "jacobi" (Appendix B, Algorithm 1): every
+    dimension is solved from the factors at the start of the sweep, then all factors move by
+    the damping fraction of their change, U_q <- U_q + damping (U_q' - U_q) (the paper divides
+    the change by 4).  In both, eps_conv = max_q ||Delta f_q|| / ||f|| after the sweep, with
+    Delta f_q the (undamped) change of the represented tensor from factor q alone.
 
     Returns (factors of f_{n+1}, report) with report = dict(sweeps, eps_conv, flags,
     sweep_eps) -- sweep_eps lists eps_conv after every sweep."""
+    if sweep not in ("gauss-seidel", "jacobi"):
+        raise ValueError(sweep)
     matsA = _op_mats(A)
     matsB = _op_mats(B)
     U = [np.array(u, dtype=np.float64, copy=True) for u in U_init]
@@ -282,9 +292,17 @@ def als_step(A, B, V: Sequence[np.ndarray], U_init: Sequence[np.ndarray], tol: f
     eps = np.inf
     for s in range(1, max_sweeps + 1):
         dmax = 0.0
-        for q in range(d):
-            U[q], delta = update_dim(A, B, U, V, q, eps_reg, source, matsA, matsB)
-            dmax = max(dmax, delta)
+        if sweep == "gauss-seidel":
+            for q in range(d):
+                U[q], delta = update_dim(A, B, U, V, q, eps_reg, source, matsA, matsB)
+                dmax = max(dmax, delta)
+        else:
+            new = []
+            for q in range(d):
+                Uq, delta = update_dim(A, B, U, V, q, eps_reg, source, matsA, matsB)
+                new.append(Uq)
+                dmax = max(dmax, delta)
+            U = [u + damping * (un - u) for u, un in zip(U, new)]
         fn = cp_norm(U)
         eps = dmax / fn if fn > 0 else dmax
         eps_hist.append(eps)

@@ -25,6 +25,7 @@ CP_OK, CP_ERR_INVALID_ARG, CP_ERR_SHAPE, CP_ERR_UNSUPPORTED, CP_ERR_HIP, CP_ERR_
 FLAG_NOT_CONVERGED, FLAG_PCG_MAXITER, FLAG_REGULARIZED, FLAG_NONFINITE, FLAG_SYNC_TIMEOUT = 1, 2, 4, 8, 16
 PREC_FP64, PREC_MIXED = 0, 1
 RANK_FIXED, RANK_ADAPTIVE = 0, 1
+SWEEP_GAUSS_SEIDEL, SWEEP_JACOBI = 0, 1
 OP_KIND = {"identity": 0, "diag": 1, "band": 2, "rank1": 3}
 
 
@@ -47,7 +48,7 @@ class cp_als_opts(C.Structure):
                 ("eps_reg", C.c_double), ("pcg_tol", C.c_double), ("pcg_max_iter", C.c_int32),
                 ("rank_mode", C.c_int32), ("tau_rank", C.c_double), ("rank_cap", C.c_int32),
                 ("replay_rank", C.c_int32), ("seed", C.c_uint64), ("report_residual", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("sweep_mode", C.c_int32), ("damping", C.c_double)]
 
 
 class cp_als_report(C.Structure):

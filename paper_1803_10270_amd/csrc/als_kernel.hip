@@ -1764,7 +1764,7 @@ __device__ __forceinline__ int drop_small_terms(int r) {
 // ------------------------------------------------------------------------------------
 // the persistent kernel
 // ------------------------------------------------------------------------------------
-enum : int { OP_STEP, OP_REFRESH, OP_UPDATE, OP_CG, OP_DELTA, OP_SWEEP, OP_RANK, OP_REPORT, OP_DONE };
+enum : int { OP_STEP, OP_REFRESH, OP_UPDATE, OP_CG, OP_DELTA, OP_JACOBI, OP_SWEEP, OP_RANK, OP_REPORT, OP_DONE };
 // phases of one dimension update's composite products
 enum : int { PH_RHS, PH_PRE_B, PH_MV_X, PH_PRE_R0, PH_MV_P0, PH_PRE_R, PH_MV_P };
 
@@ -2018,9 +2018,12 @@ __global__ void __launch_bounds__(WG) als_persistent(const Problem* __restrict__
                 op = OP_DELTA;
             }
         } else if (op == OP_DELTA) {
-            // ||Delta f_q||^2 = sum((dU^T dU) o H0), dU = x - U_q; then U_q <- x (own rows)
+            // ||Delta f_q||^2 = sum((dU^T dU) o H0), dU = x - U_q; then U_q <- x (own rows).  A
+            // Jacobi sweep keeps x in Unew_q instead: every dimension of the sweep is solved from
+            // the factors at its start, and the Grams are refreshed once at its end.
             const int n = pb.n[q];
             double* Uq = pb.U + pb.offU[q];
+            double* Udst = pb.jacobi ? pb.Unew + pb.offU[q] : Uq;
             int rlo, rhi;
             own_rows(n, rlo, rhi);
             const int W = ufirst(s.W);
@@ -2033,7 +2036,7 @@ __global__ void __launch_bounds__(WG) als_persistent(const Problem* __restrict__
                     const int l = fdiv(t, invn);
                     return (int64_t)(rlo + (t - l * nown)) + (int64_t)l * n;
                 };
-                batched_loop<8>(nown * r, [&](int t) { return ldg(pb.vx + idx(t)); }, [&](int t, double v) { stg(Uq + idx(t), v); });
+                batched_loop<8>(nown * r, [&](int t) { return ldg(pb.vx + idx(t)); }, [&](int t, double v) { stg(Udst + idx(t), v); });
             }
             __syncthreads();
             // this workgroup's share sum(S_w o H0) of ||Delta f_q||^2 (H0 is the same for every
@@ -2044,10 +2047,43 @@ __global__ void __launch_bounds__(WG) als_persistent(const Problem* __restrict__
             for (int t = tid_here(); t < r * r; t += WG) part = fma(ldg(S + t), ldg(pb.H0 + t), part);
             const double delta2 = ufirst(cluster_sum(wg_sum(part, s.red)));
             dmax2 = fmax(dmax2, delta2);
-            k = q;
-            k_end = q + 1;
-            after = (q + 1 < d) ? OP_UPDATE : OP_SWEEP;
-            q = q + 1;
+            if (pb.jacobi) {
+                q = q + 1;
+                op = (q < d) ? OP_UPDATE : OP_JACOBI;
+            } else {
+                k = q;
+                k_end = q + 1;
+                after = (q + 1 < d) ? OP_UPDATE : OP_SWEEP;
+                q = q + 1;
+                op = OP_REFRESH;
+            }
+        } else if (op == OP_JACOBI) {
+            // end of a Jacobi sweep (Appendix B, Algorithm 1): every factor moves by the damping
+            // fraction of its change, U_k <- U_k + damping (Unew_k - U_k) (own rows); the barrier
+            // publishes the new factors, then every Gram is refreshed
+            const double w = pb.damping;
+            for (int kk = 0; kk < d; ++kk) {
+                const int n = pb.n[kk];
+                int rlo, rhi;
+                own_rows(n, rlo, rhi);
+                const int nown = rhi - rlo;
+                double* Uk = pb.U + pb.offU[kk];
+                const double* Nk = pb.Unew + pb.offU[kk];
+                const float invn = __frcp_rn((float)nown);
+                auto idx = [&](int t) {
+                    const int l = fdiv(t, invn);
+                    return (int64_t)(rlo + (t - l * nown)) + (int64_t)l * n;
+                };
+                batched_loop<8>(nown * r, [&](int t) { return ldg(Nk + idx(t)); }, [&](int t, double v) {
+                    const int64_t o = idx(t);
+                    const double u = ldg(Uk + o);
+                    stg(Uk + o, fma(w, v - u, u));
+                });
+            }
+            cluster_sync();
+            k = 0;
+            k_end = d;
+            after = OP_SWEEP;
             op = OP_REFRESH;
         } else if (op == OP_SWEEP) {
             // ||f||^2 = sum o_k U_k^T U_k

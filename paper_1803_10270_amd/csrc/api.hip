@@ -361,8 +361,8 @@ cp_status compose_t(cp_handle h, const cp_op1d& a, const cp_op1d& b, CompOp& out
 
 // Byte layout of one problem's device region.
 struct Layout {
-    size_t problem, opdata, pairsC, pairsD, U, V, Q, G, X, P, Z, Cm, Dm, H0, Hinv, S, vec, reports, bar, gpart, spart, dpart,
-        termA, termB, Rdd, tv, cv, total;
+    size_t problem, opdata, pairsC, pairsD, U, Unew, V, Q, G, X, P, Z, Cm, Dm, H0, Hinv, S, vec, reports, bar, gpart, spart,
+        dpart, termA, termB, Rdd, tv, cv, total;
     size_t n_opdata, n_pairsC, n_pairsD;
     int64_t offU[CP_MAX_DIMS], offV[CP_MAX_DIMS], offQ[CP_MAX_DIMS], offG[CP_MAX_DIMS], offX[CP_MAX_DIMS];
     int64_t offR[CP_MAX_DIMS], offT[CP_MAX_DIMS], offCv[CP_MAX_DIMS];
@@ -528,6 +528,7 @@ cp_status pack_problem(cp_handle h, const HostOp& A, const HostOp& B, const cp_t
         }
     }
     L.U = take(nU * 8);
+    L.Unew = take(o.sweep_mode == CP_SWEEP_JACOBI ? nU * 8 : 8);
     L.V = take(nV * 8);
     L.Q = take(nQ * 8);
     L.G = take(nG * 8);
@@ -586,6 +587,8 @@ cp_status pack_problem(cp_handle h, const HostOp& A, const HostOp& B, const cp_t
     pb.seed = o.seed;
     pb.TA = A.T;
     pb.TB = B.T;
+    pb.jacobi = o.sweep_mode == CP_SWEEP_JACOBI ? 1 : 0;
+    pb.damping = o.damping;
     // op descriptors get device pointers at rebase time; remember offsets in elements
     for (int k = 0; k < d; ++k) {
         for (int i = 0; i < A.m[k] * A.m[k]; ++i) {
@@ -648,6 +651,7 @@ void rebase(Packed& pk, char* base, double* traj) {
     pb.pairsC = reinterpret_cast<const PairRec*>(base + L.pairsC);
     pb.pairsD = reinterpret_cast<const PairRec*>(base + L.pairsD);
     pb.U = reinterpret_cast<double*>(base + L.U);
+    pb.Unew = reinterpret_cast<double*>(base + L.Unew);
     pb.V = reinterpret_cast<double*>(base + L.V);
     pb.Q = reinterpret_cast<double*>(base + L.Q);
     pb.G = reinterpret_cast<double*>(base + L.G);
@@ -689,6 +693,10 @@ cp_status check_opts(cp_handle h, const cp_als_opts* o) {
         return fail(h, CP_ERR_INVALID_ARG, "adaptive rank needs tau_rank >= 0 and 1 <= rank_cap <= CP_MAX_RANK");
     if (o->report_residual != 0 && o->report_residual != 1)
         return fail(h, CP_ERR_INVALID_ARG, "report_residual must be 0 or 1");
+    if (o->sweep_mode != CP_SWEEP_GAUSS_SEIDEL && o->sweep_mode != CP_SWEEP_JACOBI)
+        return fail(h, CP_ERR_INVALID_ARG, "bad sweep_mode");
+    if (o->sweep_mode == CP_SWEEP_JACOBI && !(o->damping > 0.0 && o->damping <= 1.0))
+        return fail(h, CP_ERR_INVALID_ARG, "Jacobi damping must be in (0, 1]");
     return CP_OK;
 }
 
@@ -1054,6 +1062,8 @@ cp_status cp_als_default_opts(cp_als_opts* o) {
     o->replay_rank = -1;
     o->seed = 0;
     o->report_residual = 0;
+    o->sweep_mode = CP_SWEEP_GAUSS_SEIDEL;
+    o->damping = 0.25;
     return CP_OK;
 }
 

@@ -74,6 +74,11 @@ struct Problem {
     int32_t rcap, rank_mode, replay_rank, report_residual;
     double tau_rank;
     uint64_t seed;
+    // sweeps: Gauss-Seidel (jacobi 0) or damped Jacobi, whose new factors wait in Unew
+    // (offsets offU) until the sweep's end
+    int32_t jacobi, pad2_;
+    double damping;
+    double* Unew;
     // the operators' terms (residual and growth): coef, and per dimension the op index
     int32_t TA, TB;
     const PairRec* termA;

@@ -41,7 +41,7 @@ def test_default_options():
     o = B.default_opts()
     assert o.tol == 1e-8 and o.max_sweeps == 200 and o.eps_reg == 1e-10 and o.precision == B.PREC_FP64
     assert o.rank_mode == B.RANK_FIXED and o.replay_rank == -1 and o.rank_cap == 64 and o.report_residual == 0
-    assert o.tau_rank == 1e-6 and o.seed == 0
+    assert o.tau_rank == 1e-6 and o.seed == 0 and o.sweep_mode == B.SWEEP_GAUSS_SEIDEL and o.damping == 0.25
 
 
 def test_struct_layouts_match_c():
@@ -58,6 +58,7 @@ int main(void) {
   P(cp_als_opts, pcg_tol) P(cp_als_report, flags) P(cp_als_report, fnorm) P(cp_op1d, data)
   P(cp_als_opts, rank_mode) P(cp_als_opts, tau_rank) P(cp_als_opts, rank_cap) P(cp_als_opts, replay_rank)
   P(cp_als_opts, seed) P(cp_als_opts, report_residual) P(cp_als_report, rel_residual)
+  P(cp_als_opts, sweep_mode) P(cp_als_opts, damping)
   P(cp_als_report, final_rank) P(cp_als_report, grown_rank) P(cp_als_report, low_sweeps)
   return 0;
 }
@@ -84,7 +85,7 @@ int main(void) {
     assert vals["cp_als_report.flags"] == B.cp_als_report.flags.offset
     assert vals["cp_als_report.fnorm"] == B.cp_als_report.fnorm.offset
     assert vals["cp_op1d.data"] == B.cp_op1d.data.offset
-    for f in ("rank_mode", "tau_rank", "rank_cap", "replay_rank", "seed", "report_residual"):
+    for f in ("rank_mode", "tau_rank", "rank_cap", "replay_rank", "seed", "report_residual", "sweep_mode", "damping"):
         assert vals["cp_als_opts." + f] == getattr(B.cp_als_opts, f).offset, f
     for f in ("rel_residual", "final_rank", "grown_rank", "low_sweeps"):
         assert vals["cp_als_report." + f] == getattr(B.cp_als_report, f).offset, f

@@ -409,3 +409,32 @@ def test_spiral_exact_solution_satisfies_the_pde():
         grad = np.array([(W.spiral_exact(C, z + e * np.eye(3)[j], t) - W.spiral_exact(C, z - e * np.eye(3)[j], t)) / (2 * e)
                          for j in range(3)])
         assert abs(ft + (C @ z) @ grad) <= 1e-7
+
+
+# ---------------------------------------------------------------- damped Jacobi sweeps (App. B)
+
+def test_jacobi_d1_is_damped_fixed_point_iteration():
+    """d = 1: the one update is the exact minimiser U*, so damped Jacobi sweeps give
+    U_s = U* + (1 - w)^s (U_0 - U*) exactly (checked after three sweeps, w = 1/4)."""
+    p = W.advection_cn_constant(seed=0, d=1, n=24, ic_rank=1, cap=1)
+    Ustar, _ = O.als_step(p.A, p.B, p.f0, p.guess, tol=0.0, max_sweeps=1, eps_reg=0.0)
+    U0 = p.guess[0]
+    U3, rep = O.als_step(p.A, p.B, p.f0, p.guess, tol=0.0, max_sweeps=3, eps_reg=0.0, sweep="jacobi", damping=0.25)
+    expect = Ustar[0] + 0.75 ** 3 * (U0 - Ustar[0])
+    assert np.abs(U3[0] - expect).max() <= 1e-13 * np.abs(expect).max()
+
+
+def test_jacobi_single_direction_advection_is_exact():
+    """Velocity along x_1 only, rank-2 state: the exact step keeps the rank (every column's
+    first factor evolves by the 1-D Crank-Nicolson solve), and the damped Jacobi sweeps
+    converge to that solution as the Gauss-Seidel ones do."""
+    p = W.advection_cn_constant(seed=5, d=3, n=16, dt=0.05, ic_rank=2, cap=2,
+                                velocity=np.array([0.8, 0.0, 0.0]))
+    U, rep = O.als_step(p.A, p.B, p.f0, p.guess, tol=1e-13, max_sweeps=2000, eps_reg=0.0, sweep="jacobi")
+    n = 16
+    D = dense_op(W.op_central_diff(n))
+    th = 0.5 * 0.05 * 0.8
+    cay = np.linalg.solve(np.eye(n) + th * D, np.eye(n) - th * D)
+    ref = [cay @ p.f0[0]] + [u.copy() for u in p.f0[1:]]
+    assert rep["flags"] == 0
+    assert rel(cp_full(U), cp_full(ref)) <= 1e-11
