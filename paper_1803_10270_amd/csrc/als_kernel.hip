@@ -1346,6 +1346,64 @@ __device__ __forceinline__ double cgemm(int n, int r, const OpDev* comps, int nb
 }
 
 // ------------------------------------------------------------------------------------
+// Preconditioner application z = v (H_q + lambda I)^{-1} on the own rows: a row-local r x r
+// product (no stencil, no halo), so plain FMA dot products from LDS replace the matrix-core
+// tile machinery: Hinv (symmetric) is staged once, its loads in flight together with those
+// of the transform that forms v (MODE as in xform_rows, updates of the other vectors riding
+// along), then the rows in chunks of PRC.  Returns this thread's share of sum(v o z).
+// The LDS it uses lies below any operator blocks a composite product keeps across the
+// solve; a kept slot it would overlap is forgotten.
+// ------------------------------------------------------------------------------------
+__device__ __forceinline__ double precond_apply(const Xform& xf, int n, int r, const double* Hinv, double* out,
+                                                int rlo, int rhi) {
+    Smem& s = SMEM;
+    constexpr int PRC = 64;                            // rows per chunk
+    constexpr int HPT = (CP_MAX_RANK * CP_MAX_RANK + WG - 1) / WG;
+    const int rr = r * r;
+    double* Hs = s.scratch;                            // Hinv[l + j r]
+    double* Xs = s.scratch + rr;                       // chunk: v[i, l] at Xs[l (PRC + 1) + i]
+    const int ldx = PRC + 1;
+    __syncthreads();
+    double hv[HPT];
+#pragma unroll
+    for (int u = 0; u < HPT; ++u) {
+        const int t = tid_here() + u * WG;
+        hv[u] = t < rr ? ldg(Hinv + t) : 0.0;
+    }
+    double part = 0.0;
+    bool staged = false;
+    for (int i0 = rlo; i0 < rhi; i0 += PRC) {
+        const int nrow = min(PRC, rhi - i0);
+        if (i0 > rlo) __syncthreads();
+        xform_dispatch(xf, n, i0, nrow, r, true, Xs, ldx, 0);
+        if (!staged) {
+#pragma unroll
+            for (int u = 0; u < HPT; ++u) {
+                const int t = tid_here() + u * WG;
+                if (t < rr) Hs[t] = hv[u];
+            }
+            staged = true;
+        }
+        __syncthreads();
+        const float invr = __frcp_rn((float)nrow);
+        for (int t = tid_here(); t < nrow * r; t += WG) {
+            const int j = fdiv(t, invr), i = t - j * nrow;
+            double acc = 0.0;
+            for (int l = 0; l < r; ++l) acc = fma(Xs[l * ldx + i], Hs[l + j * r], acc);
+            stg(out + (i0 + i) + (int64_t)j * n, acc);
+            part = fma(Xs[j * ldx + i], acc, part);
+        }
+    }
+    __syncthreads();
+    if (tid_here() == 0) {
+        const int used = rr + r * ldx;
+        for (int k = 0; k < 2; ++k)
+            if (s.kc_key[k] && s.kc_base[k] < used) s.kc_key[k] = nullptr;
+    }
+    return part;
+}
+
+// ------------------------------------------------------------------------------------
 // balancing
 // ------------------------------------------------------------------------------------
 
@@ -1937,7 +1995,9 @@ __global__ void __launch_bounds__(WG) als_persistent(const Problem* __restrict__
             const bool f32 = lowp && !pre;
             const int tn = (r + 15) >> 4;
             double part;
-            if (f32) {
+            if (pre) {
+                part = precond_apply(xf, n, r, Kt, outp, rlo, rhi);
+            } else if (f32) {
                 if (tn == 1) part = cgemm<true, 1>(n, r, comps, nblk, rc, xf, Kt, outp, lam, mv, dot, rlo, rhi, slot);
                 else if (tn == 2) part = cgemm<true, 2>(n, r, comps, nblk, rc, xf, Kt, outp, lam, mv, dot, rlo, rhi, slot);
                 else part = cgemm<true, 4>(n, r, comps, nblk, rc, xf, Kt, outp, lam, mv, dot, rlo, rhi, slot);
