@@ -57,10 +57,10 @@ struct Smem {
     uint32_t bar_target;         // arrivals the next cluster barrier waits for (thread 0)
     uint32_t sync_ok;            // 0 once a cluster barrier timed out
     uint32_t dcount;             // calls of cluster_sum (selects the partial buffer)
-    // operator blocks and coefficients kept in LDS across the products of one solve:
-    // slot 0 the matvec, slot 1 the preconditioner (key: the Kt array; cleared per solve)
-    const double* kc_key[2];
-    int32_t kc_base[2], kc_size[2], kc_rlo[2];
+    // operator blocks and coefficients of the matvec kept in LDS across the products of one
+    // solve (key: the Kt array; cleared per solve)
+    const double* kc_key;
+    int32_t kc_base, kc_size, kc_rlo;
 };
 static_assert(sizeof(Smem) <= 160 * 1024, "LDS budget of one workgroup");
 
@@ -221,7 +221,7 @@ __device__ __forceinline__ void apply_panel(const OpDev* ops, int m, int n, int 
     const int nown = rhi - rlo;
     const int total = nown * m * r;
     const float invn = __frcp_rn((float)nown), invr = __frcp_rn((float)r);
-    constexpr int U = 8;
+    constexpr int U = 4;
     for (int t0 = tid_here(); t0 < total; t0 += U * WG) {
         double xv[U][CG_TAPS], cv[U][CG_TAPS];
 #pragma unroll
@@ -278,12 +278,16 @@ __device__ __forceinline__ void apply_panel(const OpDev* ops, int m, int n, int 
 // ------------------------------------------------------------------------------------
 // Gram refresh of one dimension: G_k = P_k^T P_k, X_k = P_k^T Q_k with P_k = [O^a U_k]_a
 // (P_k formed once in the scratch panel, then both products over row chunks staged in LDS).
+// U_k is read from `src` when given (a panel of the same layout that every workgroup has
+// published, while U_k itself may still be written).  With `carry`, the workgroup-uniform
+// cval is summed over the cluster behind the first barrier and the sum returned.
 // ------------------------------------------------------------------------------------
-__device__ __forceinline__ void refresh_dim(int k, int r0, bool lowp) {
+__device__ __forceinline__ double refresh_dim(int k, int r0, bool lowp, const double* src = nullptr, bool carry = false,
+                                              double cval = 0.0) {
     Smem& s = SMEM;
     const Problem& pb = s.pb;
     const int n = pb.n[k], r = pb.r, m = pb.mA[k], mb = pb.mB[k];
-    const double* Uk = pb.U + pb.offU[k];
+    const double* Uk = src ? src : pb.U + pb.offU[k];
     int rlo, rhi;
     own_rows(n, rlo, rhi);
     apply_panel(pb.opA[k], m, n, r, Uk, pb.P, rlo, rhi);
@@ -299,9 +303,12 @@ __device__ __forceinline__ void refresh_dim(int k, int r0, bool lowp) {
     }
     if (lowp) gram_lds<true>(rlo, rhi, M1, N2, fa, fb, G1, M1, G2, M1, s.scratch, SCRATCH);
     else gram_lds<false>(rlo, rhi, M1, N2, fa, fb, G1, M1, G2, M1, s.scratch, SCRATCH);
+    double csum = cval;
     if (W > 1) {
-        // every workgroup adds up its slice of the entries over the cluster's partials
-        cluster_sync();
+        // every workgroup adds up its slice of the entries over the cluster's partials (the
+        // barrier also sums a carried workgroup-uniform value)
+        if (carry) csum = cluster_sum(cval);
+        else cluster_sync();
         const int tot = M1 * M1 + M1 * N2;
         const int per = (tot + W - 1) / W;
         const int e0 = ufirst(s.part) * per, e1 = min(tot, e0 + per);
@@ -321,6 +328,7 @@ __device__ __forceinline__ void refresh_dim(int k, int r0, bool lowp) {
         }
         cluster_sync();
     }
+    return csum;
 }
 
 // Q_k = [O_B^b V_k]_b for every dimension (the fixed B-side panels of a time step).
@@ -642,12 +650,13 @@ __device__ __forceinline__ uint32_t factor_precond_t(double lam) {
 }
 
 // r <= 32: wave 0 alone inverts the 32 x 32 matrix [H0 + lam I, 0; 0, I] by Gauss-Jordan in
-// registers.  Lane l holds column l & 31 of rows 16 (l >> 5) .. 16 (l >> 5) + 15; the pivot,
-// the pivot row entry of the lane's column and the pivot column entries of the lane's rows
-// arrive by cross-lane permutes, so the 32 pivots need no workgroup barrier.  The pivot
-// loop is unrolled so that every register index is fixed.  Same arithmetic per entry as the
-// LDS form above (select-based update, Newton-refined reciprocal); the padding block stays
-// the identity and does not touch the leading r x r block.
+// registers.  The matrix is an 8 x 8 grid of 4 x 4 blocks, lane l holding block
+// (l >> 3, l & 7); for pivot p the pivot, the four pivot-row entries of the lane's columns
+// and the four pivot-column entries of the lane's rows arrive by cross-lane permutes (nine
+// per pivot), so the 32 pivots need no workgroup barrier.  The pivot loop is unrolled so that
+// every register index is fixed.  Same arithmetic per entry as the LDS form above
+// (select-based update, Newton-refined reciprocal); the padding block stays the identity and
+// does not touch the leading r x r block.
 __device__ __forceinline__ uint32_t factor_precond_wave(double lam) {
     Smem& s = SMEM;
     const Problem& pb = s.pb;
@@ -655,59 +664,72 @@ __device__ __forceinline__ uint32_t factor_precond_wave(double lam) {
     __syncthreads();
     if (tid_here() < 64) {
         const int lane = tid_here();
-        const int j = lane & 31, h = lane >> 5;
-        double M[16];
+        const int bi = lane >> 3, bj = lane & 7;
+        double M[4][4];
         double dmax = 0.0;
 #pragma unroll
-        for (int u = 0; u < 16; ++u) {
-            const int i = 16 * h + u;
-            double v = (i == j) ? 1.0 : 0.0;
-            if (i < r && j < r) {
-                v = ldg(pb.H0 + i + j * r);
-                if (i == j) {
-                    v += lam;
-                    dmax = fmax(dmax, v);
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int i = 4 * bi + a, j = 4 * bj + b;
+                double v = (i == j) ? 1.0 : 0.0;
+                if (i < r && j < r) v = ldg(pb.H0 + i + j * r);
+                M[a][b] = v;
+            }
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int i = 4 * bi + a, j = 4 * bj + b;
+                if (i == j && i < r) {
+                    M[a][b] += lam;
+                    dmax = fmax(dmax, M[a][b]);
                 }
             }
-            M[u] = v;
-        }
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) dmax = fmax(dmax, __shfl_xor(dmax, off, 64));
         uint32_t fl = 0;
 #pragma unroll
         for (int p = 0; p < 32; ++p) {
-            const int ph = p >> 4, pu = p & 15;
-            double piv = __shfl(M[pu], p + 32 * ph, 64);
+            const int bp = p >> 2, pa = p & 3;
+            double piv = __shfl(M[pa][pa], 9 * bp, 64);
             if (p < r) {
                 if (!(piv > 1e-12 * dmax)) fl |= CP_FLAG_REGULARIZED;
                 if (!(piv > 0.0)) piv = (lam > 0.0) ? lam : 1e-300;
             }
             const double ip = recip_nr(piv);
-            const double rv = __shfl(M[pu], j + 32 * ph, 64);
-            double cv[16];
+            double rv[4], cv[4];
 #pragma unroll
-            for (int u = 0; u < 16; ++u) cv[u] = __shfl(M[u], p + 32 * h, 64);
+            for (int b = 0; b < 4; ++b) rv[b] = __shfl(M[pa][b], 8 * bp + bj, 64);   // A[p][4 bj + b]
 #pragma unroll
-            for (int u = 0; u < 16; ++u) {
-                const int i = 16 * h + u;
-                const double e = (j == p) ? 1.0 : rv;
-                const double base = (j == p) ? 0.0 : M[u];
-                M[u] = (i == p) ? e * ip : fma(-cv[u] * ip, e, base);
-            }
+            for (int a = 0; a < 4; ++a) cv[a] = __shfl(M[a][pa], 8 * bi + bp, 64);   // A[4 bi + a][p]
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const int i = 4 * bi + a, j = 4 * bj + b;
+                    const double e = (j == p) ? 1.0 : rv[b];
+                    const double base = (j == p) ? 0.0 : M[a][b];
+                    M[a][b] = (i == p) ? e * ip : fma(-cv[a] * ip, e, base);
+                }
         }
-        // symmetrised (the preconditioner of CG must be symmetric) through a transposed copy
+        // symmetrised (the preconditioner of CG must be symmetric) through a copy in LDS
         double* T = s.scratch;
 #pragma unroll
-        for (int u = 0; u < 16; ++u) T[(16 * h + u) + 32 * j] = M[u];
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) T[(4 * bi + a) + 32 * (4 * bj + b)] = M[a][b];
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         double* Hout = pb.Hinv + (int64_t)ufirst(s.part) * rr;
 #pragma unroll
-        for (int u = 0; u < 16; ++u) {
-            const int i = 16 * h + u;
-            if (i < r && j < r) stg(Hout + i + j * r, 0.5 * (M[u] + T[j + 32 * i]));
-        }
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int i = 4 * bi + a, j = 4 * bj + b;
+                if (i < r && j < r) stg(Hout + i + j * r, 0.5 * (M[a][b] + T[j + 32 * i]));
+            }
         if (lane == 0) s.iflag = fl;
     }
     __syncthreads();
@@ -749,11 +771,12 @@ struct Xform {
 
 // Transform of the rows [rlo, rlo + nown) of an n-row panel of rc columns (ld n): all loads
 // of a batch are issued before any store.  MODE 0: v = a; 1: v = a, wv = v; 2: v = a + beta b,
-// wv = v; 3: as 2 and x2 += alpha2 p2.  With `lds`, v goes to Xs[l ldx + H + (i - rlo)].
+// wv = v; 3: as 2 and x2 += alpha2 p2.  With `lds`, v goes to Xs[l ldx + H + (i - rlo)] and,
+// given Xa, the untransformed a to the same place of Xa.
 template <int MODE>
 __device__ __forceinline__ void xform_rows(const Xform& xf, int n, int rlo, int nown, int rc, bool lds, double* Xs,
-                                           int ldx, int H) {
-    constexpr int U = 8;
+                                           int ldx, int H, double* Xa) {
+    constexpr int U = 4;
     const int total = nown * rc;
     const float invn = __frcp_rn((float)nown);
     for (int t0 = tid_here(); t0 < total; t0 += U * WG) {
@@ -780,6 +803,7 @@ __device__ __forceinline__ void xform_rows(const Xform& xf, int n, int rlo, int 
                 if (lds) {
                     const int l = fdiv(t, invn);
                     Xs[l * ldx + H + (t - l * nown)] = v;
+                    if (Xa) Xa[l * ldx + H + (t - l * nown)] = va[u];
                 }
             }
         }
@@ -787,13 +811,13 @@ __device__ __forceinline__ void xform_rows(const Xform& xf, int n, int rlo, int 
 }
 
 __device__ __forceinline__ void xform_dispatch(const Xform& xf, int n, int rlo, int nown, int rc, bool lds, double* Xs,
-                                               int ldx, int H) {
+                                               int ldx, int H, double* Xa = nullptr) {
     const int mode = xf.x2 ? 3 : (xf.b ? 2 : (xf.wv ? 1 : 0));
     switch (ufirst(mode)) {
-        case 0: xform_rows<0>(xf, n, rlo, nown, rc, lds, Xs, ldx, H); break;
-        case 1: xform_rows<1>(xf, n, rlo, nown, rc, lds, Xs, ldx, H); break;
-        case 2: xform_rows<2>(xf, n, rlo, nown, rc, lds, Xs, ldx, H); break;
-        default: xform_rows<3>(xf, n, rlo, nown, rc, lds, Xs, ldx, H); break;
+        case 0: xform_rows<0>(xf, n, rlo, nown, rc, lds, Xs, ldx, H, Xa); break;
+        case 1: xform_rows<1>(xf, n, rlo, nown, rc, lds, Xs, ldx, H, Xa); break;
+        case 2: xform_rows<2>(xf, n, rlo, nown, rc, lds, Xs, ldx, H, Xa); break;
+        default: xform_rows<3>(xf, n, rlo, nown, rc, lds, Xs, ldx, H, Xa); break;
     }
 }
 
@@ -805,7 +829,7 @@ __device__ __forceinline__ void xform_dispatch(const Xform& xf, int n, int rlo, 
 template <int MODE>
 __device__ __forceinline__ void xform_stage(const Xform& xf, int n, int i0, int nrow, int H, int rc, double* Xs,
                                             int ldx) {
-    constexpr int U = 8;
+    constexpr int U = 4;
     const int R = nrow + 2 * H;
     const int total = R * rc;
     const float invR = __frcp_rn((float)R);
@@ -853,7 +877,7 @@ __device__ __forceinline__ void xform_stage_dispatch(const Xform& xf, int n, int
 template <bool F32, int TN>
 __device__ __forceinline__ double cgemm(int n, int r, const OpDev* comps, int nblk, int rc, Xform xf,
                                         const double* Kt, double* out, double lam, bool shift, bool dot, int rlo, int rhi,
-                                        int slot) {
+                                        bool keepable) {
     constexpr int SPW = (TN == 4) ? 2 : 4;   // 16-row strips per wave and pass
     constexpr int LDB = TN * 16 + 1;
     constexpr int PF = (64 * TN * 16 + WG - 1) / WG;
@@ -895,17 +919,15 @@ __device__ __forceinline__ double cgemm(int n, int r, const OpDev* comps, int nb
     // staged rows (short passes: a cluster's share of the grid), they are staged once per
     // pass; otherwise block b + 1 is prefetched while block b is consumed.
     const bool allk = ufirst((int)(ldx * rc + nblk * (ktsz + CG_TAPS * RP) <= SCRATCH)) != 0;
-    // Kept blocks (one pass, every block staged): the slot of this product sits at the top of
-    // the scratch area (slot 1 highest, slot 0 below the space slot 1 takes), the staged rows
-    // and the reduction area of the block split at the bottom.  A slot is reused when its key,
-    // place and rows match.
+    // Kept blocks (one pass, every block staged): they sit at the top of the scratch area, the
+    // staged rows and the reduction area of the block split at the bottom.  They are reused
+    // when key, place and rows match.
     const int REDSZ = NWAVES * TN * 256;
     const int SA = nblk * (ktsz + CG_TAPS * RP);
-    const int top1 = ufirst(s.kc_key[1] ? max(s.kc_size[1], ktsz + CG_TAPS * RP) : ktsz + CG_TAPS * RP);
-    const int kbase = slot == 1 ? SCRATCH - SA : SCRATCH - top1 - SA;
-    const bool keep = ufirst((int)(slot >= 0 && allk && npass == 1 && ldx * rc + REDSZ <= kbase)) != 0;
-    const bool hit = keep && ufirst((int)(s.kc_key[slot] == Kt && s.kc_base[slot] == kbase && s.kc_size[slot] == SA &&
-                                          s.kc_rlo[slot] == rlo)) != 0;
+    const int kbase = SCRATCH - SA;
+    const bool keep = ufirst((int)(keepable && allk && npass == 1 && ldx * rc + REDSZ <= kbase)) != 0;
+    const bool hit = keep && ufirst((int)(s.kc_key == Kt && s.kc_base == kbase && s.kc_size == SA &&
+                                          s.kc_rlo == rlo)) != 0;
     double* Xs = s.scratch;
     double* KtS = keep ? s.scratch + kbase : s.scratch + ldx * rc;   // [nkb][rc4][LDB]
     double* CfS = KtS + (allk ? nblk : 2) * ktsz;        // [nkb][CG_TAPS][RP] stencil coefficients
@@ -955,7 +977,7 @@ __device__ __forceinline__ double cgemm(int n, int r, const OpDev* comps, int nb
             xform_stage_dispatch(xf, n, i0, nrow, H, rc, Xs, ldx);
         } else {
             const float invR = __frcp_rn((float)R);
-            batched_loop<8>(
+            batched_loop<4>(
                 R * rc,
                 [&](int t) {
                     const int l = fdiv(t, invR);
@@ -1011,7 +1033,7 @@ __device__ __forceinline__ double cgemm(int n, int r, const OpDev* comps, int nb
             constexpr int TW = TN * 16;
             const int per = rc4 * TW;
             const float invper = __frcp_rn((float)per);
-            batched_loop<8>(
+            batched_loop<4>(
                 nkb * per,
                 [&](int t) {
                     const int b = fdiv(t, invper), e = t - b * per;
@@ -1057,7 +1079,7 @@ __device__ __forceinline__ double cgemm(int n, int r, const OpDev* comps, int nb
         } else if (allk) {
             const int per = CG_TAPS * RP;
             const float invper = __frcp_rn((float)per);
-            batched_loop<8>(
+            batched_loop<4>(
                 nblk * per,
                 [&](int t) {
                     const int b = fdiv(t, invper), e = t - b * per;
@@ -1326,20 +1348,16 @@ __device__ __forceinline__ double cgemm(int n, int r, const OpDev* comps, int nb
         }
         __syncthreads();
     }
-    // slot bookkeeping: record this product's slot; forget a slot whose space this product
-    // used (any product that does not keep its blocks forgets both)
+    // bookkeeping of the kept blocks: recorded, or forgotten by a product that used their space
     __syncthreads();
     if (tid_here() == 0) {
         if (keep) {
-            s.kc_key[slot] = Kt;
-            s.kc_base[slot] = kbase;
-            s.kc_size[slot] = SA;
-            s.kc_rlo[slot] = rlo;
-            const int o = 1 - slot;
-            if (s.kc_key[o] && !(s.kc_base[o] >= kbase + SA || s.kc_base[o] + s.kc_size[o] <= kbase) ) s.kc_key[o] = nullptr;
-            if (s.kc_key[o] && s.kc_base[o] < ldx * rc + REDSZ) s.kc_key[o] = nullptr;
+            s.kc_key = Kt;
+            s.kc_base = kbase;
+            s.kc_size = SA;
+            s.kc_rlo = rlo;
         } else {
-            s.kc_key[0] = s.kc_key[1] = nullptr;
+            s.kc_key = nullptr;
         }
     }
     return part;
@@ -1350,12 +1368,14 @@ __device__ __forceinline__ double cgemm(int n, int r, const OpDev* comps, int nb
 // product (no stencil, no halo), so plain FMA dot products from LDS replace the matrix-core
 // tile machinery: Hinv (symmetric) is staged once, its loads in flight together with those
 // of the transform that forms v (MODE as in xform_rows, updates of the other vectors riding
-// along), then the rows in chunks of PRC.  Returns this thread's share of sum(v o z).
+// along), then the rows in chunks of PRC.  Returns this thread's share of sum(v o z); with
+// `adot`, also its share of sum(a o (a Hinv)) for the untransformed panel a in `adot_part`
+// (b^T P^{-1} b of the stopping test rides along with the first residual).
 // The LDS it uses lies below any operator blocks a composite product keeps across the
-// solve; a kept slot it would overlap is forgotten.
+// solve; kept blocks it would overlap are forgotten.
 // ------------------------------------------------------------------------------------
 __device__ __forceinline__ double precond_apply(const Xform& xf, int n, int r, const double* Hinv, double* out,
-                                                int rlo, int rhi) {
+                                                int rlo, int rhi, bool adot, double& adot_part) {
     Smem& s = SMEM;
     constexpr int PRC = 64;                            // rows per chunk
     constexpr int HPT = (CP_MAX_RANK * CP_MAX_RANK + WG - 1) / WG;
@@ -1363,6 +1383,7 @@ __device__ __forceinline__ double precond_apply(const Xform& xf, int n, int r, c
     double* Hs = s.scratch;                            // Hinv[l + j r]
     double* Xs = s.scratch + rr;                       // chunk: v[i, l] at Xs[l (PRC + 1) + i]
     const int ldx = PRC + 1;
+    double* Xa = adot ? Xs + r * ldx : nullptr;        // chunk of a (with adot)
     __syncthreads();
     double hv[HPT];
 #pragma unroll
@@ -1370,12 +1391,12 @@ __device__ __forceinline__ double precond_apply(const Xform& xf, int n, int r, c
         const int t = tid_here() + u * WG;
         hv[u] = t < rr ? ldg(Hinv + t) : 0.0;
     }
-    double part = 0.0;
+    double part = 0.0, pa = 0.0;
     bool staged = false;
     for (int i0 = rlo; i0 < rhi; i0 += PRC) {
         const int nrow = min(PRC, rhi - i0);
         if (i0 > rlo) __syncthreads();
-        xform_dispatch(xf, n, i0, nrow, r, true, Xs, ldx, 0);
+        xform_dispatch(xf, n, i0, nrow, r, true, Xs, ldx, 0, Xa);
         if (!staged) {
 #pragma unroll
             for (int u = 0; u < HPT; ++u) {
@@ -1392,13 +1413,18 @@ __device__ __forceinline__ double precond_apply(const Xform& xf, int n, int r, c
             for (int l = 0; l < r; ++l) acc = fma(Xs[l * ldx + i], Hs[l + j * r], acc);
             stg(out + (i0 + i) + (int64_t)j * n, acc);
             part = fma(Xs[j * ldx + i], acc, part);
+            if (adot) {
+                double acc2 = 0.0;
+                for (int l = 0; l < r; ++l) acc2 = fma(Xa[l * ldx + i], Hs[l + j * r], acc2);
+                pa = fma(Xa[j * ldx + i], acc2, pa);
+            }
         }
     }
+    adot_part = pa;
     __syncthreads();
     if (tid_here() == 0) {
-        const int used = rr + r * ldx;
-        for (int k = 0; k < 2; ++k)
-            if (s.kc_key[k] && s.kc_base[k] < used) s.kc_key[k] = nullptr;
+        const int used = rr + (adot ? 2 : 1) * r * ldx;
+        if (s.kc_key && s.kc_base < used) s.kc_key = nullptr;
     }
     return part;
 }
@@ -1563,7 +1589,7 @@ __device__ __forceinline__ void gram_dd(int k, int r, int r0) {
             const int nr = min(RB, n - i0);
             const float invnr = __frcp_rn((float)nr);
             __syncthreads();
-            batched_loop<8>(
+            batched_loop<4>(
                 nr * N,
                 [&](int t) {
                     const int c = fdiv(t, invnr);
@@ -1824,7 +1850,7 @@ __device__ __forceinline__ int drop_small_terms(int r) {
 // ------------------------------------------------------------------------------------
 enum : int { OP_STEP, OP_REFRESH, OP_UPDATE, OP_CG, OP_DELTA, OP_JACOBI, OP_SWEEP, OP_RANK, OP_REPORT, OP_DONE };
 // phases of one dimension update's composite products
-enum : int { PH_RHS, PH_PRE_B, PH_MV_X, PH_PRE_R0, PH_MV_P0, PH_PRE_R, PH_MV_P };
+enum : int { PH_RHS, PH_MV_X, PH_PRE_R0, PH_MV_P0, PH_PRE_R, PH_MV_P };
 
 __global__ void __launch_bounds__(WG) als_persistent(const Problem* __restrict__ problems, int count, int W,
                                                       const int32_t* __restrict__ wg_first) {
@@ -1862,7 +1888,7 @@ __global__ void __launch_bounds__(WG) als_persistent(const Problem* __restrict__
             s.bar_target = 0;
             s.sync_ok = 1;
             s.dcount = 0;
-            s.kc_key[0] = s.kc_key[1] = nullptr;
+            s.kc_key = nullptr;
             // this workgroup's copy of the assembled blocks
 
         }
@@ -1893,6 +1919,8 @@ __global__ void __launch_bounds__(WG) als_persistent(const Problem* __restrict__
     int low_sweeps = 0;           // sweeps of this step with FP32 contractions
     int grown = r;                // rank before the drop of negligible terms
     double rho = -1.0;            // step residual (when formed)
+    bool carry = false;           // a share of ||Delta f_q||^2 waits for the next refresh's barrier
+    double carry_val = 0.0;
     // the current rank into the LDS descriptor, which the routines read
     auto set_rank = [&](int rn) {
         __syncthreads();
@@ -1954,7 +1982,13 @@ __global__ void __launch_bounds__(WG) als_persistent(const Problem* __restrict__
             after = OP_UPDATE;
             op = OP_REFRESH;
         } else if (op == OP_REFRESH) {
-            refresh_dim(k, r0, lowp);
+            if (carry) {
+                // dimension k was just solved: its Grams from x, with the sum of ||Delta f_k||^2
+                dmax2 = fmax(dmax2, ufirst(refresh_dim(k, r0, lowp, pb.vx, true, carry_val)));
+                carry = false;
+            } else {
+                refresh_dim(k, r0, lowp);
+            }
             ++k;
             if (k >= k_end) op = after;
         } else if (op == OP_UPDATE) {
@@ -1967,7 +2001,7 @@ __global__ void __launch_bounds__(WG) als_persistent(const Problem* __restrict__
             const int m = pb.mA[q];
             const int64_t oq = pb.offU[q];
             const bool mv = ph == PH_MV_X || ph == PH_MV_P0 || ph == PH_MV_P;
-            const bool pre = ph == PH_PRE_B || ph == PH_PRE_R0 || ph == PH_PRE_R;
+            const bool pre = ph == PH_PRE_R0 || ph == PH_PRE_R;
             const OpDev* comps = pre ? &s.ident : (mv ? pb.compAA[q] : pb.compAB[q]);
             const int nblk = pre ? 1 : (mv ? m * m : m * pb.mB[q]);
             const int rc = ph == PH_RHS ? r0 : r;
@@ -1980,7 +2014,6 @@ __global__ void __launch_bounds__(WG) als_persistent(const Problem* __restrict__
             Xform xf{nullptr, nullptr, 0.0, nullptr, nullptr, nullptr, 0.0};
             switch (ph) {
                 case PH_RHS: xf.a = pb.V + pb.offV[q]; break;
-                case PH_PRE_B: xf.a = pb.vb; break;
                 case PH_MV_X: xf.a = pb.U + oq; xf.wv = pb.vx; break;                 // x <- U_q
                 case PH_PRE_R0: xf.a = pb.vb; xf.b = pb.vw; xf.beta = -1.0; xf.wv = pb.vr; break;  // r = b - A x
                 case PH_MV_P0: xf.a = pb.vz; xf.wv = pcur; break;                     // p = z
@@ -1991,29 +2024,27 @@ __global__ void __launch_bounds__(WG) als_persistent(const Problem* __restrict__
                 default: xf.a = pb.vz; xf.b = pcur; xf.beta = beta; xf.wv = pnxt; break;  // p' = z + beta p
             }
             const bool dot = ph != PH_RHS && ph != PH_MV_X;
-            const int slot = pre ? 1 : (mv ? 0 : -1);
             const bool f32 = lowp && !pre;
             const int tn = (r + 15) >> 4;
-            double part;
+            double part, part_b = 0.0;
             if (pre) {
-                part = precond_apply(xf, n, r, Kt, outp, rlo, rhi);
+                part = precond_apply(xf, n, r, Kt, outp, rlo, rhi, ph == PH_PRE_R0, part_b);
             } else if (f32) {
-                if (tn == 1) part = cgemm<true, 1>(n, r, comps, nblk, rc, xf, Kt, outp, lam, mv, dot, rlo, rhi, slot);
-                else if (tn == 2) part = cgemm<true, 2>(n, r, comps, nblk, rc, xf, Kt, outp, lam, mv, dot, rlo, rhi, slot);
-                else part = cgemm<true, 4>(n, r, comps, nblk, rc, xf, Kt, outp, lam, mv, dot, rlo, rhi, slot);
+                if (tn == 1) part = cgemm<true, 1>(n, r, comps, nblk, rc, xf, Kt, outp, lam, mv, dot, rlo, rhi, mv);
+                else if (tn == 2) part = cgemm<true, 2>(n, r, comps, nblk, rc, xf, Kt, outp, lam, mv, dot, rlo, rhi, mv);
+                else part = cgemm<true, 4>(n, r, comps, nblk, rc, xf, Kt, outp, lam, mv, dot, rlo, rhi, mv);
             } else {
-                if (tn == 1) part = cgemm<false, 1>(n, r, comps, nblk, rc, xf, Kt, outp, lam, mv, dot, rlo, rhi, slot);
-                else if (tn == 2) part = cgemm<false, 2>(n, r, comps, nblk, rc, xf, Kt, outp, lam, mv, dot, rlo, rhi, slot);
-                else part = cgemm<false, 4>(n, r, comps, nblk, rc, xf, Kt, outp, lam, mv, dot, rlo, rhi, slot);
+                if (tn == 1) part = cgemm<false, 1>(n, r, comps, nblk, rc, xf, Kt, outp, lam, mv, dot, rlo, rhi, mv);
+                else if (tn == 2) part = cgemm<false, 2>(n, r, comps, nblk, rc, xf, Kt, outp, lam, mv, dot, rlo, rhi, mv);
+                else part = cgemm<false, 4>(n, r, comps, nblk, rc, xf, Kt, outp, lam, mv, dot, rlo, rhi, mv);
             }
-            // dot products are summed over the cluster (fixed order); b^T P^{-1} b is only needed
-            // by the stopping test two phases later, so its sum rides with that of r^T P^{-1} r
+            // dot products are summed over the cluster (fixed order); b^T P^{-1} b of the stopping
+            // test is summed with r^T P^{-1} r of the first residual
             double val;
-            if (ph == PH_PRE_B) {
-                val = ufirst(wg_sum(part, s.red));
-            } else if (ph == PH_PRE_R0) {
+            if (ph == PH_PRE_R0) {
                 double sv, su;
-                cluster_sum2(wg_sum(part, s.red), bz, sv, su);
+                const double bpart = wg_sum(part_b, s.red);
+                cluster_sum2(wg_sum(part, s.red), bpart, sv, su);
                 val = ufirst(sv);
                 bz = ufirst(su);
             } else {
@@ -2024,13 +2055,9 @@ __global__ void __launch_bounds__(WG) als_persistent(const Problem* __restrict__
             switch (ph) {
                 case PH_RHS:
                     // the new update's blocks and preconditioner: nothing kept is valid
-                    if (tid_here() == 0) s.kc_key[0] = s.kc_key[1] = nullptr;
+                    if (tid_here() == 0) s.kc_key = nullptr;
                     flags |= factor_precond(lam);
                     psel = 0;
-                    ph = PH_PRE_B;
-                    break;
-                case PH_PRE_B:
-                    bz = val;   // this workgroup's share until the next cluster sum
                     ph = PH_MV_X;
                     break;
                 case PH_MV_X:
@@ -2086,9 +2113,11 @@ __global__ void __launch_bounds__(WG) als_persistent(const Problem* __restrict__
             double* Udst = pb.jacobi ? pb.Unew + pb.offU[q] : Uq;
             int rlo, rhi;
             own_rows(n, rlo, rhi);
-            const int W = ufirst(s.W);
-            double* S = W > 1 ? pb.spart + (int64_t)cpart * r * r : pb.S;
-            gram_lds<false>(rlo, rhi, r, 0, DiffF{pb.vx, Uq, n}, DiffF{pb.vx, Uq, n}, S, r, nullptr, 0, s.scratch, SCRATCH);
+            // the own rows' share of sum_i dU_i H0 dU_i^T (dU = x - U_q, written to the free
+            // panel vw; H0 symmetric): the quadratic form of the preconditioner apply
+            Xform dxf{pb.vx, Uq, -1.0, pb.vw, nullptr, nullptr, 0.0};
+            double unused;
+            const double part = precond_apply(dxf, n, r, pb.H0, pb.vz, rlo, rhi, false, unused);
             {
                 const int nown = rhi - rlo;
                 const float invn = __frcp_rn((float)nown);
@@ -2096,21 +2125,20 @@ __global__ void __launch_bounds__(WG) als_persistent(const Problem* __restrict__
                     const int l = fdiv(t, invn);
                     return (int64_t)(rlo + (t - l * nown)) + (int64_t)l * n;
                 };
-                batched_loop<8>(nown * r, [&](int t) { return ldg(pb.vx + idx(t)); }, [&](int t, double v) { stg(Udst + idx(t), v); });
+                batched_loop<4>(nown * r, [&](int t) { return ldg(pb.vx + idx(t)); }, [&](int t, double v) { stg(Udst + idx(t), v); });
             }
-            __syncthreads();
-            // this workgroup's share sum(S_w o H0) of ||Delta f_q||^2 (H0 is the same for every
-            // workgroup), then the shares in a fixed order; the cluster sum's barrier also
-            // publishes U_q
-            double part = 0.0;
-#pragma unroll 4
-            for (int t = tid_here(); t < r * r; t += WG) part = fma(ldg(S + t), ldg(pb.H0 + t), part);
-            const double delta2 = ufirst(cluster_sum(wg_sum(part, s.red)));
-            dmax2 = fmax(dmax2, delta2);
+            // the workgroups' shares of ||Delta f_q||^2 are summed in a fixed order: in a Jacobi
+            // sweep here (the barrier also publishes Unew_q); in a Gauss-Seidel sweep behind the
+            // first barrier of the Gram refresh of dimension q, which reads x (published by the
+            // last barrier of the solve) instead of U_q
+            const double wpart = wg_sum(part, s.red);
             if (pb.jacobi) {
+                dmax2 = fmax(dmax2, ufirst(cluster_sum(wpart)));
                 q = q + 1;
                 op = (q < d) ? OP_UPDATE : OP_JACOBI;
             } else {
+                carry = true;
+                carry_val = wpart;
                 k = q;
                 k_end = q + 1;
                 after = (q + 1 < d) ? OP_UPDATE : OP_SWEEP;
@@ -2288,7 +2316,7 @@ __global__ void __launch_bounds__(WG) residual_kernel(const Problem* __restrict_
             s.bar_target = 0;
             s.sync_ok = 1;
             s.dcount = 0;
-            s.kc_key[0] = s.kc_key[1] = nullptr;
+            s.kc_key = nullptr;
         }
     }
     __syncthreads();

@@ -167,21 +167,44 @@ struct PanelA {
 // ---------------------------------------------------------------------------------------
 constexpr int GRAM_TPW = 9;
 
+// The matrix-core steps of one staged chunk for the first NT tile slots of a wave: all
+// operand reads of a k-step first, then NT independent steps, none of them predicated (an
+// idle slot accumulates tile (0, 0) into a tile that is never stored), so the reads are
+// not sunk into branches and overlap the steps.
+template <bool F32, int NT>
+__device__ __forceinline__ void gram_ksteps(Tile<F32> (&acc)[GRAM_TPW], const double* As, const double* Bs, int wa,
+                                            int wb, int KC, int kk, int cc, const int (&ti)[GRAM_TPW],
+                                            const int (&tj)[GRAM_TPW], const int (&which)[GRAM_TPW]) {
+    for (int k0 = 0; k0 < KC; k0 += 4) {
+        double av[NT], bv[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const bool g1 = which[t] != 2;
+            av[t] = As[(k0 + kk) * wa + ti[t] * 16 + cc];
+            bv[t] = g1 ? As[(k0 + kk) * wa + tj[t] * 16 + cc] : Bs[(k0 + kk) * wb + tj[t] * 16 + cc];
+        }
+        // operands swapped: the tile holds the transposed block, so a lane's results lie in
+        // one row-contiguous run (coalesced stores)
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[t].step(bv[t], av[t]);
+    }
+}
+
 // Stage rows i0 .. i0 + 2^lg - 1 of a panel functor into LDS (row stride ld), `total` =
-// 2^lg * (columns rounded to 16); eight elements' loads per thread are in flight together.
+// 2^lg * (columns rounded to 16); four elements' loads per thread are in flight together.
 template <class F>
 __device__ __forceinline__ void gram_stage(const F& f, int n, int i0, int ncol, int total, int lg, double* dst, int ld) {
     const int msk = (1 << lg) - 1;
-    for (int t0 = tid_here(); t0 < total; t0 += 8 * WG) {
-        typename F::raw_t v[8];
+    for (int t0 = tid_here(); t0 < total; t0 += 4 * WG) {
+        typename F::raw_t v[4];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
+        for (int u = 0; u < 4; ++u) {
             const int t = t0 + u * WG;
             const int i = i0 + (t & msk), c = t >> lg;
             v[u] = (t < total && i < n && c < ncol) ? f.raw(i, c) : F::zero();
         }
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
+        for (int u = 0; u < 4; ++u) {
             const int t = t0 + u * WG;
             if (t < total) dst[(t & msk) * ld + (t >> lg)] = f.val(v[u]);
         }
@@ -213,6 +236,9 @@ __device__ __forceinline__ void gram_lds(int i_begin, int i_end, int M1, int N2,
     const int kk = lane >> 4, cc = lane & 15;
     const int msk = KC - 1;
     for (int base = 0; base < ntiles; base += per_pass) {
+        // tile slots this pass occupies per wave (1, 2, 3, 5 or 9: one instantiation each)
+        const int need = (min(per_pass, ntiles - base) + NWAVES - 1) / NWAVES;
+        const int nslot = need <= 3 ? need : (need <= 5 ? 5 : GRAM_TPW);
         int ti[GRAM_TPW], tj[GRAM_TPW], which[GRAM_TPW];
 #pragma unroll
         for (int t = 0; t < GRAM_TPW; ++t) {
@@ -256,21 +282,12 @@ __device__ __forceinline__ void gram_lds(int i_begin, int i_end, int M1, int N2,
                     rb[u] = (t < nb && i < n && col < N2) ? fb.raw(i, col) : FB::zero();
                 }
             }
-            // per k-step: the operands of all of the wave's tiles are read first (branch-free;
-            // an idle tile reads tile (0, 0)), then the independent matrix-core steps
-            for (int k0 = 0; k0 < KC; k0 += 4) {
-                double av[GRAM_TPW], bv[GRAM_TPW];
-#pragma unroll
-                for (int t = 0; t < GRAM_TPW; ++t) {
-                    const bool g1 = which[t] != 2;
-                    av[t] = As[(k0 + kk) * wa + ti[t] * 16 + cc];
-                    bv[t] = g1 ? As[(k0 + kk) * wa + tj[t] * 16 + cc] : Bs[(k0 + kk) * wb + tj[t] * 16 + cc];
-                }
-                // operands swapped: the tile holds the transposed block, so a lane's results
-                // lie in one row-contiguous run (coalesced stores)
-#pragma unroll
-                for (int t = 0; t < GRAM_TPW; ++t)
-                    if (which[t] > 0) acc[t].step(bv[t], av[t]);
+            switch (nslot) {
+                case 1: gram_ksteps<F32, 1>(acc, As, Bs, wa, wb, KC, kk, cc, ti, tj, which); break;
+                case 2: gram_ksteps<F32, 2>(acc, As, Bs, wa, wb, KC, kk, cc, ti, tj, which); break;
+                case 3: gram_ksteps<F32, 3>(acc, As, Bs, wa, wb, KC, kk, cc, ti, tj, which); break;
+                case 5: gram_ksteps<F32, 5>(acc, As, Bs, wa, wb, KC, kk, cc, ti, tj, which); break;
+                default: gram_ksteps<F32, GRAM_TPW>(acc, As, Bs, wa, wb, KC, kk, cc, ti, tj, which); break;
             }
             if (!more) break;
             if (pre) {
