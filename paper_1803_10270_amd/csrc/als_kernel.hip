@@ -703,15 +703,22 @@ __device__ __forceinline__ uint32_t factor_precond_wave(double lam) {
             for (int b = 0; b < 4; ++b) rv[b] = __shfl(M[pa][b], 8 * bp + bj, 64);   // A[p][4 bj + b]
 #pragma unroll
             for (int a = 0; a < 4; ++a) cv[a] = __shfl(M[a][pa], 8 * bi + bp, 64);   // A[4 bi + a][p]
+            // entry (i, j) = (4 bi + a, 4 bj + b) lies in the pivot row only if a == pa and
+            // bi == bp, in the pivot column only if b == pa and bj == bp: the register index
+            // settles the first half of each test at compile time
+            const bool prow = bi == bp, pcol = bj == bp;
 #pragma unroll
-            for (int a = 0; a < 4; ++a)
+            for (int a = 0; a < 4; ++a) {
+                const double mc = -cv[a] * ip;
 #pragma unroll
                 for (int b = 0; b < 4; ++b) {
-                    const int i = 4 * bi + a, j = 4 * bj + b;
-                    const double e = (j == p) ? 1.0 : rv[b];
-                    const double base = (j == p) ? 0.0 : M[a][b];
-                    M[a][b] = (i == p) ? e * ip : fma(-cv[a] * ip, e, base);
+                    const bool jp = (b == pa) && pcol;
+                    const double e = jp ? 1.0 : rv[b];
+                    const double base = jp ? 0.0 : M[a][b];
+                    const double upd = fma(mc, e, base);
+                    M[a][b] = ((a == pa) && prow) ? e * ip : upd;
                 }
+            }
         }
         // symmetrised (the preconditioner of CG must be symmetric) through a copy in LDS
         double* T = s.scratch;
