@@ -60,7 +60,8 @@ typedef enum {
 /* report.flags bits */
 #define CP_FLAG_NOT_CONVERGED 1u  /* max_sweeps reached with eps_conv > tol            */
 #define CP_FLAG_PCG_MAXITER 2u    /* a per-dimension solve hit pcg_max_iter            */
-#define CP_FLAG_REGULARIZED 4u    /* a Cholesky pivot of H_q fell below 1e-12 max diag */
+#define CP_FLAG_REGULARIZED 4u    /* a Gauss-Jordan pivot of H_q + lambda_q I fell     */
+                                  /* below 1e-12 of its largest diagonal entry         */
 #define CP_FLAG_NONFINITE 8u      /* a NaN/Inf was produced                            */
 #define CP_FLAG_SYNC_TIMEOUT 16u  /* a workgroup of a cluster waited too long for the    */
                                   /* others at a barrier; the result is not valid       */
