@@ -649,6 +649,13 @@ __device__ __forceinline__ uint32_t factor_precond_t(double lam) {
     return fl;
 }
 
+// The value of lane `src` (a compile-time constant after unrolling) in every lane.
+__device__ __forceinline__ double readlane_f64(double v, int src) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
+    return __hiloint2double(hi, lo);
+}
+
 // r <= 32: wave 0 alone inverts the 32 x 32 matrix [H0 + lam I, 0; 0, I] by Gauss-Jordan in
 // registers.  The matrix is an 8 x 8 grid of 4 x 4 blocks, lane l holding block
 // (l >> 3, l & 7); for pivot p the pivot, the four pivot-row entries of the lane's columns
@@ -692,7 +699,8 @@ __device__ __forceinline__ uint32_t factor_precond_wave(double lam) {
 #pragma unroll
         for (int p = 0; p < 32; ++p) {
             const int bp = p >> 2, pa = p & 3;
-            double piv = __shfl(M[pa][pa], 9 * bp, 64);
+            // the pivot from its fixed lane by scalar reads (no LDS round trip on the chain)
+            double piv = readlane_f64(M[pa][pa], 9 * bp);
             if (p < r) {
                 if (!(piv > 1e-12 * dmax)) fl |= CP_FLAG_REGULARIZED;
                 if (!(piv > 0.0)) piv = (lam > 0.0) ? lam : 1e-300;
