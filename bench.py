@@ -214,11 +214,12 @@ def summarize_rho(rhos):
 
 
 def bench_learned(args, log):
-    """Config 5: training data are solver trajectories of new seeds, generated in one batched
-    launch (every step converged); the network is trained on them; held-out instances are
-    stepped K times from the same two levels three ways: plain (f_n), the trained network's
-    prediction, and the untrained network's (the linear extrapolation alone).  Every step of
-    every leg stops at eps_conv <= 1e-8; rho of every step is reported."""
+    """Learned warm start on the d = 6, n = 256, rank-32 workload: training data are solver
+    trajectories of new seeds, generated in one batched launch (every step converged); the
+    network is trained on them; held-out instances are stepped K times from the same two
+    levels three ways: plain (f_n), the trained network's prediction, and the untrained
+    network's (the linear extrapolation alone).  Every step of every leg stops at
+    eps_conv <= 1e-8; rho of every step is reported."""
     import torch
     from paper_1803_10270_amd import binding as B
     from paper_1803_10270_amd import warmstart as WS
@@ -317,7 +318,7 @@ def bench_learned(args, log):
 
 
 def bench_batched(args, log):
-    """Config 4: 256 uneven advection instances, n_steps each, adaptive rank up to each
+    """Batched form: 256 uneven advection instances, n_steps each, adaptive rank up to each
     instance's cap (tau_rank TAU_BATCHED), tol 1e-8, in one persistent launch; a seeded
     sample advanced one launch at a time with the same options (their results equal the
     batched ones bit for bit: both run one workgroup per instance), scaled to all instances
@@ -380,7 +381,7 @@ def bench_batched(args, log):
 
 
 def bench_mixed(args, log):
-    """Config 3: the kinetic Crank-Nicolson workload (d = 6, n = 128, rank 64, 5 Kronecker
+    """Mixed precision on the kinetic Crank-Nicolson workload (d = 6, n = 128, rank 64, 5 Kronecker
     terms), K steps in FP64 and in mixed precision (FP32 matrix-core sweeps, then FP64 sweeps
     to the tolerance) from the same state: rates, FP32/FP64 sweeps, converged steps, rho of
     sampled steps, and the double-double distance of the two final states."""

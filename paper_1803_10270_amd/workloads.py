@@ -420,16 +420,5 @@ def spiral_exact(C: np.ndarray, z: np.ndarray, t: float) -> float:
     return float(np.exp(-y @ y))
 
 
-def config(i: int, seed: int = 0) -> Problem:
-    """The five configurations (1-based), full size."""
-    if i == 1:
-        return advection_cn_constant(seed)
-    if i == 2:
-        return advection_ie_variable(seed)
-    if i == 3:
-        return kinetic_cn(seed)
-    raise ValueError("config %d has no single-problem form" % i)
-
-
 def random_factors(rng: np.random.Generator, dims: List[int], r: int) -> List[np.ndarray]:
     return [rng.standard_normal((n, r)) for n in dims]

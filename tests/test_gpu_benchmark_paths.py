@@ -67,7 +67,7 @@ def test_full_size_converged_steps_match_oracle(handle):
 BATCH_SEL = [32, 43, 73, 182, 17]   # d = 6/4/6/4/6, n = 512 (four) and 256, rank caps 34/39/40/45/45
 
 
-def test_batched_config4_instances_match_oracle(handle):
+def test_batched_uneven_instances_match_oracle(handle):
     """Five of the 256 uneven advection instances in one batched launch, in the form the
     benchmark runs them: adaptive rank from the initial condition's own rank up to the
     instance's cap (tau 1e-5), three sweeps per solve.  Each instance against the oracle's
