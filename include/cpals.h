@@ -143,11 +143,7 @@ typedef enum { CP_SWEEP_GAUSS_SEIDEL = 0, CP_SWEEP_JACOBI = 1 } cp_sweep_mode;
  *                 FP64 and FP64 sweeps until eps_conv <= tol
  *  eps_reg      : every per-dimension system is shifted by
  *                 lambda_q = eps_reg * trace(M_q) / (n_q r)  (regularisation, Section 2.1)
- *  pcg_tol      : relative residual target (preconditioned norm) of the per-dimension PCG
- *                 solve; in a run with tol > 0 the target after a step's first sweep is
- *                 max(pcg_tol, min(1e-6, 1e-4 * eps_conv of the previous sweep, 1e-2 * tol)),
- *                 so the solve error stays well below the sweep's own increment and below
- *                 the stopping threshold (with tol = 0 every solve goes to pcg_tol)
+ *  pcg_tol      : relative residual target of the per-dimension PCG solve
  *  pcg_max_iter : PCG iteration cap per dimension update
  *  rank_mode    : CP_RANK_FIXED: the rank of the guess is kept.  CP_RANK_ADAPTIVE: the
  *                 separation rank is chosen per step (Section 4.1: adaptive rank up to a

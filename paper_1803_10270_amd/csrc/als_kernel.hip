@@ -2085,12 +2085,7 @@ __global__ void __launch_bounds__(WG) als_persistent(const Problem* __restrict__
                     // FP32 contractions cannot resolve the system below ~1e-7; the FP64
                     // sweeps finish it.
                     rz = val;
-                    double ptol = lowp ? fmax(pb.pcg_tol, 1e-6) : pb.pcg_tol;
-                    // In a run that converges to a tolerance, an update after the first sweep
-                    // is solved to 1e-4 of the previous sweep's increment and to 1e-2 of the
-                    // tolerance (at most 1e-6): the solve error stays far below what the sweep
-                    // itself changes and below the stopping threshold.
-                    if (pb.tol > 0.0 && eps > 0.0) ptol = fmax(ptol, fmin(fmin(1e-6, 1e-4 * eps), 1e-2 * pb.tol));
+                    const double ptol = lowp ? fmax(pb.pcg_tol, 1e-6) : pb.pcg_tol;
                     stop = ptol * ptol * bz;
                     it = 0;
                     if (rz <= stop) finish = true;
