@@ -1927,6 +1927,7 @@ __global__ void __launch_bounds__(WG) als_persistent(const Problem* __restrict__
     bool lowp = false;
     double lam = 0.0, bz = 0.0, stop = 0.0, rz = 0.0, pw = 0.0, alpha = 0.0, beta = 0.0;
     double dmax2 = 0.0, eps = 0.0, fnorm = 0.0;
+    bool inc_bad = false;         // a non-finite increment this sweep (fmax would drop it)
     double eps_low_min = 1e300;   // smallest increment of the FP32 sweeps of this step
     int low_stall = 0;            // FP32 sweeps since that minimum last improved
     int psel = 0;   // which of the two search-direction buffers holds p
@@ -1990,6 +1991,7 @@ __global__ void __launch_bounds__(WG) als_persistent(const Problem* __restrict__
             rho = -1.0;
             flags = CP_FLAG_NOT_CONVERGED;
             eps = fnorm = dmax2 = 0.0;
+            inc_bad = false;
             sw = 1;
             q = 0;
             k = 0;
@@ -1999,7 +2001,9 @@ __global__ void __launch_bounds__(WG) als_persistent(const Problem* __restrict__
         } else if (op == OP_REFRESH) {
             if (carry) {
                 // dimension k was just solved: its Grams from x, with the sum of ||Delta f_k||^2
-                dmax2 = fmax(dmax2, ufirst(refresh_dim(k, r0, lowp, pb.vx, true, carry_val)));
+                const double d2 = ufirst(refresh_dim(k, r0, lowp, pb.vx, true, carry_val));
+                inc_bad = inc_bad || !isfinite(d2);
+                dmax2 = fmax(dmax2, d2);
                 carry = false;
             } else {
                 refresh_dim(k, r0, lowp);
@@ -2148,7 +2152,9 @@ __global__ void __launch_bounds__(WG) als_persistent(const Problem* __restrict__
             // last barrier of the solve) instead of U_q
             const double wpart = wg_sum(part, s.red);
             if (pb.jacobi) {
-                dmax2 = fmax(dmax2, ufirst(cluster_sum(wpart)));
+                const double d2 = ufirst(cluster_sum(wpart));
+                inc_bad = inc_bad || !isfinite(d2);
+                dmax2 = fmax(dmax2, d2);
                 q = q + 1;
                 op = (q < d) ? OP_UPDATE : OP_JACOBI;
             } else {
@@ -2213,7 +2219,7 @@ __global__ void __launch_bounds__(WG) als_persistent(const Problem* __restrict__
             if (was_low) ++low_sweeps;
             bool refresh_all = false;
             bool done = false;
-            if (!isfinite(eps)) {
+            if (inc_bad || !isfinite(f2) || !isfinite(eps)) {
                 flags |= CP_FLAG_NONFINITE;
                 done = true;
             } else if (was_low) {
@@ -2240,6 +2246,7 @@ __global__ void __launch_bounds__(WG) als_persistent(const Problem* __restrict__
                 ++sw;
                 q = 0;
                 dmax2 = 0.0;
+                inc_bad = false;
                 if (refresh_all) {
                     k = 0;
                     k_end = d;
@@ -2268,6 +2275,7 @@ __global__ void __launch_bounds__(WG) als_persistent(const Problem* __restrict__
                 low_stall = 0;
                 flags = CP_FLAG_NOT_CONVERGED;
                 eps = fnorm = dmax2 = 0.0;
+                inc_bad = false;
                 sw = 1;
                 q = 0;
                 k = 0;

@@ -108,3 +108,16 @@ def test_refused_shapes_launch_nothing(handle):
     Gd = dev(p.guess)
     rep = B.cp_als_step(handle, p.A, p.B, Vd, Gd, B.default_opts(tol=0.0, max_sweeps=1))
     assert rep["sweeps"] == 1
+
+
+def test_nonfinite_guess_is_flagged(handle):
+    """A NaN in the guess reaches the increments and the norm: the step ends flagged
+    NONFINITE and not converged (a non-finite increment must not read as a zero one)."""
+    log("nonfinite guess")
+    p = W.advection_ie_constant(seed=19, d=3, n=16, cap=2, ic_rank=2, dt=1e-2)
+    guess = [np.array(g) for g in p.guess]
+    guess[1][3, 0] = np.nan
+    rep = B.cp_als_step(handle, p.A, p.B, dev(p.f0), dev(guess), B.default_opts(tol=1e-8, max_sweeps=20))
+    log("  flags", rep["flags"], "sweeps", rep["sweeps"], "eps", rep["eps_conv"])
+    assert rep["flags"] & B.FLAG_NONFINITE
+    assert rep["flags"] & B.FLAG_NOT_CONVERGED
