@@ -760,9 +760,9 @@ __device__ __forceinline__ uint32_t factor_precond(double lam) {
 // Composite product on the matrix cores:
 //   out[i, j] = sum_blk sum_{l < rc} (comp_blk X)[i, l] Kt[j + (blk rc + l) r]   (i < n, j < r)
 // then, with `shift`, out += lam X and, with `dot`, the return value sum_ij X[i, j] out[i, j]
-// (per thread; both need rc == r).  Used for the right-hand side (comp = (O_A^a)^T O_B^b, Kt = D blocks),
-// the matvec (M_q + lam I) p (comp = (O^a)^T O^b, Kt = C blocks) and the preconditioner
-// r Hinv (comp = I, Kt = Hinv).
+// (per thread; both need rc == r).  Used for the right-hand side (comp = (O_A^a)^T O_B^b, Kt = D blocks)
+// and the matvec (M_q + lam I) p (comp = (O^a)^T O^b, Kt = C blocks); the preconditioner has a
+// row-local routine of its own (precond_apply).
 //
 // X is staged in LDS pass by pass (up to 16 SPW NWAVES rows plus a halo of the widest
 // stencil); each lane forms the A fragment it feeds to the matrix core directly from the

@@ -361,8 +361,8 @@ cp_status compose_t(cp_handle h, const cp_op1d& a, const cp_op1d& b, CompOp& out
 
 // Byte layout of one problem's device region.
 struct Layout {
-    size_t problem, opdata, pairsC, pairsD, U, Unew, V, Q, G, X, P, Z, Cm, Dm, H0, Hinv, S, vec, reports, bar, gpart, spart,
-        dpart, termA, termB, Rdd, tv, cv, total;
+    size_t problem, opdata, pairsC, pairsD, U, Unew, V, Q, G, X, P, Z, Cm, Dm, H0, Hinv, vec, reports, bar, gpart, dpart,
+        termA, termB, Rdd, tv, cv, total;
     size_t n_opdata, n_pairsC, n_pairsD;
     int64_t offU[CP_MAX_DIMS], offV[CP_MAX_DIMS], offQ[CP_MAX_DIMS], offG[CP_MAX_DIMS], offX[CP_MAX_DIMS];
     int64_t offR[CP_MAX_DIMS], offT[CP_MAX_DIMS], offCv[CP_MAX_DIMS];
@@ -539,7 +539,6 @@ cp_status pack_problem(cp_handle h, const HostOp& A, const HostOp& B, const cp_t
     L.Dm = take((size_t)(L.mAmax * rc) * (L.mBmax * L.r0max) * 8);
     L.H0 = take((size_t)rc * rc * 8);
     L.Hinv = take((size_t)W * rc * rc * 8);
-    L.S = take((size_t)rc * rc * 8);
     L.vec = take((size_t)7 * align_up((size_t)L.nmax * rc * 8));
     L.reports = take((size_t)n_steps * sizeof(cp_als_report));
     size_t psz = 0;
@@ -549,7 +548,6 @@ cp_status pack_problem(cp_handle h, const HostOp& A, const HostOp& B, const cp_t
     pb.psz = (int32_t)psz;
     L.bar = take(256);
     L.gpart = take(W > 1 ? (size_t)W * psz * 8 : 8);
-    L.spart = take(W > 1 ? (size_t)W * rc * rc * 8 : 8);
     L.dpart = take((size_t)2 * W * 8 * 8);
     // terms of A and B (coefficient, op index per dimension)
     pk.termA.assign(A.T, PairRec{});
@@ -662,7 +660,6 @@ void rebase(Packed& pk, char* base, double* traj) {
     pb.Dm = reinterpret_cast<double*>(base + L.Dm);
     pb.H0 = reinterpret_cast<double*>(base + L.H0);
     pb.Hinv = reinterpret_cast<double*>(base + L.Hinv);
-    pb.S = reinterpret_cast<double*>(base + L.S);
     const size_t vstride = align_up((size_t)L.nmax * L.rc * 8);
     char* vb = base + L.vec;
     pb.vb = reinterpret_cast<double*>(vb + 0 * vstride);
@@ -675,7 +672,6 @@ void rebase(Packed& pk, char* base, double* traj) {
     pb.reports = reinterpret_cast<cp_als_report*>(base + L.reports);
     pb.bar = reinterpret_cast<uint32_t*>(base + L.bar);
     pb.gpart = reinterpret_cast<double*>(base + L.gpart);
-    pb.spart = reinterpret_cast<double*>(base + L.spart);
     pb.dpart = reinterpret_cast<double*>(base + L.dpart);
     pb.traj = traj;
 }

@@ -64,7 +64,6 @@ struct Problem {
     double* Dm;    // r x (mA mB r0): Dm[l + (blk r0 + l0) r] = D^{blk}[l, l0]
     double* H0;    // r x r
     double* Hinv;  // r x r
-    double* S;     // r x r
     double* vb; double* vx; double* vr; double* vz; double* vp; double* vw;  // n_max x r
     // options
     double tol, eps_reg, pcg_tol;
@@ -97,7 +96,6 @@ struct Problem {
     int32_t W, psz;           // cluster size; doubles per workgroup in the Gram partial area
     uint32_t* bar;            // arrival counter of the cluster barrier (zero at launch)
     double* gpart;            // [W][psz] Gram / cross-Gram partials
-    double* spart;            // [W][r r] increment-Gram partials
     double* dpart;            // [2][W][8] scalar partials (dot products, trace), alternating
     double* vp2;              // second search-direction buffer (p is double-buffered)
 };
