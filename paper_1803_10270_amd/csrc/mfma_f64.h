@@ -162,7 +162,8 @@ struct PanelA {
 // so that a batch of loads is issued before any value is formed.
 // Only the upper-triangular tiles of G1 are computed; both halves are written.  Tiles are
 // dealt round-robin to the waves, up to GRAM_TPW per wave per pass over the rows.  Chunks
-// of 32 rows (16 when LDS is short) are staged; `lds` holds `cap` doubles, at least
+// of 32 rows (16 when LDS is short or there are at most 16 rows) are staged; `lds` holds
+// `cap` doubles, at least
 // 16 * ((TM1*16 + 1) + (TN2*16 + 1)).  Starts and ends with a barrier.
 // ---------------------------------------------------------------------------------------
 constexpr int GRAM_TPW = 9;
@@ -222,10 +223,11 @@ __device__ __forceinline__ void gram_lds(int i_begin, int i_end, int M1, int N2,
     const int wa = TM * 16 + 1, wb = TN * 16 + 1;   // LDS row strides (odd: bank spread)
     // chunk rows: 32 (or 16), double-buffered when the LDS area allows it; with double
     // buffering the next chunk's loads are in flight during this chunk's matrix-core work
-    int lgKC = 5;
+    // (16 when there are at most 16 rows: no matrix-core steps over zero padding)
+    int lgKC = (n - i_begin <= 16) ? 4 : 5;
     while (lgKC > 4 && 2 * (1 << lgKC) * (wa + wb) > cap) --lgKC;
     const bool dbl = 2 * (1 << lgKC) * (wa + wb) <= cap;
-    if (!dbl) lgKC = (32 * (wa + wb) <= cap) ? 5 : 4;
+    if (!dbl && n - i_begin > 16) lgKC = (32 * (wa + wb) <= cap) ? 5 : 4;
     const int KC = 1 << lgKC;
     const int na = KC * TM * 16, nb = KC * TN * 16;
     const bool pre = dbl && na <= PFN * WG && nb <= PFN * WG;
