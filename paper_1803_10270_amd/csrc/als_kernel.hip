@@ -141,6 +141,27 @@ __device__ __forceinline__ double sum_partials(const double* base, int64_t strid
     return acc;
 }
 
+// E sums of that kind (base pointers b[e], nullptr for none) with all their loads in flight
+// together, each in the order of sum_partials.
+template <int E>
+__device__ __forceinline__ void sum_partials_n(const double* const (&b)[E], int64_t stride, int W, double (&out)[E]) {
+    constexpr int B = 16;
+#pragma unroll
+    for (int e = 0; e < E; ++e) out[e] = 0.0;
+    for (int w0 = 0; w0 < W; w0 += B) {
+        double v[E][B];
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+#pragma unroll
+            for (int u = 0; u < B; ++u) v[e][u] = (w0 + u < W && b[e]) ? ldg(b[e] + (int64_t)(w0 + u) * stride) : 0.0;
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+#pragma unroll
+            for (int u = 0; u < B; ++u)
+                if (w0 + u < W) out[e] += v[e][u];
+    }
+}
+
 // Sum over the cluster of one workgroup-uniform value, in a fixed order (partials in
 // device memory, two alternating buffers so that a fast workgroup never overwrites a
 // partial that a slow one has not read).
@@ -318,13 +339,16 @@ __device__ __forceinline__ double refresh_dim(int k, int r0, bool lowp, const do
             if (e < M1 * M1) stg(Gk + e, v);
             else stg(Xk + (e - M1 * M1), v);
         };
-        // two entries per thread and pass, all their loads before the stores
-        for (int e = e0 + tid_here(); e < e1; e += 2 * WG) {
-            const bool two = e + WG < e1;
-            const double a0 = sum_partials(pb.gpart + e, pb.psz, W);
-            const double a1 = two ? sum_partials(pb.gpart + e + WG, pb.psz, W) : 0.0;
-            put(e, a0);
-            if (two) put(e + WG, a1);
+        // three entries per thread and pass, all their partials' loads in flight together
+        for (int e = e0 + tid_here(); e < e1; e += 3 * WG) {
+            const double* b[3];
+#pragma unroll
+            for (int u = 0; u < 3; ++u) b[u] = e + u * WG < e1 ? pb.gpart + e + u * WG : nullptr;
+            double a[3];
+            sum_partials_n<3>(b, pb.psz, W, a);
+#pragma unroll
+            for (int u = 0; u < 3; ++u)
+                if (b[u]) put(e + u * WG, a[u]);
         }
         cluster_sync();
     }
