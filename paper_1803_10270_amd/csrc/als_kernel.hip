@@ -28,6 +28,8 @@
 
 namespace cpals {
 
+constexpr int XCDS = 8;          // XCDs of the device (MI355X), each with its own L2
+constexpr int XCD_CUS = 32;      // compute units of one XCD
 constexpr int SCRATCH = 16384;   // doubles of LDS shared by the phases of one dimension update
 constexpr int LDS_PAIRS = 384;   // pair records of one dimension kept in LDS during assembly
 constexpr int CG_TAPS = 5;       // stencils up to half bandwidth 2 keep their coefficients in registers
@@ -56,6 +58,7 @@ struct Smem {
     int32_t part, W;             // this workgroup's index in the problem's cluster, cluster size
     uint32_t bar_target;         // arrivals the next cluster barrier waits for (thread 0)
     uint32_t sync_ok;            // 0 once a cluster barrier timed out
+    uint32_t xlocal;             // 1: every workgroup of the cluster runs on this one XCD
     uint32_t dcount;             // calls of cluster_sum (selects the partial buffer)
     // operator blocks and coefficients of the matvec kept in LDS across the products of one
     // solve (key: the Kt array; cleared per solve)
@@ -97,19 +100,28 @@ __device__ __forceinline__ void own_rows(int n, int& rlo, int& rhi) {
     rhi = rlo + per;
 }
 
-// Barrier of the cluster's workgroups with device-scope release/acquire (so that every
-// write before it is visible to every workgroup after it).  The arrival counter only
-// grows; a workgroup waits for W arrivals per barrier.  A wait is bounded: past the bound
-// the barrier returns and sync_ok is cleared (the caller ends the problem).
+// Barrier of the cluster's workgroups (so that every write before it is visible to every
+// workgroup after it).  The arrival counter only grows; a workgroup waits for W arrivals per
+// barrier.  A wait is bounded: past the bound the barrier returns and sync_ok is cleared
+// (the caller ends the problem).
+// The wait ends with a device-scope acquire.  The arrival has two forms:
+// - cluster spread over several XCDs: a device-scope release, which writes the dirty lines
+//   of the XCD's L2 back to memory, since every XCD has an L2 of its own;
+// - cluster on one XCD (xlocal): all members share one L2, which the vector L1s write
+//   through, so it suffices that every wave's stores (and loads) have completed before the
+//   arrival; the members' writes are not written back to memory at every barrier.
 __device__ __forceinline__ void cluster_sync() {
     Smem& s = SMEM;
+    const bool xl = ufirst((int)s.xlocal) != 0;
+    if (xl) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     __syncthreads();
     if (ufirst(s.W) == 1) return;
     if (tid_here() == 0) {
         const uint32_t tgt = s.bar_target + (uint32_t)s.W;
         s.bar_target = tgt;
         uint32_t* ctr = s.pb.bar;
-        __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        if (xl) __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        else __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         long spins = 0;
         // spin on relaxed loads; one acquire fence once the count is reached (an acquire load
         // per spin would invalidate the L2 of the workgroup's XCD on every poll)
@@ -121,6 +133,26 @@ __device__ __forceinline__ void cluster_sync() {
             }
         }
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    __syncthreads();
+}
+
+// XCD of the executing wave (hardware register XCC_ID, bits 3:0).
+__device__ __forceinline__ uint32_t xcd_id() { return __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & 15u; }
+
+// Whether the whole cluster runs on one XCD: every member sets its XCD's bit in a word of
+// the barrier area (zeroed before the launch), a device-scope barrier publishes the bits,
+// and every member reads the same mask.  Until then, and whenever the members are spread,
+// the barriers keep the device-scope form.
+__device__ __forceinline__ void detect_xcd_local() {
+    Smem& s = SMEM;
+    if (ufirst(s.W) == 1) return;
+    uint32_t* mask = s.pb.bar + 16;
+    if (tid_here() == 0) __hip_atomic_fetch_or(mask, 1u << xcd_id(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    cluster_sync();
+    if (tid_here() == 0) {
+        const uint32_t m = __hip_atomic_load(mask, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s.xlocal = (m != 0u && (m & (m - 1u)) == 0u) ? 1u : 0u;
     }
     __syncthreads();
 }
@@ -806,12 +838,13 @@ struct Xform {
     double* x2;          // optional: x2 += alpha2 * p2
     const double* p2;
     double alpha2;
+    double* acopy;       // optional (modes 2 and 3): a itself is written here
 };
 
 // Transform of the rows [rlo, rlo + nown) of an n-row panel of rc columns (ld n): all loads
 // of a batch are issued before any store.  MODE 0: v = a; 1: v = a, wv = v; 2: v = a + beta b,
-// wv = v; 3: as 2 and x2 += alpha2 p2.  With `lds`, v goes to Xs[l ldx + H + (i - rlo)] and,
-// given Xa, the untransformed a to the same place of Xa.
+// wv = v (and acopy = a when given); 3: as 2 and x2 += alpha2 p2.  With `lds`, v goes to
+// Xs[l ldx + H + (i - rlo)] and, given Xa, the untransformed a to the same place of Xa.
 template <int MODE>
 __device__ __forceinline__ void xform_rows(const Xform& xf, int n, int rlo, int nown, int rc, bool lds, double* Xs,
                                            int ldx, int H, double* Xa) {
@@ -838,6 +871,7 @@ __device__ __forceinline__ void xform_rows(const Xform& xf, int n, int rlo, int 
             if (t < total) {
                 const double v = (MODE >= 2) ? fma(xf.beta, vb[u], va[u]) : va[u];
                 if (MODE >= 1) stg(xf.wv + idx[u], v);
+                if (MODE >= 2 && xf.acopy) stg(xf.acopy + idx[u], va[u]);
                 if (MODE == 3) stg(xf.x2 + idx[u], fma(xf.alpha2, vp[u], vx[u]));
                 if (lds) {
                     const int l = fdiv(t, invn);
@@ -1892,10 +1926,13 @@ enum : int { OP_STEP, OP_REFRESH, OP_UPDATE, OP_CG, OP_DELTA, OP_JACOBI, OP_SWEE
 enum : int { PH_RHS, PH_MV_X, PH_PRE_R0, PH_MV_P0, PH_PRE_R, PH_MV_P };
 
 __global__ void __launch_bounds__(WG) als_persistent(const Problem* __restrict__ problems, int count, int W,
-                                                      const int32_t* __restrict__ wg_first) {
+                                                      const int32_t* __restrict__ wg_first, int nx) {
     Smem& s = SMEM;
     // problem pid is advanced by its workgroups wg_first[pid] .. wg_first[pid + 1] - 1 (a
-    // table of count + 1 offsets) or, without the table, by workgroups pid W .. pid W + W - 1
+    // table of count + 1 offsets) or, without the table, by the workgroups of slots
+    // pid W .. pid W + W - 1.  With nx > 1 the slots are striped over nx XCDs: the dispatcher
+    // deals workgroup b to XCD b mod nx, so slot (b mod nx) (grid / nx) + b / nx puts each
+    // cluster on one XCD (whether it really is there is checked at run time).
     int pid, cpart, Wp;
     if (wg_first) {
         const int b = blockIdx.x;
@@ -1909,8 +1946,10 @@ __global__ void __launch_bounds__(WG) als_persistent(const Problem* __restrict__
         cpart = b - wg_first[lo];
         Wp = wg_first[lo + 1] - wg_first[lo];
     } else {
-        pid = blockIdx.x / W;
-        cpart = blockIdx.x - pid * W;
+        int b = blockIdx.x;
+        if (nx > 1) b = (b % nx) * (int)(gridDim.x / nx) + b / nx;
+        pid = b / W;
+        cpart = b - pid * W;
         Wp = W;
     }
     if (pid >= count) return;
@@ -1933,6 +1972,7 @@ __global__ void __launch_bounds__(WG) als_persistent(const Problem* __restrict__
         }
     }
     __syncthreads();
+    detect_xcd_local();
     const Problem& pb = s.pb;
     const int d = ufirst(pb.d);
     int r = ufirst(pb.r);   // the current rank (changes only in adaptive mode)
@@ -2054,7 +2094,7 @@ __global__ void __launch_bounds__(WG) als_persistent(const Problem* __restrict__
             double* pnxt = psel ? pb.vp : pb.vp2;
             int rlo, rhi;
             own_rows(n, rlo, rhi);
-            Xform xf{nullptr, nullptr, 0.0, nullptr, nullptr, nullptr, 0.0};
+            Xform xf{nullptr, nullptr, 0.0, nullptr, nullptr, nullptr, 0.0, nullptr};
             switch (ph) {
                 case PH_RHS: xf.a = pb.V + pb.offV[q]; break;
                 case PH_MV_X: xf.a = pb.U + oq; xf.wv = pb.vx; break;                 // x <- U_q
@@ -2158,18 +2198,10 @@ __global__ void __launch_bounds__(WG) als_persistent(const Problem* __restrict__
             own_rows(n, rlo, rhi);
             // the own rows' share of sum_i dU_i H0 dU_i^T (dU = x - U_q, written to the free
             // panel vw; H0 symmetric): the quadratic form of the preconditioner apply
-            Xform dxf{pb.vx, Uq, -1.0, pb.vw, nullptr, nullptr, 0.0};
+            // the staging of the apply also writes x to Udst (own rows): U_q <- x, or Unew_q
+            Xform dxf{pb.vx, Uq, -1.0, pb.vw, nullptr, nullptr, 0.0, Udst};
             double unused;
             const double part = precond_apply(dxf, n, r, pb.H0, pb.vz, rlo, rhi, false, unused);
-            {
-                const int nown = rhi - rlo;
-                const float invn = __frcp_rn((float)nown);
-                auto idx = [&](int t) {
-                    const int l = fdiv(t, invn);
-                    return (int64_t)(rlo + (t - l * nown)) + (int64_t)l * n;
-                };
-                batched_loop<4>(nown * r, [&](int t) { return ldg(pb.vx + idx(t)); }, [&](int t, double v) { stg(Udst + idx(t), v); });
-            }
             // the workgroups' shares of ||Delta f_q||^2 are summed in a fixed order: in a Jacobi
             // sweep here (the barrier also publishes Unew_q); in a Gauss-Seidel sweep behind the
             // first barrier of the Gram refresh of dimension q, which reads x (published by the
@@ -2401,12 +2433,18 @@ hipError_t prepare_als() {
 }
 
 // The kernel's LDS size must have been allowed by prepare_als (launch_als does both).
-// Uniform clusters of W workgroups (wg_first null, grid count W), or per-problem clusters
-// given by the device table wg_first (count + 1 offsets, grid = total workgroups).
+// Uniform clusters of W workgroups (wg_first null), or per-problem clusters given by the
+// device table wg_first (count + 1 offsets, grid = total workgroups).  Uniform clusters of
+// 2 .. XCD_CUS workgroups are striped so that each lies on one XCD: the grid is XCDS
+// columns of ceil(count / XCDS) clusters (the slots past count exit at once).  A row of
+// XCDS clusters is at most XCDS XCD_CUS workgroups, which the device holds at once, so a
+// cluster whose members are dispatched late waits only for clusters that can finish.
 hipError_t launch_als_prepared(const Problem* d_problems, int count, int W, const int32_t* wg_first, int total_wg,
                                hipStream_t stream) {
-    const int grid = wg_first ? total_wg : count * W;
-    hipLaunchKernelGGL(als_persistent, dim3(grid), dim3(WG), sizeof(Smem), stream, d_problems, count, W, wg_first);
+    const bool stripe = !wg_first && W > 1 && W <= XCD_CUS;
+    const int grid = wg_first ? total_wg : stripe ? XCDS * ((count + XCDS - 1) / XCDS) * W : count * W;
+    hipLaunchKernelGGL(als_persistent, dim3(grid), dim3(WG), sizeof(Smem), stream, d_problems, count, W, wg_first,
+                       stripe ? XCDS : 1);
     return hipGetLastError();
 }
 
