@@ -354,33 +354,61 @@ __device__ __forceinline__ double refresh_dim(int k, int r0, bool lowp, const do
         G1 = pb.gpart + (int64_t)ufirst(s.part) * pb.psz;
         G2 = G1 + M1 * M1;
     }
-    if (lowp) gram_lds<true>(rlo, rhi, M1, N2, fa, fb, G1, M1, G2, M1, s.scratch, SCRATCH);
-    else gram_lds<false>(rlo, rhi, M1, N2, fa, fb, G1, M1, G2, M1, s.scratch, SCRATCH);
+    // a cluster's partials hold the tiles of G1 on and above the diagonal only; the
+    // reduction below mirrors them
+    if (lowp) gram_lds<true>(rlo, rhi, M1, N2, fa, fb, G1, M1, G2, M1, s.scratch, SCRATCH, W == 1);
+    else gram_lds<false>(rlo, rhi, M1, N2, fa, fb, G1, M1, G2, M1, s.scratch, SCRATCH, W == 1);
     double csum = cval;
     if (W > 1) {
         // every workgroup adds up its slice of the entries over the cluster's partials (the
         // barrier also sums a carried workgroup-uniform value)
         if (carry) csum = cluster_sum(cval);
         else cluster_sync();
-        const int tot = M1 * M1 + M1 * N2;
+        // the work items: the 16 x 16 tiles of G1 on and above the diagonal (row tile <= column
+        // tile, in the order of the Gram routine, 256 items each: 16 consecutive rows of a
+        // column, then the next column), then the entries of G2; each G1 item is also stored
+        // at its mirror
+        const int TM = (M1 + 15) >> 4;
+        const int nup = TM * (TM + 1) / 2 * 256;
+        const int tot = nup + M1 * N2;
         const int per = (tot + W - 1) / W;
         const int e0 = ufirst(s.part) * per, e1 = min(tot, e0 + per);
         double* Gk = pb.G + pb.offG[k];
         double* Xk = pb.X + pb.offX[k];
-        auto put = [&](int e, double v) {
-            if (e < M1 * M1) stg(Gk + e, v);
-            else stg(Xk + (e - M1 * M1), v);
+        // offset of item e in a partial (and in G1 / after it for G2), -1 for tile padding
+        auto at = [&](int e, int& i, int& j) {
+            if (e >= nup) return M1 * M1 + (e - nup);
+            int a = 0, rem = e >> 8;
+            while (rem >= TM - a) {
+                rem -= TM - a;
+                ++a;
+            }
+            i = a * 16 + (e & 15);
+            j = (a + rem) * 16 + ((e >> 4) & 15);
+            return (i < M1 && j < M1) ? i + j * M1 : -1;
         };
-        // three entries per thread and pass, all their partials' loads in flight together
+        // three items per thread and pass, all their partials' loads in flight together
         for (int e = e0 + tid_here(); e < e1; e += 3 * WG) {
             const double* b[3];
+            int off[3], ii[3], jj[3];
 #pragma unroll
-            for (int u = 0; u < 3; ++u) b[u] = e + u * WG < e1 ? pb.gpart + e + u * WG : nullptr;
+            for (int u = 0; u < 3; ++u) {
+                ii[u] = jj[u] = 0;
+                off[u] = e + u * WG < e1 ? at(e + u * WG, ii[u], jj[u]) : -1;
+                b[u] = off[u] >= 0 ? pb.gpart + off[u] : nullptr;
+            }
             double a[3];
             sum_partials_n<3>(b, pb.psz, W, a);
 #pragma unroll
-            for (int u = 0; u < 3; ++u)
-                if (b[u]) put(e + u * WG, a[u]);
+            for (int u = 0; u < 3; ++u) {
+                if (!b[u]) continue;
+                if (off[u] >= M1 * M1) {
+                    stg(Xk + (off[u] - M1 * M1), a[u]);
+                } else {
+                    stg(Gk + off[u], a[u]);
+                    if ((ii[u] >> 4) != (jj[u] >> 4)) stg(Gk + jj[u] + (int64_t)ii[u] * M1, a[u]);
+                }
+            }
         }
         cluster_sync();
     }

@@ -160,11 +160,12 @@ struct PanelA {
 // where element (i, c) of A (c < M1) and of B (c < N2) come from panel functors with
 //   raw(i, c) -> raw_t (loads only) and val(raw_t) -> double,
 // so that a batch of loads is issued before any value is formed.
-// Only the upper-triangular tiles of G1 are computed; both halves are written.  Tiles are
-// dealt round-robin to the waves, up to GRAM_TPW per wave per pass over the rows.  Chunks
-// of 32 rows (16 when LDS is short or there are at most 16 rows) are staged; `lds` holds
-// `cap` doubles, at least
-// 16 * ((TM1*16 + 1) + (TN2*16 + 1)).  Starts and ends with a barrier.
+// Only the upper-triangular tiles of G1 (row tile <= column tile) are computed; both halves
+// are written unless `mirror` is off (then the tiles below the diagonal are left as they
+// are).  Tiles are dealt round-robin to the waves, up to GRAM_TPW per wave per pass over the
+// rows.  Chunks of 32 rows (16 when LDS is short or there are at most 16 rows) are staged;
+// `lds` holds `cap` doubles, at least 16 * ((TM1*16 + 1) + (TN2*16 + 1)).  Starts and ends
+// with a barrier.
 // ---------------------------------------------------------------------------------------
 constexpr int GRAM_TPW = 9;
 
@@ -215,7 +216,7 @@ __device__ __forceinline__ void gram_stage(const F& f, int n, int i0, int ncol, 
 template <bool F32, class FA, class FB>
 __device__ __forceinline__ void gram_lds(int i_begin, int i_end, int M1, int N2, const FA& fa, const FB& fb,
                                          double* __restrict__ G1, int ld1, double* __restrict__ G2, int ld2, double* lds,
-                                         int cap) {
+                                         int cap, bool mirror = true) {
     const int n = i_end;   // rows i_begin .. i_end - 1
     constexpr int PFN = 16;   // prefetched elements per thread and operand
     const int lane = tid_here() & 63, wave = tid_here() >> 6;
@@ -321,7 +322,7 @@ __device__ __forceinline__ void gram_lds(int i_begin, int i_end, int M1, int N2,
                     if (row < M1 && col < M1) {
                         stg(G1 + row + (int64_t)col * ld1, val);
                         // mirror into the lower triangle (diagonal tiles hold both halves)
-                        if (ti[t] != tj[t]) stg(G1 + col + (int64_t)row * ld1, val);
+                        if (mirror && ti[t] != tj[t]) stg(G1 + col + (int64_t)row * ld1, val);
                     }
                 } else if (row < M1 && col < N2) {
                     stg(G2 + row + (int64_t)col * ld2, val);
