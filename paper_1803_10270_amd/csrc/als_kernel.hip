@@ -248,6 +248,16 @@ struct ColF {
     __device__ __forceinline__ double val(raw_t v) const { return v; }
 };
 
+// Rows rlo .. of a panel held in LDS, column c at X[c ld].
+struct LdsColF {
+    typedef double raw_t;
+    const double* X;
+    int rlo, ld;
+    __device__ __forceinline__ static raw_t zero() { return 0.0; }
+    __device__ __forceinline__ raw_t raw(int i, int c) const { return X[(i - rlo) + c * ld]; }
+    __device__ __forceinline__ double val(raw_t v) const { return v; }
+};
+
 // x - u elementwise (the increment of one factor).
 struct DiffF {
     typedef double2 raw_t;
@@ -266,8 +276,9 @@ struct DiffF {
 // a r + l) into `out`.
 // For each batch of elements every tap and coefficient load is issued before the sums are
 // formed.  Ends with a barrier.
+// With ldo > 0, out is an LDS panel of the own rows: row i, column c at out[(i - rlo) + c ldo].
 __device__ __forceinline__ void apply_panel(const OpDev* ops, int m, int n, int r, const double* X, double* out,
-                                            int rlo, int rhi) {
+                                            int rlo, int rhi, int ldo = 0) {
     Smem& s = SMEM;
     for (int a = 0; a < m; ++a)
         if (ops[a].kind == CP_OP_RANK1) wg_coldots(n, r, ops[a].data + n, X, n, s.dots + a * r);
@@ -321,7 +332,8 @@ __device__ __forceinline__ void apply_panel(const OpDev* ops, int m, int n, int 
 #pragma unroll
                 for (int j = 0; j < CG_TAPS; ++j) v = fma(cv[u][j], xv[u][j], v);
                 const int c = fdiv(t, invn), i = rlo + (t - c * nown);
-                stg(out + i + (int64_t)c * n, v);
+                if (ldo) out[(i - rlo) + c * ldo] = v;
+                else stg(out + i + (int64_t)c * n, v);
             }
         }
     }
@@ -343,9 +355,6 @@ __device__ __forceinline__ double refresh_dim(int k, int r0, bool lowp, const do
     const double* Uk = src ? src : pb.U + pb.offU[k];
     int rlo, rhi;
     own_rows(n, rlo, rhi);
-    apply_panel(pb.opA[k], m, n, r, Uk, pb.P, rlo, rhi);
-    ColF fa{pb.P, n};
-    ColF fb{pb.Q + pb.offQ[k], n};
     const int M1 = m * r, N2 = mb * r0;
     const int W = ufirst(s.W);
     double* G1 = pb.G + pb.offG[k];
@@ -354,10 +363,25 @@ __device__ __forceinline__ double refresh_dim(int k, int r0, bool lowp, const do
         G1 = pb.gpart + (int64_t)ufirst(s.part) * pb.psz;
         G2 = G1 + M1 * M1;
     }
+    ColF fb{pb.Q + pb.offQ[k], n};
     // a cluster's partials hold the tiles of G1 on and above the diagonal only; the
     // reduction below mirrors them
-    if (lowp) gram_lds<true>(rlo, rhi, M1, N2, fa, fb, G1, M1, G2, M1, s.scratch, SCRATCH, W == 1);
-    else gram_lds<false>(rlo, rhi, M1, N2, fa, fb, G1, M1, G2, M1, s.scratch, SCRATCH, W == 1);
+    const int nown = rhi - rlo;
+    const int cap = SCRATCH - nown * M1;
+    const int stage2 = 32 * ((((M1 + 15) >> 4) * 16 + 1) + (((N2 + 15) >> 4) * 16 + 1));   // two 16-row chunks
+    if (!lowp && W > 1 && nown * M1 <= SCRATCH / 4 && stage2 <= cap) {
+        // FP64 sweeps of a cluster: the applied panel of the own rows stays in LDS, above the
+        // Gram routine's staging
+        double* Pl = s.scratch + cap;
+        apply_panel(pb.opA[k], m, n, r, Uk, Pl, rlo, rhi, nown);
+        LdsColF fa{Pl, rlo, nown};
+        gram_lds<false>(rlo, rhi, M1, N2, fa, fb, G1, M1, G2, M1, s.scratch, cap, false);
+    } else {
+        apply_panel(pb.opA[k], m, n, r, Uk, pb.P, rlo, rhi);
+        ColF fa{pb.P, n};
+        if (lowp) gram_lds<true>(rlo, rhi, M1, N2, fa, fb, G1, M1, G2, M1, s.scratch, SCRATCH, W == 1);
+        else gram_lds<false>(rlo, rhi, M1, N2, fa, fb, G1, M1, G2, M1, s.scratch, SCRATCH, W == 1);
+    }
     double csum = cval;
     if (W > 1) {
         // every workgroup adds up its slice of the entries over the cluster's partials (the
