@@ -2017,6 +2017,7 @@ __global__ void __launch_bounds__(WG) als_persistent(const Problem* __restrict__
             s.W = Wp;
             s.bar_target = 0;
             s.sync_ok = 1;
+            s.xlocal = 0;
             s.dcount = 0;
             s.kc_key = nullptr;
             // this workgroup's copy of the assembled blocks
@@ -2446,6 +2447,7 @@ __global__ void __launch_bounds__(WG) residual_kernel(const Problem* __restrict_
             s.W = 1;
             s.bar_target = 0;
             s.sync_ok = 1;
+            s.xlocal = 0;
             s.dcount = 0;
             s.kc_key = nullptr;
         }
