@@ -30,6 +30,7 @@ namespace cpals {
 
 constexpr int XCDS = 8;          // XCDs of the device (MI355X), each with its own L2
 constexpr int XCD_CUS = 32;      // compute units of one XCD
+constexpr int TILE_PAR_N = 512;  // a cluster's Gram refresh forms whole tiles over grids up to this size
 constexpr int SCRATCH = 16384;   // doubles of LDS shared by the phases of one dimension update
 constexpr int LDS_PAIRS = 384;   // pair records of one dimension kept in LDS during assembly
 constexpr int CG_TAPS = 5;       // stencils up to half bandwidth 2 keep their coefficients in registers
@@ -340,6 +341,86 @@ __device__ __forceinline__ void apply_panel(const OpDev* ops, int m, int n, int 
     __syncthreads();
 }
 
+// Tiles t0 .. t1 - 1 of the Grams (the 16 x 16 tiles of G1 = P^T P on and above the
+// diagonal in row-major triangular order, then those of G2 = P^T Q), each formed over all n
+// rows of the published panels and stored (G1 also at its mirror).  The four waves split the
+// rows (k-steps of four rows) and load their matrix-core operands straight from the panels,
+// all loads of a batch in flight together; the partial tiles are added in LDS in wave order.
+// Operands and result layout as in gram_lds.  Starts and ends with a barrier.
+template <bool F32>
+__device__ __forceinline__ void gram_tiles_direct(int n, int M1, int N2, const double* P, const double* Q, double* G1,
+                                                  double* G2, int t0, int t1) {
+    Smem& s = SMEM;
+    constexpr int KB = 16;   // k-steps per batch of loads
+    const int lane = tid_here() & 63, wave = tid_here() >> 6;
+    const int kk = lane >> 4, cc = lane & 15;
+    const int TM = (M1 + 15) >> 4;
+    const int nt1 = TM * (TM + 1) / 2;
+    const int S = (n + 3) >> 2;
+    const int s0 = (wave * S) / NWAVES, s1 = ((wave + 1) * S) / NWAVES;
+    double* red = s.scratch;   // [NWAVES - 1][4][64]
+    __syncthreads();
+    for (int t = t0; t < t1; ++t) {
+        int ti, tj;
+        const bool g1 = t < nt1;
+        if (g1) {
+            int a = 0, rem = t;
+            while (rem >= TM - a) {
+                rem -= TM - a;
+                ++a;
+            }
+            ti = a;
+            tj = a + rem;
+        } else {
+            ti = (t - nt1) % TM;
+            tj = (t - nt1) / TM;
+        }
+        const int ca = ti * 16 + cc, cb = tj * 16 + cc;
+        const bool oka = ca < M1, okb = cb < (g1 ? M1 : N2);
+        const double* pa = P + (int64_t)(oka ? ca : 0) * n;
+        const double* pbb = (g1 ? P : Q) + (int64_t)(okb ? cb : 0) * n;
+        Tile<F32> acc;
+        acc.zero();
+        for (int sb = s0; sb < s1; sb += KB) {
+            double av[KB], bv[KB];
+#pragma unroll
+            for (int u = 0; u < KB; ++u) {
+                const int k = 4 * (sb + u) + kk;
+                const bool ok = sb + u < s1 && k < n;
+                av[u] = (ok && oka) ? ldg(pa + k) : 0.0;
+                bv[u] = (ok && okb) ? ldg(pbb + k) : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < KB; ++u) acc.step(bv[u], av[u]);
+        }
+        if (wave > 0) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) red[((wave - 1) * 4 + v) * 64 + lane] = acc.get(v);
+        }
+        __syncthreads();
+        if (wave == 0) {
+            for (int w = 1; w < NWAVES; ++w)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc.add(v, red[((w - 1) * 4 + v) * 64 + lane]);
+            const int row = ti * 16 + cc;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int col = tj * 16 + Tile<F32>::row(lane, v);
+                const double val = acc.get(v);
+                if (g1) {
+                    if (row < M1 && col < M1) {
+                        stg(G1 + row + (int64_t)col * M1, val);
+                        if (ti != tj) stg(G1 + col + (int64_t)row * M1, val);
+                    }
+                } else if (row < M1 && col < N2) {
+                    stg(G2 + row + (int64_t)col * M1, val);
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // ------------------------------------------------------------------------------------
 // Gram refresh of one dimension: G_k = P_k^T P_k, X_k = P_k^T Q_k with P_k = [O^a U_k]_a
 // (P_k formed once in the scratch panel, then both products over row chunks staged in LDS).
@@ -359,6 +440,21 @@ __device__ __forceinline__ double refresh_dim(int k, int r0, bool lowp, const do
     const int W = ufirst(s.W);
     double* G1 = pb.G + pb.offG[k];
     double* G2 = pb.X + pb.offX[k];
+    if (W > 1 && n <= TILE_PAR_N) {
+        // a cluster on a short grid: the applied panel of the own rows is published, then
+        // every workgroup forms whole tiles of G_q, X_q over all rows and stores them (the
+        // barrier also sums a carried workgroup-uniform value); no partials, no reduction
+        apply_panel(pb.opA[k], m, n, r, Uk, pb.P, rlo, rhi);
+        const double csum = carry ? cluster_sum(cval) : (cluster_sync(), cval);
+        const int TM = (M1 + 15) >> 4, TN = (N2 + 15) >> 4;
+        const int ntiles = TM * (TM + 1) / 2 + TM * TN;
+        const int part = ufirst(s.part);
+        const int t0 = (part * ntiles) / W, t1 = ((part + 1) * ntiles) / W;
+        if (lowp) gram_tiles_direct<true>(n, M1, N2, pb.P, pb.Q + pb.offQ[k], G1, G2, t0, t1);
+        else gram_tiles_direct<false>(n, M1, N2, pb.P, pb.Q + pb.offQ[k], G1, G2, t0, t1);
+        cluster_sync();
+        return csum;
+    }
     if (W > 1) {
         G1 = pb.gpart + (int64_t)ufirst(s.part) * pb.psz;
         G2 = G1 + M1 * M1;
